@@ -1,0 +1,224 @@
+/*
+ * rt.h -- C ABI of the MI355X (gfx950) direct-volume-rendering raycaster.
+ *
+ * The library renders a scalar volume on a Cartesian grid (arXiv:1211.5595,
+ * Section 2.1) by image-order ray casting (Section 4.1): one viewing ray per
+ * pixel, intersected with the volume, sampled at evenly spaced points,
+ * classified by a colour+opacity transfer function (Sections 2.6 and 6) and
+ * combined by a ray function -- compositing as in Section 4.2, eqs. (1)-(5),
+ * or one of the other ray functions listed in Section 4.1.
+ *
+ * Conventions shared by every entry point
+ *   - Volume: node-centred grid, node (i,j,k) at (i*sx, j*sy, k*sz) mm;
+ *     source arrays are C-order [z][y][x] (x fastest); dims = {nx, ny, nz},
+ *     each >= 2.  The volume is the closed box [0,(n-1)s] per axis.
+ *   - Sampling: dt = step_vox * min(spacing) mm along a unit ray; samples at
+ *     the midpoints of the dt-segments of the clipped chord, plus one at the
+ *     midpoint of the remaining partial segment (length r) whose opacity is
+ *     1-(1-a)^(r/dt).  Trilinear interpolation with clamp-to-edge.
+ *   - Classification: post-classification; x = clamp((v-vmin)/(vmax-vmin),
+ *     0, 1)*(K-1), linear interpolation between table entries floor(x) and
+ *     floor(x)+1.  Table colours are non-premultiplied.
+ *   - Compositing: front-to-back, C += T*a*c, T *= 1-a; stop after the first
+ *     sample with 1-T >= alpha_cutoff (early ray termination).  Output pixel
+ *     = (C + T*bg.rgb, (1-T) + T*bg.a), premultiplied, float32 RGBA.
+ *   - Image: H x W x 4 float32, row-major, row 0 at the top; pixel (i,j) is
+ *     sampled at its centre; aspect ratio W/H.
+ *   - Arithmetic: float32 (float-float pairs for ray set-up and fixed-point
+ *     sample positions); no float64 on the device.
+ *
+ * Memory ownership
+ *   The caller allocates and owns every device buffer (volume storage,
+ *   transfer-function storage, images, workspaces) and keeps it alive until
+ *   the handle using it is destroyed and all work queued on it has finished.
+ *   Handles (rt_volume, rt_tf, rt_batch_plan) are small host objects owned by
+ *   the library; destroy them with the matching rt_destroy_* call.
+ *
+ * Streams
+ *   Every call that touches the device is ordered on the caller's stream
+ *   (a hipStream_t passed as void*; NULL = the null stream).  No call
+ *   synchronises the device unless its comment says so.
+ *
+ * Errors
+ *   Every function returns an rt_status and never aborts.  rt_last_error()
+ *   returns a thread-local message for the last failing call on the calling
+ *   thread.  Launch failures are reported synchronously as RT_ERR_DEVICE; an
+ *   asynchronous device fault surfaces at the caller's next synchronisation.
+ */
+#ifndef RTVOL_RT_H
+#define RTVOL_RT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RT_OK = 0,
+    RT_ERR_INVALID_ARG = 1,   /* null pointer, bad size, bad camera, ... */
+    RT_ERR_OUT_OF_MEMORY = 2, /* a caller-provided buffer is too small */
+    RT_ERR_DEVICE = 3,        /* a HIP runtime call failed */
+    RT_ERR_UNSUPPORTED = 4    /* valid request outside what this build supports */
+} rt_status;
+
+/* Storage (and source) element types of a volume. */
+typedef enum {
+    RT_U8 = 0,              /* unsigned 8-bit integers, converted exactly */
+    RT_U16 = 1,             /* unsigned 16-bit integers, converted exactly */
+    RT_F16 = 2,             /* IEEE half; conversion from other types rounds to nearest even */
+    RT_F32 = 3,             /* IEEE single */
+    RT_U8_BRICKSCALED = 4   /* storage only: 8-bit codes with a (lo, scale) per brick of B^3 cells */
+} rt_dtype;
+
+/* Ray functions (Section 4.1 list; Section 2.4 for maximum intensity and
+ * X-ray projection). */
+typedef enum {
+    RT_COMPOSITE = 0,  /* emission-absorption compositing, Section 4.2 */
+    RT_MIP = 1,        /* maximum interpolated value along the ray */
+    RT_XRAY = 2,       /* sum of interpolated values times segment length */
+    RT_AVERAGE = 3,    /* mean interpolated value */
+    RT_ISO = 4,        /* first crossing of an iso-value, shaded */
+    RT_THRESHOLD = 5   /* compositing of the samples inside a value window */
+} rt_ray_function;
+
+/* Look-at camera (Section 6: camera settings).  w = normalize(center-eye),
+ * u = normalize(w x up), v = u x w.  Invalid when eye == center or up is
+ * parallel to w.  perspective != 0: pinhole at eye with full vertical field
+ * of view fovy_deg in (0, 180).  perspective == 0: parallel rays along w
+ * through a window of half-height ortho_half_height (> 0) mm centred on eye. */
+typedef struct {
+    double eye[3], center[3], up[3];
+    int perspective;
+    double fovy_deg;
+    double ortho_half_height;
+} rt_camera;
+
+typedef struct rt_volume rt_volume;
+typedef struct rt_tf rt_tf;
+typedef struct rt_batch_plan rt_batch_plan;
+
+/* Optional per-render settings; a NULL pointer or zeroed struct selects the
+ * defaults. */
+typedef struct {
+    unsigned long long* sample_counter; /* device, nullable: atomically += samples processed */
+    int32_t* pixel_counts;              /* device, nullable: H*W samples processed per pixel */
+    int ray_function;                   /* rt_ray_function; 0 = compositing */
+    float iso_value;                    /* RT_ISO iso-value; RT_THRESHOLD window low */
+    float iso_high;                     /* RT_THRESHOLD window high */
+    int tile_w, tile_h;                 /* ray tile of one wavefront, tile_w*tile_h == 64; 0 = 8x8 */
+    int waves_per_block;                /* wavefronts per workgroup, 1..16; 0 = default */
+} rt_render_opts;
+
+/* ---------------------------------------------------------------------------
+ * Volume data (Section 2.1: samples f(x,y,z,d) on a Cartesian grid; slices
+ * with thickness and gaps, Section 1, give an anisotropic spacing).
+ * ------------------------------------------------------------------------- */
+
+/* Device bytes needed to hold a volume of `dims` in `storage` layout.  brick
+ * is the brick edge B in cells (8, 16 or 32) for RT_U8_BRICKSCALED and must
+ * be 0 for the other types.  Errors: RT_ERR_INVALID_ARG (bad dims/brick,
+ * NULL), RT_ERR_UNSUPPORTED (volume too large for 32-bit addressing). */
+rt_status rt_volume_bytes(const int64_t dims[3], int storage, int brick, size_t* bytes);
+
+/* Convert a device-resident source array (C-order [z][y][x] of src_dtype,
+ * one of RT_U8/RT_U16/RT_F16/RT_F32) into the raycaster's storage layout in
+ * the caller's device buffer dev_buf (>= rt_volume_bytes bytes), on `stream`.
+ * The layout adds a one-node replicated border on every face (bricked with
+ * per-brick scale and halo for RT_U8_BRICKSCALED: lo = brick minimum, scale =
+ * (max-lo)/255, code = rint((v-lo)/scale), all binary32).  The source may be
+ * freed once the stream has passed this call.  *out receives the handle.
+ * Errors: RT_ERR_INVALID_ARG (NULL, dims < 2, non-finite or non-positive
+ * spacing, storage/src combination such as F32 -> U8), RT_ERR_OUT_OF_MEMORY
+ * (dev_buf_bytes too small), RT_ERR_DEVICE (launch failure). */
+rt_status rt_create_volume(const void* src_dev, int src_dtype, const int64_t dims[3], const double spacing[3],
+                           int storage, int brick, void* dev_buf, size_t dev_buf_bytes, void* stream,
+                           rt_volume** out);
+rt_status rt_destroy_volume(rt_volume* vol);
+
+/* ---------------------------------------------------------------------------
+ * Transfer function (Sections 2.6 and 6: colour and scalar-opacity transfer
+ * functions), held as one K x 4 RGBA table over the value window
+ * [vmin, vmax].
+ * ------------------------------------------------------------------------- */
+
+/* Device bytes for a K-entry table (K in [2, 4096]). */
+rt_status rt_tf_bytes(int K, size_t* bytes);
+
+/* Create (*tf == NULL) or update in place (*tf != NULL) a transfer function:
+ * copies the host table rgba[K][4] (each value in [0,1]) into dev_buf
+ * (>= rt_tf_bytes(K)) on `stream`.  An update must keep dev_buf and K.
+ * Errors: RT_ERR_INVALID_ARG (NULL, K outside [2,4096], vmax <= vmin,
+ * non-finite or out-of-range entries), RT_ERR_OUT_OF_MEMORY (buffer too
+ * small), RT_ERR_DEVICE. */
+rt_status rt_set_transfer_function(rt_tf** tf, const float* rgba, int K, double vmin, double vmax, void* dev_buf,
+                                   size_t dev_buf_bytes, void* stream);
+rt_status rt_destroy_tf(rt_tf* tf);
+
+/* ---------------------------------------------------------------------------
+ * Rendering (Section 4.1: ray path, values along the ray, ray function).
+ * ------------------------------------------------------------------------- */
+
+/* Render one image of `volume` into out_dev (H*W*4 float32, device).  dims
+ * must equal the volume's dims; spacing (> 0) may differ from the one given
+ * at creation (geometry only).  step_vox > 0 in units of the finest spacing;
+ * alpha_cutoff in (0, 1] (1 = stop only at full opacity).  bg_rgba may be
+ * NULL (transparent black).  One kernel launch on `stream`.
+ * Errors: RT_ERR_INVALID_ARG (NULL, size/camera/step/cutoff out of range,
+ * dims mismatch), RT_ERR_UNSUPPORTED (ray function or tile shape not built),
+ * RT_ERR_DEVICE (launch failure). */
+rt_status rt_render(const rt_volume* volume, const int64_t dims[3], const double spacing[3], const rt_tf* tf,
+                    const rt_camera* camera, int width, int height, double step_vox, double alpha_cutoff,
+                    const float bg_rgba[4], float* out_dev, const rt_render_opts* opts, void* stream);
+
+/* One view of a batch. */
+typedef struct {
+    const rt_volume* volume;
+    const rt_tf* tf;
+    rt_camera camera;
+    int width, height;
+    double step_vox, alpha_cutoff;
+    float bg_rgba[4];
+    float* out_dev;           /* H*W*4 float32, device */
+    int32_t* pixel_counts;    /* device, nullable */
+} rt_render_job;
+
+/* Workspace bytes for batches of up to max_jobs views (max_jobs >= 1). */
+rt_status rt_batch_workspace_bytes(int max_jobs, size_t* bytes);
+
+/* Render n views (of possibly different volumes, transfer functions and
+ * sizes; all volumes of one storage type) in one persistent launch that pulls
+ * ray tiles from a device work queue.  Copies the job table into `workspace`
+ * (>= rt_batch_workspace_bytes(n)) on `stream`; the job array may be reused
+ * once the call returns.  Results are bitwise identical to rt_render of each
+ * view.  Errors: as rt_render, plus RT_ERR_OUT_OF_MEMORY (workspace too
+ * small) and RT_ERR_UNSUPPORTED (mixed storage types). */
+rt_status rt_render_batch(const rt_render_job* jobs, int n, void* workspace, size_t ws_bytes,
+                          unsigned long long* sample_counter, const rt_render_opts* opts, void* stream);
+
+/* A batch plan: the persistent launch captured once into a HIP graph over a
+ * fixed workspace, replayed for every batch of up to max_jobs views of one
+ * storage type.  rt_batch_plan_launch copies the job table into the
+ * workspace (plain stream copy, outside the graph) and launches the graph on
+ * `stream`.  The plan keeps a pinned host staging buffer and waits for the
+ * previous launch's copy before reusing it.  Calls on one plan must not run
+ * concurrently. */
+rt_status rt_batch_plan_create(int max_jobs, int storage, void* workspace, size_t ws_bytes,
+                               const rt_render_opts* opts, rt_batch_plan** out);
+rt_status rt_batch_plan_launch(rt_batch_plan* plan, const rt_render_job* jobs, int n,
+                               unsigned long long* sample_counter, void* stream);
+rt_status rt_batch_plan_destroy(rt_batch_plan* plan);
+
+/* ---------------------------------------------------------------------------
+ * Diagnostics
+ * ------------------------------------------------------------------------- */
+const char* rt_status_string(rt_status status);
+const char* rt_last_error(void);
+/* Library version string (static). */
+const char* rt_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

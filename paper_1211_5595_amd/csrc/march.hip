@@ -1,0 +1,447 @@
+// march.hip -- the ray marcher for gfx950.
+//
+// One ray per lane, one ray tile (64 pixels) per wavefront, tiles grouped
+// into workgroup blocks.  Per ray (arXiv:1211.5595, Section 4.1, three steps):
+//   1. ray path: pixel ray from the camera (Section 6 camera settings),
+//      clipped to the volume box, cut into evenly spaced samples;
+//   2. values along the ray: trilinear resampling of the stored grid
+//      (Section 3.2) and classification by the RGBA transfer function
+//      (Sections 2.6 and 6) held in LDS;
+//   3. ray function: front-to-back compositing of the emission-absorption
+//      sum (Section 4.2, eqs. (4)-(5)) with early ray termination.
+//
+// Precision: the ray set-up (direction, box entry/exit, sample lattice) runs
+// in float-float; sample positions then advance as exact 32.32 fixed-point
+// integers in padded index space, so the cell index is the high word and the
+// trilinear fraction the low word.  Interpolation, classification and
+// compositing run in binary32.  No binary64 on the device.
+//
+// Memory: the volume is read through buffer resources (out-of-range reads
+// return zero, never fault); the 8 corners of a cell are one vector offset
+// plus 8 wave-uniform scalar offsets.
+#include "ff_math.h"
+#include "rt_internal.h"
+
+namespace rtv {
+
+namespace {
+
+constexpr int kRsrcWord3 = 0x00020000;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, kRsrcWord3);
+}
+
+// Per-lane state after the ray set-up.
+struct Ray {
+    long long Q[3];   // padded index-space position of the next full sample, 32.32 fixed point
+    long long dQ[3];  // increment per sample
+    long long Qp[3];  // position of the remainder sample
+    int m;            // number of full samples
+    float wp;         // remainder weight r/dt, 0 when there is no remainder
+};
+
+// Step 1 of the ray-casting process: the ray path.  Returns false for a ray
+// that misses the box [0, box_hi].
+__device__ __forceinline__ bool setup_ray(const ViewDesc& V, int i, int j, Ray& R) {
+    const float a = (float)(2 * i + 1 - V.W);
+    const float b = (float)(V.H - 2 * j - 1);
+    ff o[3], d[3];
+    if (V.perspective) {
+        ff r[3];
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) r[ax] = ff_add(ff_add(V.w[ax], ff_mul_f(V.U[ax], a)), ff_mul_f(V.V[ax], b));
+        ff n2 = ff_add(ff_add(ff_mul(r[0], r[0]), ff_mul(r[1], r[1])), ff_mul(r[2], r[2]));
+        ff inv = ff_div(ff_make(1.0f), ff_sqrt(n2));
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+            o[ax] = V.eye[ax];
+            d[ax] = ff_mul(r[ax], inv);
+        }
+    } else {
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+            o[ax] = ff_add(ff_add(V.eye[ax], ff_mul_f(V.U[ax], a)), ff_mul_f(V.V[ax], b));
+            d[ax] = V.w[ax];
+        }
+    }
+    // Slab test against the closed box.
+    ff tin = ff_make(-INFINITY), tout = ff_make(INFINITY);
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+        if (d[ax].hi == 0.0f) {
+            if (ff_lt(o[ax], ff_make(0.0f)) || ff_lt(V.box_hi[ax], o[ax])) return false;
+            continue;
+        }
+        ff rd = ff_div(ff_make(1.0f), d[ax]);
+        ff t0 = ff_mul(ff_neg(o[ax]), rd);
+        ff t1 = ff_mul(ff_sub(V.box_hi[ax], o[ax]), rd);
+        if (ff_lt(t1, t0)) {
+            ff x = t0;
+            t0 = t1;
+            t1 = x;
+        }
+        tin = ff_max(tin, t0);
+        tout = ff_min(tout, t1);
+    }
+    const ff tnear = ff_max(tin, ff_make(0.0f));
+    if (!ff_lt(tnear, tout)) return false;
+    // Evenly spaced samples: m segments of dt and a remainder r in [0, dt).
+    const ff L = ff_sub(tout, tnear);
+    int m = ff_floor_int(ff_div(L, V.dt));
+    ff r = ff_sub(L, ff_mul_f(V.dt, (float)m));
+    if (r.hi < 0.0f) {
+        m -= 1;
+        r = ff_add(r, V.dt);
+    }
+    if (!ff_lt(r, V.dt)) {
+        m += 1;
+        r = ff_sub(r, V.dt);
+    }
+    if (m < 0) {
+        m = 0;
+        r = ff_make(0.0f);
+    }
+    R.m = m;
+    // First sample at tnear + dt/2; positions in padded index space q + 1.
+    const ff s0 = ff_add(tnear, ff_mul_f(V.dt, 0.5f));
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+        ff p = ff_add(o[ax], ff_mul(s0, d[ax]));
+        R.Q[ax] = ff_to_fixed32(ff_add(ff_mul(p, V.inv_sp[ax]), ff_make(1.0f)));
+        R.dQ[ax] = ff_to_fixed32(ff_mul(ff_mul(V.dt, d[ax]), V.inv_sp[ax]));
+    }
+    R.wp = 0.0f;
+    if (r.hi > 0.0f) {
+        const ff sp = ff_add(ff_add(tnear, ff_mul_f(V.dt, (float)m)), ff_mul_f(r, 0.5f));
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+            ff p = ff_add(o[ax], ff_mul(sp, d[ax]));
+            R.Qp[ax] = ff_to_fixed32(ff_add(ff_mul(p, V.inv_sp[ax]), ff_make(1.0f)));
+        }
+        R.wp = r.hi / V.dt.hi;
+    }
+    return true;
+}
+
+__device__ __forceinline__ float lerp(float a, float b, float t) { return fmaf(t, b - a, a); }
+
+template <int KIND>
+struct Elem;
+template <>
+struct Elem<ST_U8> {
+    static constexpr uint32_t bytes = 1;
+    static __device__ __forceinline__ float load(__amdgpu_buffer_rsrc_t r, uint32_t off, int soff) {
+        return (float)__builtin_amdgcn_raw_buffer_load_b8(r, off, soff, 0);
+    }
+};
+template <>
+struct Elem<ST_U8B> : Elem<ST_U8> {};
+template <>
+struct Elem<ST_U16> {
+    static constexpr uint32_t bytes = 2;
+    static __device__ __forceinline__ float load(__amdgpu_buffer_rsrc_t r, uint32_t off, int soff) {
+        return (float)__builtin_amdgcn_raw_buffer_load_b16(r, off, soff, 0);
+    }
+};
+template <>
+struct Elem<ST_F16> {
+    static constexpr uint32_t bytes = 2;
+    static __device__ __forceinline__ float load(__amdgpu_buffer_rsrc_t r, uint32_t off, int soff) {
+        unsigned short h = __builtin_amdgcn_raw_buffer_load_b16(r, off, soff, 0);
+        return (float)__builtin_bit_cast(_Float16, h);
+    }
+};
+template <>
+struct Elem<ST_F32> {
+    static constexpr uint32_t bytes = 4;
+    static __device__ __forceinline__ float load(__amdgpu_buffer_rsrc_t r, uint32_t off, int soff) {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, soff, 0));
+    }
+};
+
+// Wave-uniform corner offsets of a cell, in bytes.
+struct Corners {
+    int c1, c2, c3, c4, c5, c6, c7;
+};
+
+__device__ __forceinline__ Corners corners_of(uint32_t e, uint32_t sy, uint32_t sz) {
+    return Corners{(int)e, (int)sy, (int)(sy + e), (int)sz, (int)(sz + e), (int)(sz + sy), (int)(sz + sy + e)};
+}
+
+// Trilinear blend of the 8 corners at base offset `off` (Section 3.2).
+template <int KIND>
+__device__ __forceinline__ float trilinear(__amdgpu_buffer_rsrc_t r, uint32_t off, const Corners& c, float fx,
+                                           float fy, float fz) {
+    using E = Elem<KIND>;
+    const float v000 = E::load(r, off, 0), v100 = E::load(r, off, c.c1);
+    const float v010 = E::load(r, off, c.c2), v110 = E::load(r, off, c.c3);
+    const float v001 = E::load(r, off, c.c4), v101 = E::load(r, off, c.c5);
+    const float v011 = E::load(r, off, c.c6), v111 = E::load(r, off, c.c7);
+    const float x00 = lerp(v000, v100, fx), x10 = lerp(v010, v110, fx);
+    const float x01 = lerp(v001, v101, fx), x11 = lerp(v011, v111, fx);
+    return lerp(lerp(x00, x10, fy), lerp(x01, x11, fy), fz);
+}
+
+__device__ __forceinline__ float frac32(long long Q) { return (float)(uint32_t)Q * 0x1p-32f; }
+
+// Step 2 of the ray-casting process: the value at a sample.
+template <int KIND>
+__device__ __forceinline__ float sample_value(const VolDev& vol, __amdgpu_buffer_rsrc_t rs, const Corners& cn,
+                                              const long long Q[3]) {
+    const uint32_t ix = (uint32_t)(Q[0] >> 32), iy = (uint32_t)(Q[1] >> 32), iz = (uint32_t)(Q[2] >> 32);
+    const float fx = frac32(Q[0]), fy = frac32(Q[1]), fz = frac32(Q[2]);
+    if constexpr (KIND != ST_U8B) {
+        const uint32_t off = __umul24(iz, vol.sz) + __umul24(iy, vol.sy) + ix * Elem<KIND>::bytes;
+        return trilinear<KIND>(rs, off, cn, fx, fy, fz);
+    } else {
+        // The brick that owns the (clamped) cell; local padded node = padded node - b*B.
+        const int cx = min(max((int)ix - 1, 0), vol.n[0] - 2) >> vol.bshift;
+        const int cy = min(max((int)iy - 1, 0), vol.n[1] - 2) >> vol.bshift;
+        const int cz = min(max((int)iz - 1, 0), vol.n[2] - 2) >> vol.bshift;
+        const uint32_t lx = ix - ((uint32_t)cx << vol.bshift);
+        const uint32_t ly = iy - ((uint32_t)cy << vol.bshift);
+        const uint32_t lz = iz - ((uint32_t)cz << vol.bshift);
+        const uint32_t bid = __umul24(__umul24((uint32_t)cz, (uint32_t)vol.nb[1]) + (uint32_t)cy, (uint32_t)vol.nb[0]) +
+                             (uint32_t)cx;
+        const uint32_t off = __umul24(bid, vol.brick_bytes) + __umul24(lz, vol.sz) + __umul24(ly, vol.sy) + lx;
+        const float t = trilinear<KIND>(rs, off, cn, fx, fy, fz);
+        const float2 par = vol.brick_par[bid];
+        return fmaf(par.y, t, par.x);
+    }
+}
+
+// Classification: post-classified RGBA by linear interpolation between
+// table entries (entry K duplicates entry K-1 so x = K-1 needs no clamp).
+__device__ __forceinline__ float4 classify(const float4* __restrict__ s_tf, float val, float ta, float tb,
+                                           float Km1) {
+    const float x = __builtin_amdgcn_fmed3f(fmaf(val, ta, tb), 0.0f, Km1);
+    const uint32_t j0 = (uint32_t)x;
+    const float g = x - (float)j0;
+    const float4 t0 = s_tf[j0], t1 = s_tf[j0 + 1];
+    return make_float4(lerp(t0.x, t1.x, g), lerp(t0.y, t1.y, g), lerp(t0.z, t1.z, g), lerp(t0.w, t1.w, g));
+}
+
+// Step 3: compositing one pixel's ray.
+template <int KIND>
+__device__ __forceinline__ void march_pixel(const ViewDesc& V, const float4* __restrict__ s_tf,
+                                            __amdgpu_buffer_rsrc_t rs, const Corners& cn, int i, int j,
+                                            float4& px, int& count) {
+    Ray R;
+    float Cr = 0.0f, Cg = 0.0f, Cb = 0.0f, T = 1.0f;
+    int k = 0;
+    if (setup_ray(V, i, j, R)) {
+        const float Km1 = (float)(V.K - 1);
+        const float ta = V.tf_a, tb = V.tf_b, thr = V.thr;
+        if (R.m > 0) {
+            for (;;) {
+                const float val = sample_value<KIND>(V.vol, rs, cn, R.Q);
+                const float4 c = classify(s_tf, val, ta, tb, Km1);
+                const float Ta = T * c.w;
+                Cr = fmaf(Ta, c.x, Cr);
+                Cg = fmaf(Ta, c.y, Cg);
+                Cb = fmaf(Ta, c.z, Cb);
+                T = fmaf(-T, c.w, T);
+                ++k;
+                if (k >= R.m || T <= thr) break;
+                R.Q[0] += R.dQ[0];
+                R.Q[1] += R.dQ[1];
+                R.Q[2] += R.dQ[2];
+            }
+        }
+        if (R.wp > 0.0f && T > thr) {
+            const float val = sample_value<KIND>(V.vol, rs, cn, R.Qp);
+            const float4 c = classify(s_tf, val, ta, tb, Km1);
+            const float a = 1.0f - exp2f(R.wp * log2f(1.0f - c.w));
+            const float Ta = T * a;
+            Cr = fmaf(Ta, c.x, Cr);
+            Cg = fmaf(Ta, c.y, Cg);
+            Cb = fmaf(Ta, c.z, Cb);
+            T = fmaf(-T, a, T);
+            ++k;
+        }
+    }
+    px = make_float4(fmaf(T, V.bg[0], Cr), fmaf(T, V.bg[1], Cg), fmaf(T, V.bg[2], Cb), fmaf(T, V.bg[3], 1.0f - T));
+    count = k;
+}
+
+__device__ __forceinline__ int wave_sum(int v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ void load_tf(float4* s_tf, const float4* __restrict__ tf, int K) {
+    for (int e = threadIdx.x; e < K; e += blockDim.x) s_tf[e] = tf[e];
+    if (threadIdx.x == 0) s_tf[K] = tf[K - 1];
+}
+
+// One workgroup block of a view: wave w renders tile (w % bw, w / bw) of the block.
+template <int KIND>
+__device__ __forceinline__ void render_block(const ViewDesc& V, const float4* __restrict__ s_tf, int blk,
+                                             const LaunchShape& ls, int tw_shift,
+                                             unsigned long long* __restrict__ counter) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int by = blk / V.blocks_x, bx = blk - by * V.blocks_x;
+    const int tx = bx * ls.bw + wave % ls.bw, ty = by * ls.bh + wave / ls.bw;
+    if (tx >= V.tiles_x || ty >= V.tiles_y) return;
+    const int i = tx * ls.tile_w + (lane & (ls.tile_w - 1)), j = ty * ls.tile_h + (lane >> tw_shift);
+    const __amdgpu_buffer_rsrc_t rs = make_rsrc(V.vol.data, V.vol.data_bytes);
+    const Corners cn = corners_of(Elem<KIND>::bytes, V.vol.sy, V.vol.sz);
+    int count = 0;
+    if (i < V.W && j < V.H) {
+        float4 px;
+        march_pixel<KIND>(V, s_tf, rs, cn, i, j, px, count);
+        const size_t p = (size_t)j * V.W + i;
+        reinterpret_cast<float4*>(V.out)[p] = px;
+        if (V.counts) V.counts[p] = count;
+    }
+    if (counter) {
+        const int tot = wave_sum(count);
+        if (lane == 0 && tot) atomicAdd(counter, (unsigned long long)tot);
+    }
+}
+
+// Blocks are dispatched round-robin over the 8 XCDs; give each XCD a
+// contiguous range of blocks (a compact band of the image) for L2 locality.
+__device__ __forceinline__ int xcd_remap(int b, int n) {
+    const int x = b & 7, idx = b >> 3;
+    const int per = n >> 3, rem = n & 7;
+    return x * per + min(x, rem) + idx;
+}
+
+template <int KIND>
+__global__ void __launch_bounds__(1024) march_plain_kernel(const ViewDesc V, const LaunchShape ls, int tw_shift,
+                                                            unsigned long long* __restrict__ counter) {
+    extern __shared__ float4 s_tf[];
+    load_tf(s_tf, V.tf, V.K);
+    __syncthreads();
+    render_block<KIND>(V, s_tf, xcd_remap(blockIdx.x, gridDim.x), ls, tw_shift, counter);
+}
+
+// Persistent batched marcher: workgroups claim blocks from a queue in the
+// workspace until it runs dry; the view of a block is found by binary search
+// over the per-view block prefix.  The transfer function in LDS is reloaded
+// only when the claimed view uses a different table.
+template <int KIND>
+__global__ void __launch_bounds__(1024) march_batch_kernel(char* __restrict__ ws, const LaunchShape ls, int tw_shift,
+                                                            int tf_entries) {
+    extern __shared__ float4 s_tf[];
+    int* s_claim = reinterpret_cast<int*>(s_tf + tf_entries);
+    BatchHeader* hdr = reinterpret_cast<BatchHeader*>(ws);
+    const int* __restrict__ prefix = reinterpret_cast<const int*>(ws + kBatchHeaderBytes);
+    const ViewDesc* __restrict__ jobs = reinterpret_cast<const ViewDesc*>(ws + kBatchHeaderBytes + kBatchPrefixBytes);
+    const int n_jobs = (int)__builtin_amdgcn_readfirstlane(hdr->n_jobs);
+    unsigned long long* counter = hdr->counter;
+    const int total = prefix[n_jobs];
+    const float4* cur_tf = nullptr;
+    for (;;) {
+        if (threadIdx.x == 0) s_claim[0] = (int)atomicAdd(&hdr->queue, 1u);
+        __syncthreads();
+        const int g = __builtin_amdgcn_readfirstlane(s_claim[0]);
+        if (g >= total) break;
+        int lo = 0, hi = n_jobs;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (prefix[mid] <= g) lo = mid;
+            else hi = mid;
+        }
+        const int jdx = __builtin_amdgcn_readfirstlane(lo);
+        const ViewDesc& V = jobs[jdx];
+        if (V.tf != cur_tf) {
+            cur_tf = V.tf;
+            load_tf(s_tf, V.tf, V.K);
+            __syncthreads();
+        }
+        render_block<KIND>(V, s_tf, g - prefix[jdx], ls, tw_shift, counter);
+        __syncthreads();
+    }
+}
+
+__global__ void batch_reset_kernel(unsigned int* queue) {
+    if (threadIdx.x == 0) *queue = 0u;
+}
+
+int log2i(int x) {
+    int s = 0;
+    while ((1 << s) < x) ++s;
+    return s;
+}
+
+template <int KIND>
+hipError_t plain_launch(const ViewDesc& v, const LaunchShape& ls, unsigned long long* counter, hipStream_t s) {
+    const int nblk = v.nblocks;
+    if (nblk <= 0) return hipSuccess;
+    const size_t lds = (size_t)(v.K + 1) * sizeof(float4);
+    static bool attr = false;
+    if (!attr) {
+        (void)hipFuncSetAttribute((const void*)march_plain_kernel<KIND>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)((kMaxK + 1) * sizeof(float4)));
+        attr = true;
+    }
+    hipLaunchKernelGGL(march_plain_kernel<KIND>, dim3(nblk), dim3(64 * ls.waves), lds, s, v, ls, log2i(ls.tile_w),
+                       counter);
+    return hipGetLastError();
+}
+
+template <int KIND>
+hipError_t batch_launch(void* ws, int grid, const LaunchShape& ls, int max_k, hipStream_t s) {
+    const int tf_entries = max_k + 1;
+    const size_t lds = (size_t)tf_entries * sizeof(float4) + 16;
+    static bool attr = false;
+    if (!attr) {
+        (void)hipFuncSetAttribute((const void*)march_batch_kernel<KIND>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)((kMaxK + 1) * sizeof(float4) + 16));
+        attr = true;
+    }
+    hipLaunchKernelGGL(march_batch_kernel<KIND>, dim3(grid), dim3(64 * ls.waves), lds, s, static_cast<char*>(ws), ls,
+                       log2i(ls.tile_w), tf_entries);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_march_plain(const ViewDesc& v, const LaunchShape& ls, unsigned long long* counter,
+                              hipStream_t s) {
+    switch (v.vol.kind) {
+        case ST_U8: return plain_launch<ST_U8>(v, ls, counter, s);
+        case ST_U16: return plain_launch<ST_U16>(v, ls, counter, s);
+        case ST_F16: return plain_launch<ST_F16>(v, ls, counter, s);
+        case ST_F32: return plain_launch<ST_F32>(v, ls, counter, s);
+        case ST_U8B: return plain_launch<ST_U8B>(v, ls, counter, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_march_batch(int kind, void* workspace, int grid, const LaunchShape& ls, int max_k,
+                              hipStream_t s) {
+    switch (kind) {
+        case ST_U8: return batch_launch<ST_U8>(workspace, grid, ls, max_k, s);
+        case ST_U16: return batch_launch<ST_U16>(workspace, grid, ls, max_k, s);
+        case ST_F16: return batch_launch<ST_F16>(workspace, grid, ls, max_k, s);
+        case ST_F32: return batch_launch<ST_F32>(workspace, grid, ls, max_k, s);
+        case ST_U8B: return batch_launch<ST_U8B>(workspace, grid, ls, max_k, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_batch_reset(void* workspace, hipStream_t s) {
+    hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, s, static_cast<unsigned int*>(workspace));
+    return hipGetLastError();
+}
+
+int batch_persistent_grid(const LaunchShape& ls, int max_k) {
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    const size_t lds = (size_t)(max_k + 1) * sizeof(float4) + 16;
+    (void)hipFuncSetAttribute((const void*)march_batch_kernel<ST_U16>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        (int)lds);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)march_batch_kernel<ST_U16>,
+                                                     64 * ls.waves, lds) != hipSuccess)
+        per_cu = 1;
+    if (per_cu < 1) per_cu = 1;
+    return cus * per_cu;
+}
+
+}  // namespace rtv

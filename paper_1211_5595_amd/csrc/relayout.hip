@@ -1,0 +1,215 @@
+// relayout.hip -- volume creation: source grid -> storage layout.
+//
+// The scalar field f(x,y,z) on a Cartesian grid (arXiv:1211.5595, Section
+// 2.1) arrives as a C-order [z][y][x] array.  The marcher reads
+//   - linear layouts: the grid with a one-node replicated border on every
+//     face, so a sample that rounding places a hair outside the box still
+//     has 8 valid corners and reproduces clamp-to-edge exactly;
+//   - brick-scaled 8-bit: per brick of B^3 cells a (lo, scale) and 8-bit
+//     codes for local nodes -1..B+1 (B+3 per axis), lo = min and
+//     scale = (max-lo)/255 over the brick's nodes, code = rint((v-lo)/scale)
+//     in binary32.  Every cell's 8 corners come from the brick owning it.
+#include <hip/hip_fp16.h>
+
+#include "rt_internal.h"
+
+namespace rtv {
+
+namespace {
+
+template <int KIND>
+struct Src;
+template <>
+struct Src<ST_U8> {
+    using T = unsigned char;
+    static __device__ __forceinline__ float f(T x) { return (float)x; }
+};
+template <>
+struct Src<ST_U16> {
+    using T = unsigned short;
+    static __device__ __forceinline__ float f(T x) { return (float)x; }
+};
+template <>
+struct Src<ST_F16> {
+    using T = unsigned short;
+    static __device__ __forceinline__ float f(T x) { return (float)__builtin_bit_cast(_Float16, x); }
+};
+template <>
+struct Src<ST_F32> {
+    using T = float;
+    static __device__ __forceinline__ float f(T x) { return x; }
+};
+
+template <int SRC, int DST>
+__device__ __forceinline__ void store_elem(void* dst, size_t e, typename Src<SRC>::T x) {
+    if constexpr (DST == ST_U8) {
+        static_cast<unsigned char*>(dst)[e] = (unsigned char)x;
+    } else if constexpr (DST == ST_U16) {
+        static_cast<unsigned short*>(dst)[e] = (unsigned short)x;
+    } else if constexpr (DST == ST_F16) {
+        if constexpr (SRC == ST_F16) {
+            static_cast<unsigned short*>(dst)[e] = x;
+        } else {
+            // integers up to 2^24 and binary32 values are exact in float; one RNE rounding to half
+            _Float16 h = (_Float16)Src<SRC>::f(x);
+            static_cast<unsigned short*>(dst)[e] = __builtin_bit_cast(unsigned short, h);
+        }
+    } else {
+        static_cast<float*>(dst)[e] = Src<SRC>::f(x);
+    }
+}
+
+template <int SRC, int DST>
+__global__ void __launch_bounds__(256) relayout_linear_kernel(const typename Src<SRC>::T* __restrict__ src,
+                                                               void* __restrict__ dst, int nx, int ny, int nz) {
+    const int px = nx + 2, py = ny + 2, pz = nz + 2;
+    const size_t total = (size_t)px * py * pz;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+        const int pi = (int)(e % px);
+        const size_t t = e / px;
+        const int pj = (int)(t % py), pk = (int)(t / py);
+        const int i = min(max(pi - 1, 0), nx - 1), j = min(max(pj - 1, 0), ny - 1), k = min(max(pk - 1, 0), nz - 1);
+        store_elem<SRC, DST>(dst, e, src[((size_t)k * ny + j) * nx + i]);
+    }
+}
+
+// One workgroup per brick: min and max over nodes [b*B, min(b*B+B, n-1)].
+template <int SRC>
+__global__ void __launch_bounds__(256) brick_minmax_kernel(const typename Src<SRC>::T* __restrict__ src, int nx,
+                                                            int ny, int nz, int B, int nbx, int nby,
+                                                            float2* __restrict__ par) {
+    __shared__ float s_lo[256], s_hi[256];
+    const int bid = blockIdx.x;
+    const int bx = bid % nbx, by = (bid / nbx) % nby, bz = bid / (nbx * nby);
+    const int x0 = bx * B, y0 = by * B, z0 = bz * B;
+    const int ex = min(x0 + B, nx - 1) - x0 + 1, ey = min(y0 + B, ny - 1) - y0 + 1, ez = min(z0 + B, nz - 1) - z0 + 1;
+    const int cnt = ex * ey * ez;
+    float lo = INFINITY, hi = -INFINITY;
+    for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
+        const int i = e % ex, j = (e / ex) % ey, k = e / (ex * ey);
+        const float v = Src<SRC>::f(src[((size_t)(z0 + k) * ny + (y0 + j)) * nx + (x0 + i)]);
+        lo = fminf(lo, v);
+        hi = fmaxf(hi, v);
+    }
+    s_lo[threadIdx.x] = lo;
+    s_hi[threadIdx.x] = hi;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            s_lo[threadIdx.x] = fminf(s_lo[threadIdx.x], s_lo[threadIdx.x + s]);
+            s_hi[threadIdx.x] = fmaxf(s_hi[threadIdx.x], s_hi[threadIdx.x + s]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const float l = s_lo[0], h = s_hi[0];
+        par[bid] = make_float2(l, h > l ? (h - l) / 255.0f : 1.0f);
+    }
+}
+
+// One thread per stored code; local node l in [0, B+2] is global node b*B+l-1,
+// clamped into the volume.
+template <int SRC>
+__global__ void __launch_bounds__(256) brick_encode_kernel(const typename Src<SRC>::T* __restrict__ src, int nx,
+                                                            int ny, int nz, int B, int nbx, int nby, int nbz,
+                                                            const float2* __restrict__ par,
+                                                            unsigned char* __restrict__ codes) {
+    const int S = B + 3;
+    const size_t per = (size_t)S * S * S;
+    const size_t total = per * nbx * nby * nbz;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+        const int bid = (int)(e / per);
+        const int l = (int)(e - (size_t)bid * per);
+        const int lx = l % S, ly = (l / S) % S, lz = l / (S * S);
+        const int bx = bid % nbx, by = (bid / nbx) % nby, bz = bid / (nbx * nby);
+        const int i = min(max(bx * B + lx - 1, 0), nx - 1);
+        const int j = min(max(by * B + ly - 1, 0), ny - 1);
+        const int k = min(max(bz * B + lz - 1, 0), nz - 1);
+        const float v = Src<SRC>::f(src[((size_t)k * ny + j) * nx + i]);
+        const float2 p = par[bid];
+        const float q = rintf((v - p.x) / p.y);
+        codes[e] = (unsigned char)fminf(fmaxf(q, 0.0f), 255.0f);
+    }
+}
+
+int grid_for(size_t total, int block) {
+    size_t g = (total + block - 1) / block;
+    if (g > (size_t)1 << 20) g = (size_t)1 << 20;
+    return (int)(g ? g : 1);
+}
+
+template <int SRC>
+hipError_t linear_dispatch(const void* src, int dst_kind, const int32_t n[3], void* dst, hipStream_t s) {
+    using T = typename Src<SRC>::T;
+    const T* p = static_cast<const T*>(src);
+    const size_t total = (size_t)(n[0] + 2) * (n[1] + 2) * (n[2] + 2);
+    const int g = grid_for(total, 256);
+    switch (dst_kind) {
+        case ST_U8:
+            if constexpr (SRC == ST_U8)
+                hipLaunchKernelGGL((relayout_linear_kernel<SRC, ST_U8>), dim3(g), dim3(256), 0, s, p, dst, n[0], n[1],
+                                   n[2]);
+            else
+                return hipErrorInvalidValue;
+            break;
+        case ST_U16:
+            if constexpr (SRC == ST_U8 || SRC == ST_U16)
+                hipLaunchKernelGGL((relayout_linear_kernel<SRC, ST_U16>), dim3(g), dim3(256), 0, s, p, dst, n[0],
+                                   n[1], n[2]);
+            else
+                return hipErrorInvalidValue;
+            break;
+        case ST_F16:
+            hipLaunchKernelGGL((relayout_linear_kernel<SRC, ST_F16>), dim3(g), dim3(256), 0, s, p, dst, n[0], n[1],
+                               n[2]);
+            break;
+        case ST_F32:
+            hipLaunchKernelGGL((relayout_linear_kernel<SRC, ST_F32>), dim3(g), dim3(256), 0, s, p, dst, n[0], n[1],
+                               n[2]);
+            break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <int SRC>
+hipError_t u8b_dispatch(const void* src, const int32_t n[3], int B, const int32_t nb[3], float2* par,
+                        unsigned char* codes, hipStream_t s) {
+    using T = typename Src<SRC>::T;
+    const T* p = static_cast<const T*>(src);
+    const int nbt = nb[0] * nb[1] * nb[2];
+    hipLaunchKernelGGL(brick_minmax_kernel<SRC>, dim3(nbt), dim3(256), 0, s, p, n[0], n[1], n[2], B, nb[0], nb[1],
+                       par);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const size_t total = (size_t)nbt * (B + 3) * (B + 3) * (B + 3);
+    hipLaunchKernelGGL(brick_encode_kernel<SRC>, dim3(grid_for(total, 256)), dim3(256), 0, s, p, n[0], n[1], n[2], B,
+                       nb[0], nb[1], nb[2], par, codes);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_relayout_linear(const void* src, int src_kind, int dst_kind, const int32_t n[3], void* dst,
+                                  hipStream_t s) {
+    switch (src_kind) {
+        case ST_U8: return linear_dispatch<ST_U8>(src, dst_kind, n, dst, s);
+        case ST_U16: return linear_dispatch<ST_U16>(src, dst_kind, n, dst, s);
+        case ST_F16: return linear_dispatch<ST_F16>(src, dst_kind, n, dst, s);
+        case ST_F32: return linear_dispatch<ST_F32>(src, dst_kind, n, dst, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_relayout_u8b(const void* src, int src_kind, const int32_t n[3], int B, const int32_t nb[3],
+                               float2* brick_par, unsigned char* codes, hipStream_t s) {
+    switch (src_kind) {
+        case ST_U8: return u8b_dispatch<ST_U8>(src, n, B, nb, brick_par, codes, s);
+        case ST_U16: return u8b_dispatch<ST_U16>(src, n, B, nb, brick_par, codes, s);
+        case ST_F16: return u8b_dispatch<ST_F16>(src, n, B, nb, brick_par, codes, s);
+        case ST_F32: return u8b_dispatch<ST_F32>(src, n, B, nb, brick_par, codes, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace rtv

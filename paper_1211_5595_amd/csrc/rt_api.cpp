@@ -1,0 +1,595 @@
+// rt_api.cpp -- host runtime behind include/rt.h: argument validation,
+// handle lifetime, view set-up in binary64 (rounded to float-float for the
+// device), launches on the caller's stream, batch plans captured in HIP
+// graphs.  See rt.h for the contract of every entry point.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "rt.h"
+#include "rt_internal.h"
+
+using namespace rtv;
+
+struct rt_volume {
+    VolDev dev;
+    int64_t dims[3];
+    double spacing[3];
+    int storage;
+    int brick;
+};
+
+struct rt_tf {
+    const float4* dev;
+    int K;
+    double vmin, vmax;
+    size_t bytes;
+};
+
+struct rt_batch_plan {
+    int max_jobs;
+    int kind;
+    LaunchShape ls;
+    int grid;
+    void* ws;
+    size_t ws_bytes;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+    void* staging;  // pinned host copy of header + prefix + job table
+    size_t staging_bytes;
+    hipEvent_t copy_done;
+    bool copy_pending;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+rt_status fail(rt_status s, const std::string& msg) {
+    g_last_error = msg;
+    return s;
+}
+
+rt_status hip_fail(hipError_t e, const char* what) {
+    return fail(RT_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+bool finite3(const double a[3]) { return std::isfinite(a[0]) && std::isfinite(a[1]) && std::isfinite(a[2]); }
+
+int elem_bytes(int kind) {
+    switch (kind) {
+        case ST_U8: return 1;
+        case ST_U16: return 2;
+        case ST_F16: return 2;
+        case ST_F32: return 4;
+        default: return 0;
+    }
+}
+
+size_t round256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Layout {
+    size_t total;         // bytes
+    size_t data_offset;   // start of the grid / codes
+    size_t data_bytes;
+    uint32_t sy, sz, brick_bytes;
+    int32_t nb[3];
+    int32_t bshift;
+};
+
+rt_status compute_layout(const int64_t dims[3], int storage, int brick, Layout& L) {
+    if (!dims) return fail(RT_ERR_INVALID_ARG, "dims is NULL");
+    for (int a = 0; a < 3; ++a)
+        if (dims[a] < 2 || dims[a] > (1 << 20)) return fail(RT_ERR_INVALID_ARG, "each dimension must be in [2, 2^20]");
+    std::memset(&L, 0, sizeof(L));
+    if (storage == RT_U8_BRICKSCALED) {
+        if (brick != 8 && brick != 16 && brick != 32)
+            return fail(RT_ERR_INVALID_ARG, "brick-scaled storage needs brick 8, 16 or 32");
+        size_t nbt = 1;
+        for (int a = 0; a < 3; ++a) {
+            L.nb[a] = (int32_t)((dims[a] - 1 + brick - 1) / brick);
+            nbt *= (size_t)L.nb[a];
+        }
+        const size_t S = (size_t)brick + 3;
+        L.sy = (uint32_t)S;
+        L.sz = (uint32_t)(S * S);
+        L.brick_bytes = (uint32_t)(S * S * S);
+        L.bshift = brick == 8 ? 3 : (brick == 16 ? 4 : 5);
+        L.data_offset = round256(nbt * sizeof(float2));
+        L.data_bytes = nbt * S * S * S;
+        if (nbt >= ((size_t)1 << 24) || L.data_bytes >= ((size_t)1 << 31))
+            return fail(RT_ERR_UNSUPPORTED, "volume too large for 32-bit brick addressing");
+        L.total = round256(L.data_offset + L.data_bytes);
+        return RT_OK;
+    }
+    if (brick != 0) return fail(RT_ERR_INVALID_ARG, "brick must be 0 for linear storage");
+    const int e = elem_bytes(storage);
+    if (!e) return fail(RT_ERR_INVALID_ARG, "unknown storage type");
+    const size_t px = (size_t)dims[0] + 2, py = (size_t)dims[1] + 2, pz = (size_t)dims[2] + 2;
+    L.sy = (uint32_t)(px * e);
+    L.sz = (uint32_t)(px * py * e);
+    if (px * py * e >= ((size_t)1 << 24)) return fail(RT_ERR_UNSUPPORTED, "slice too large for 24-bit addressing");
+    L.data_offset = 0;
+    L.data_bytes = px * py * pz * e;
+    if (L.data_bytes >= ((size_t)1 << 31)) return fail(RT_ERR_UNSUPPORTED, "volume larger than 2 GiB of storage");
+    L.total = round256(L.data_bytes);
+    return RT_OK;
+}
+
+ff to_ff(double x) {
+    ff r;
+    r.hi = (float)x;
+    r.lo = (float)(x - (double)r.hi);
+    return r;
+}
+
+void cross(const double a[3], const double b[3], double c[3]) {
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+}
+double norm(const double a[3]) { return std::sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]); }
+
+rt_status make_shape(const rt_render_opts* opts, LaunchShape& ls) {
+    int tw = 8, th = 8, waves = 16;
+    if (opts) {
+        if (opts->tile_w || opts->tile_h) {
+            tw = opts->tile_w;
+            th = opts->tile_h;
+        }
+        if (opts->waves_per_block) waves = opts->waves_per_block;
+    }
+    if (tw <= 0 || th <= 0 || tw * th != 64 || (tw & (tw - 1)))
+        return fail(RT_ERR_UNSUPPORTED, "tile must be tile_w x tile_h = 64 with tile_w a power of two");
+    if (waves != 1 && waves != 2 && waves != 4 && waves != 8 && waves != 16)
+        return fail(RT_ERR_UNSUPPORTED, "waves_per_block must be 1, 2, 4, 8 or 16");
+    ls.tile_w = tw;
+    ls.tile_h = th;
+    ls.waves = waves;
+    ls.bw = waves >= 4 ? (waves >= 16 ? 4 : (waves == 8 ? 4 : 2)) : waves;
+    ls.bh = waves / ls.bw;
+    return RT_OK;
+}
+
+rt_status make_view(const rt_volume* vol, const int64_t dims[3], const double spacing[3], const rt_tf* tf,
+                    const rt_camera* cam, int W, int H, double step_vox, double cutoff, const float* bg,
+                    float* out, int32_t* counts, const LaunchShape& ls, int ray_function, ViewDesc& v) {
+    if (!vol || !tf || !cam || !out) return fail(RT_ERR_INVALID_ARG, "NULL volume, transfer function, camera or output");
+    if (dims)
+        for (int a = 0; a < 3; ++a)
+            if (dims[a] != vol->dims[a]) return fail(RT_ERR_INVALID_ARG, "dims differ from the volume's dims");
+    double sp[3];
+    for (int a = 0; a < 3; ++a) {
+        sp[a] = spacing ? spacing[a] : vol->spacing[a];
+        if (!(sp[a] > 0.0) || !std::isfinite(sp[a])) return fail(RT_ERR_INVALID_ARG, "spacing must be finite and > 0");
+    }
+    if (W < 1 || H < 1 || W > 32768 || H > 32768) return fail(RT_ERR_INVALID_ARG, "image size must be in [1, 32768]");
+    if (!(step_vox > 0.0) || !std::isfinite(step_vox)) return fail(RT_ERR_INVALID_ARG, "step must be finite and > 0");
+    if (!(cutoff > 0.0 && cutoff <= 1.0)) return fail(RT_ERR_INVALID_ARG, "alpha cutoff must be in (0, 1]");
+    if (((uintptr_t)out & 15) != 0) return fail(RT_ERR_INVALID_ARG, "output must be 16-byte aligned");
+    if (ray_function != RT_COMPOSITE) return fail(RT_ERR_UNSUPPORTED, "ray function not built");
+    if (!finite3(cam->eye) || !finite3(cam->center) || !finite3(cam->up))
+        return fail(RT_ERR_INVALID_ARG, "camera vectors must be finite");
+    double f[3] = {cam->center[0] - cam->eye[0], cam->center[1] - cam->eye[1], cam->center[2] - cam->eye[2]};
+    const double fl = norm(f);
+    if (!(fl > 0.0)) return fail(RT_ERR_INVALID_ARG, "camera eye equals center");
+    double w[3] = {f[0] / fl, f[1] / fl, f[2] / fl}, s[3], u[3], vv[3];
+    cross(w, cam->up, s);
+    const double sl = norm(s);
+    if (!(sl >= 1e-12 * norm(cam->up)) || !(sl > 0.0)) return fail(RT_ERR_INVALID_ARG, "camera up is parallel to the view");
+    for (int a = 0; a < 3; ++a) u[a] = s[a] / sl;
+    cross(u, w, vv);
+    double scale;
+    if (cam->perspective) {
+        if (!(cam->fovy_deg > 0.0 && cam->fovy_deg < 180.0)) return fail(RT_ERR_INVALID_ARG, "fovy must be in (0, 180)");
+        scale = std::tan(0.5 * cam->fovy_deg * M_PI / 180.0) / (double)H;
+    } else {
+        if (!(cam->ortho_half_height > 0.0) || !std::isfinite(cam->ortho_half_height))
+            return fail(RT_ERR_INVALID_ARG, "orthographic half-height must be finite and > 0");
+        scale = cam->ortho_half_height / (double)H;
+    }
+    if (bg)
+        for (int c = 0; c < 4; ++c)
+            if (!std::isfinite(bg[c])) return fail(RT_ERR_INVALID_ARG, "background must be finite");
+    const double dt = step_vox * std::min(sp[0], std::min(sp[1], sp[2]));
+    double diag2 = 0.0;
+    for (int a = 0; a < 3; ++a) diag2 += std::pow((double)(vol->dims[a] - 1) * sp[a], 2);
+    if (std::sqrt(diag2) / dt + 2.0 > (double)(1 << 30)) return fail(RT_ERR_INVALID_ARG, "step too small for the volume");
+
+    std::memset(&v, 0, sizeof(v));
+    for (int a = 0; a < 3; ++a) {
+        v.eye[a] = to_ff(cam->eye[a]);
+        v.w[a] = to_ff(w[a]);
+        v.U[a] = to_ff(scale * u[a]);
+        v.V[a] = to_ff(scale * vv[a]);
+        v.inv_sp[a] = to_ff(1.0 / sp[a]);
+        v.box_hi[a] = to_ff((double)(vol->dims[a] - 1) * sp[a]);
+    }
+    v.dt = to_ff(dt);
+    v.thr = (float)(1.0 - cutoff);
+    for (int c = 0; c < 4; ++c) v.bg[c] = bg ? bg[c] : 0.0f;
+    v.W = W;
+    v.H = H;
+    v.perspective = cam->perspective ? 1 : 0;
+    v.tiles_x = (W + ls.tile_w - 1) / ls.tile_w;
+    v.tiles_y = (H + ls.tile_h - 1) / ls.tile_h;
+    v.blocks_x = (v.tiles_x + ls.bw - 1) / ls.bw;
+    v.nblocks = v.blocks_x * ((v.tiles_y + ls.bh - 1) / ls.bh);
+    v.ray_function = ray_function;
+    v.vol = vol->dev;
+    v.tf = tf->dev;
+    v.K = tf->K;
+    const double ta = (double)(tf->K - 1) / (tf->vmax - tf->vmin);
+    v.tf_a = (float)ta;
+    v.tf_b = (float)(-tf->vmin * ta);
+    v.out = out;
+    v.counts = counts;
+    return RT_OK;
+}
+
+// Pinned staging buffer reused across calls once its last copy has finished.
+struct Staging {
+    void* p = nullptr;
+    size_t bytes = 0;
+    hipEvent_t ev = nullptr;
+    bool pending = false;
+};
+thread_local Staging g_staging;
+
+rt_status staging_acquire(Staging& st, size_t bytes, void** out) {
+    if (st.pending) {
+        hipError_t e = hipEventSynchronize(st.ev);
+        if (e != hipSuccess) return hip_fail(e, "waiting for the previous job-table copy");
+        st.pending = false;
+    }
+    if (!st.ev) {
+        hipError_t e = hipEventCreateWithFlags(&st.ev, hipEventDisableTiming);
+        if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+    }
+    if (st.bytes < bytes) {
+        if (st.p) (void)hipHostFree(st.p);
+        st.p = nullptr;
+        st.bytes = 0;
+        hipError_t e = hipHostMalloc(&st.p, bytes, hipHostMallocDefault);
+        if (e != hipSuccess) return hip_fail(e, "hipHostMalloc(staging)");
+        st.bytes = bytes;
+    }
+    *out = st.p;
+    return RT_OK;
+}
+
+size_t prefix_bytes() { return kBatchPrefixBytes; }
+
+size_t batch_ws_bytes(int max_jobs) { return kBatchHeaderBytes + prefix_bytes() + (size_t)max_jobs * sizeof(ViewDesc); }
+
+// Fill header, prefix and job table for n jobs into host memory `h`; returns
+// the bytes to copy.
+rt_status build_batch(const rt_render_job* jobs, int n, const LaunchShape& ls, int ray_function, int* kind,
+                      int* max_k, std::vector<ViewDesc>& descs, std::vector<int>& prefix) {
+    if (!jobs || n < 1) return fail(RT_ERR_INVALID_ARG, "empty batch");
+    if (n > kMaxBatchJobs) return fail(RT_ERR_UNSUPPORTED, "too many jobs in one batch");
+    descs.resize(n);
+    prefix.assign(n + 1, 0);
+    *kind = -1;
+    *max_k = 2;
+    for (int i = 0; i < n; ++i) {
+        const rt_render_job& J = jobs[i];
+        if (!J.volume) return fail(RT_ERR_INVALID_ARG, "job without volume");
+        rt_status st = make_view(J.volume, nullptr, nullptr, J.tf, &J.camera, J.width, J.height, J.step_vox,
+                                 J.alpha_cutoff, J.bg_rgba, J.out_dev, J.pixel_counts, ls, ray_function, descs[i]);
+        if (st != RT_OK) return fail(st, "job " + std::to_string(i) + ": " + g_last_error);
+        if (*kind < 0) *kind = J.volume->storage == RT_U8_BRICKSCALED ? ST_U8B : J.volume->storage;
+        const int k = J.volume->storage == RT_U8_BRICKSCALED ? ST_U8B : J.volume->storage;
+        if (k != *kind) return fail(RT_ERR_UNSUPPORTED, "all volumes of a batch must share one storage type");
+        *max_k = std::max(*max_k, J.tf->K);
+        const long long next = (long long)prefix[i] + descs[i].nblocks;
+        if (next >= (1LL << 31)) return fail(RT_ERR_UNSUPPORTED, "batch too large");
+        prefix[i + 1] = (int)next;
+    }
+    return RT_OK;
+}
+
+void write_batch_host(void* h, const std::vector<ViewDesc>& descs, const std::vector<int>& prefix, int max_k,
+                      unsigned long long* counter) {
+    char* b = static_cast<char*>(h);
+    BatchHeader hdr;
+    std::memset(&hdr, 0, sizeof(hdr));
+    hdr.queue = 0;
+    hdr.n_jobs = (unsigned)descs.size();
+    hdr.total_blocks = (unsigned)prefix.back();
+    hdr.tf_lds_entries = max_k + 1;
+    hdr.counter = counter;
+    std::memset(b, 0, kBatchHeaderBytes);
+    std::memcpy(b, &hdr, sizeof(hdr));
+    std::memcpy(b + kBatchHeaderBytes, prefix.data(), prefix.size() * sizeof(int));
+    std::memcpy(b + kBatchHeaderBytes + prefix_bytes(), descs.data(), descs.size() * sizeof(ViewDesc));
+}
+
+size_t batch_copy_bytes(int n) { return kBatchHeaderBytes + prefix_bytes() + (size_t)n * sizeof(ViewDesc); }
+
+}  // namespace
+
+extern "C" {
+
+const char* rt_status_string(rt_status s) {
+    switch (s) {
+        case RT_OK: return "ok";
+        case RT_ERR_INVALID_ARG: return "invalid argument";
+        case RT_ERR_OUT_OF_MEMORY: return "buffer too small";
+        case RT_ERR_DEVICE: return "device error";
+        case RT_ERR_UNSUPPORTED: return "unsupported";
+    }
+    return "unknown status";
+}
+
+const char* rt_last_error(void) { return g_last_error.c_str(); }
+
+const char* rt_version(void) { return "rtvol 0.1 gfx950"; }
+
+rt_status rt_volume_bytes(const int64_t dims[3], int storage, int brick, size_t* bytes) {
+    if (!bytes) return fail(RT_ERR_INVALID_ARG, "bytes is NULL");
+    Layout L;
+    rt_status st = compute_layout(dims, storage, brick, L);
+    if (st != RT_OK) return st;
+    *bytes = L.total;
+    return RT_OK;
+}
+
+rt_status rt_create_volume(const void* src_dev, int src_dtype, const int64_t dims[3], const double spacing[3],
+                           int storage, int brick, void* dev_buf, size_t dev_buf_bytes, void* stream,
+                           rt_volume** out) {
+    if (!out) return fail(RT_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!src_dev || !dev_buf || !spacing) return fail(RT_ERR_INVALID_ARG, "NULL source, buffer or spacing");
+    if (src_dtype < RT_U8 || src_dtype > RT_F32) return fail(RT_ERR_INVALID_ARG, "source type must be U8, U16, F16 or F32");
+    for (int a = 0; a < 3; ++a)
+        if (!(spacing[a] > 0.0) || !std::isfinite(spacing[a])) return fail(RT_ERR_INVALID_ARG, "spacing must be finite and > 0");
+    Layout L;
+    rt_status st = compute_layout(dims, storage, brick, L);
+    if (st != RT_OK) return st;
+    if (dev_buf_bytes < L.total) return fail(RT_ERR_OUT_OF_MEMORY, "volume buffer smaller than rt_volume_bytes");
+    if (((uintptr_t)dev_buf & 255) != 0) return fail(RT_ERR_INVALID_ARG, "volume buffer must be 256-byte aligned");
+    if (storage != RT_U8_BRICKSCALED) {
+        const bool ok = storage == RT_F16 || storage == RT_F32 || (storage == RT_U16 && src_dtype <= RT_U16) ||
+                        (storage == RT_U8 && src_dtype == RT_U8);
+        if (!ok) return fail(RT_ERR_INVALID_ARG, "conversion to this storage type would lose information");
+    }
+    const int32_t n[3] = {(int32_t)dims[0], (int32_t)dims[1], (int32_t)dims[2]};
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char* base = static_cast<char*>(dev_buf);
+    hipError_t e;
+    if (storage == RT_U8_BRICKSCALED)
+        e = launch_relayout_u8b(src_dev, src_dtype, n, brick, L.nb, reinterpret_cast<float2*>(base),
+                                reinterpret_cast<unsigned char*>(base + L.data_offset), s);
+    else
+        e = launch_relayout_linear(src_dev, src_dtype, storage, n, base, s);
+    if (e != hipSuccess) return hip_fail(e, "relayout launch");
+    rt_volume* v = new (std::nothrow) rt_volume;
+    if (!v) return fail(RT_ERR_OUT_OF_MEMORY, "host allocation failed");
+    std::memset(v, 0, sizeof(*v));
+    v->dev.data = reinterpret_cast<const unsigned char*>(base + L.data_offset);
+    v->dev.brick_par = storage == RT_U8_BRICKSCALED ? reinterpret_cast<const float2*>(base) : nullptr;
+    v->dev.data_bytes = (uint32_t)L.data_bytes;
+    v->dev.sy = L.sy;
+    v->dev.sz = L.sz;
+    v->dev.brick_bytes = L.brick_bytes;
+    for (int a = 0; a < 3; ++a) {
+        v->dev.n[a] = n[a];
+        v->dev.nb[a] = L.nb[a];
+        v->dims[a] = dims[a];
+        v->spacing[a] = spacing[a];
+    }
+    v->dev.bshift = L.bshift;
+    v->dev.kind = storage == RT_U8_BRICKSCALED ? ST_U8B : storage;
+    v->storage = storage;
+    v->brick = brick;
+    *out = v;
+    return RT_OK;
+}
+
+rt_status rt_destroy_volume(rt_volume* vol) {
+    delete vol;
+    return RT_OK;
+}
+
+rt_status rt_tf_bytes(int K, size_t* bytes) {
+    if (!bytes) return fail(RT_ERR_INVALID_ARG, "bytes is NULL");
+    if (K < 2 || K > kMaxK) return fail(RT_ERR_INVALID_ARG, "K must be in [2, 4096]");
+    *bytes = round256((size_t)K * 16);
+    return RT_OK;
+}
+
+rt_status rt_set_transfer_function(rt_tf** tf, const float* rgba, int K, double vmin, double vmax, void* dev_buf,
+                                   size_t dev_buf_bytes, void* stream) {
+    if (!tf || !rgba) return fail(RT_ERR_INVALID_ARG, "NULL handle pointer or table");
+    if (K < 2 || K > kMaxK) return fail(RT_ERR_INVALID_ARG, "K must be in [2, 4096]");
+    if (!std::isfinite(vmin) || !std::isfinite(vmax) || !(vmax > vmin)) return fail(RT_ERR_INVALID_ARG, "need vmin < vmax");
+    for (int i = 0; i < 4 * K; ++i)
+        if (!(rgba[i] >= 0.0f && rgba[i] <= 1.0f)) return fail(RT_ERR_INVALID_ARG, "table entries must be in [0, 1]");
+    const size_t need = (size_t)K * 16;
+    if (*tf) {
+        if ((*tf)->K != K || (dev_buf && dev_buf != (const void*)(*tf)->dev))
+            return fail(RT_ERR_INVALID_ARG, "an update must keep the buffer and K");
+        dev_buf = const_cast<float4*>((*tf)->dev);
+        dev_buf_bytes = (*tf)->bytes;
+    }
+    if (!dev_buf) return fail(RT_ERR_INVALID_ARG, "NULL device buffer");
+    if (dev_buf_bytes < need) return fail(RT_ERR_OUT_OF_MEMORY, "transfer-function buffer smaller than rt_tf_bytes");
+    if (((uintptr_t)dev_buf & 15) != 0) return fail(RT_ERR_INVALID_ARG, "transfer-function buffer must be 16-byte aligned");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = hipMemcpyAsync(dev_buf, rgba, need, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "transfer-function copy");
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "transfer-function copy");
+    if (!*tf) {
+        rt_tf* t = new (std::nothrow) rt_tf;
+        if (!t) return fail(RT_ERR_OUT_OF_MEMORY, "host allocation failed");
+        t->dev = static_cast<const float4*>(dev_buf);
+        t->K = K;
+        t->bytes = dev_buf_bytes;
+        *tf = t;
+    }
+    (*tf)->vmin = vmin;
+    (*tf)->vmax = vmax;
+    return RT_OK;
+}
+
+rt_status rt_destroy_tf(rt_tf* tf) {
+    delete tf;
+    return RT_OK;
+}
+
+rt_status rt_render(const rt_volume* volume, const int64_t dims[3], const double spacing[3], const rt_tf* tf,
+                    const rt_camera* camera, int width, int height, double step_vox, double alpha_cutoff,
+                    const float bg_rgba[4], float* out_dev, const rt_render_opts* opts, void* stream) {
+    if (!dims) return fail(RT_ERR_INVALID_ARG, "dims is NULL");
+    LaunchShape ls;
+    rt_status st = make_shape(opts, ls);
+    if (st != RT_OK) return st;
+    ViewDesc v;
+    st = make_view(volume, dims, spacing, tf, camera, width, height, step_vox, alpha_cutoff, bg_rgba, out_dev,
+                   opts ? opts->pixel_counts : nullptr, ls, opts ? opts->ray_function : 0, v);
+    if (st != RT_OK) return st;
+    hipError_t e = launch_march_plain(v, ls, opts ? opts->sample_counter : nullptr, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "render launch");
+    return RT_OK;
+}
+
+rt_status rt_batch_workspace_bytes(int max_jobs, size_t* bytes) {
+    if (!bytes) return fail(RT_ERR_INVALID_ARG, "bytes is NULL");
+    if (max_jobs < 1 || max_jobs > kMaxBatchJobs) return fail(RT_ERR_INVALID_ARG, "max_jobs must be in [1, 4096]");
+    *bytes = batch_ws_bytes(max_jobs);
+    return RT_OK;
+}
+
+rt_status rt_render_batch(const rt_render_job* jobs, int n, void* workspace, size_t ws_bytes,
+                          unsigned long long* sample_counter, const rt_render_opts* opts, void* stream) {
+    if (!workspace) return fail(RT_ERR_INVALID_ARG, "workspace is NULL");
+    if (((uintptr_t)workspace & 255) != 0) return fail(RT_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+    LaunchShape ls;
+    rt_status st = make_shape(opts, ls);
+    if (st != RT_OK) return st;
+    std::vector<ViewDesc> descs;
+    std::vector<int> prefix;
+    int kind, max_k;
+    st = build_batch(jobs, n, ls, opts ? opts->ray_function : 0, &kind, &max_k, descs, prefix);
+    if (st != RT_OK) return st;
+    if (ws_bytes < batch_ws_bytes(n)) return fail(RT_ERR_OUT_OF_MEMORY, "workspace smaller than rt_batch_workspace_bytes");
+    const size_t bytes = batch_copy_bytes(n);
+    void* h = nullptr;
+    st = staging_acquire(g_staging, bytes, &h);
+    if (st != RT_OK) return st;
+    write_batch_host(h, descs, prefix, max_k, sample_counter);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = hipMemcpyAsync(workspace, h, bytes, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "job-table copy");
+    e = hipEventRecord(g_staging.ev, s);
+    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    g_staging.pending = true;
+    const int grid = std::min(batch_persistent_grid(ls, max_k), std::max(prefix.back(), 1));
+    e = launch_march_batch(kind, workspace, grid, ls, max_k, s);
+    if (e != hipSuccess) return hip_fail(e, "batch launch");
+    return RT_OK;
+}
+
+rt_status rt_batch_plan_create(int max_jobs, int storage, void* workspace, size_t ws_bytes, const rt_render_opts* opts,
+                               rt_batch_plan** out) {
+    if (!out) return fail(RT_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!workspace) return fail(RT_ERR_INVALID_ARG, "workspace is NULL");
+    if (((uintptr_t)workspace & 255) != 0) return fail(RT_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+    if (max_jobs < 1 || max_jobs > kMaxBatchJobs) return fail(RT_ERR_INVALID_ARG, "max_jobs must be in [1, 4096]");
+    if (ws_bytes < batch_ws_bytes(max_jobs)) return fail(RT_ERR_OUT_OF_MEMORY, "workspace smaller than rt_batch_workspace_bytes");
+    if (storage < RT_U8 || storage > RT_U8_BRICKSCALED) return fail(RT_ERR_INVALID_ARG, "unknown storage type");
+    LaunchShape ls;
+    rt_status st = make_shape(opts, ls);
+    if (st != RT_OK) return st;
+    if (opts && opts->ray_function != RT_COMPOSITE) return fail(RT_ERR_UNSUPPORTED, "ray function not built");
+    rt_batch_plan* p = new (std::nothrow) rt_batch_plan;
+    if (!p) return fail(RT_ERR_OUT_OF_MEMORY, "host allocation failed");
+    std::memset(p, 0, sizeof(*p));
+    p->max_jobs = max_jobs;
+    p->kind = storage == RT_U8_BRICKSCALED ? ST_U8B : storage;
+    p->ls = ls;
+    p->grid = batch_persistent_grid(ls, kMaxK);
+    p->ws = workspace;
+    p->ws_bytes = ws_bytes;
+    hipStream_t cs;
+    hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        delete p;
+        return hip_fail(e, "hipStreamCreate");
+    }
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) e = launch_batch_reset(workspace, cs);
+    if (e == hipSuccess) e = launch_march_batch(p->kind, workspace, p->grid, ls, kMaxK, cs);
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(cs, &g);
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess) e = hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0);
+    (void)hipStreamDestroy(cs);
+    if (e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        delete p;
+        return hip_fail(e, "batch graph capture");
+    }
+    p->graph = g;
+    e = hipEventCreateWithFlags(&p->copy_done, hipEventDisableTiming);
+    if (e == hipSuccess) {
+        p->staging_bytes = batch_copy_bytes(max_jobs);
+        e = hipHostMalloc(&p->staging, p->staging_bytes, hipHostMallocDefault);
+    }
+    if (e != hipSuccess) {
+        rt_batch_plan_destroy(p);
+        return hip_fail(e, "batch plan staging");
+    }
+    *out = p;
+    return RT_OK;
+}
+
+rt_status rt_batch_plan_launch(rt_batch_plan* p, const rt_render_job* jobs, int n, unsigned long long* sample_counter,
+                               void* stream) {
+    if (!p) return fail(RT_ERR_INVALID_ARG, "plan is NULL");
+    if (n > p->max_jobs) return fail(RT_ERR_INVALID_ARG, "more jobs than the plan holds");
+    std::vector<ViewDesc> descs;
+    std::vector<int> prefix;
+    int kind, max_k;
+    rt_status st = build_batch(jobs, n, p->ls, 0, &kind, &max_k, descs, prefix);
+    if (st != RT_OK) return st;
+    if (kind != p->kind) return fail(RT_ERR_INVALID_ARG, "jobs' storage type differs from the plan's");
+    if (p->copy_pending) {
+        hipError_t e = hipEventSynchronize(p->copy_done);
+        if (e != hipSuccess) return hip_fail(e, "waiting for the previous job-table copy");
+        p->copy_pending = false;
+    }
+    const size_t bytes = batch_copy_bytes(n);
+    write_batch_host(p->staging, descs, prefix, max_k, sample_counter);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = hipMemcpyAsync(p->ws, p->staging, bytes, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "job-table copy");
+    e = hipEventRecord(p->copy_done, s);
+    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    p->copy_pending = true;
+    e = hipGraphLaunch(p->exec, s);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    return RT_OK;
+}
+
+rt_status rt_batch_plan_destroy(rt_batch_plan* p) {
+    if (!p) return RT_OK;
+    if (p->copy_pending && p->copy_done) (void)hipEventSynchronize(p->copy_done);
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->copy_done) (void)hipEventDestroy(p->copy_done);
+    if (p->staging) (void)hipHostFree(p->staging);
+    delete p;
+    return RT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,101 @@
+// rt_internal.h -- structures shared by the library's host runtime and its
+// HIP kernels.  Product code only; the reference oracle has its own header.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rtv {
+
+// A float-float number: value = hi + lo with |lo| <= ulp(hi)/2.  Used for the
+// per-ray set-up so that sample positions carry ~44 bits.
+struct ff {
+    float hi, lo;
+};
+
+enum StorageKind : int { ST_U8 = 0, ST_U16 = 1, ST_F16 = 2, ST_F32 = 3, ST_U8B = 4 };
+
+// Device view of a volume in storage layout.
+//  Linear layouts (U8/U16/F16/F32): (nx+2)(ny+2)(nz+2) elements with a
+//  one-node replicated border; element (Pi,Pj,Pk) of the padded grid holds
+//  node (clamp(Pi-1), clamp(Pj-1), clamp(Pk-1)).
+//  Brick-scaled 8-bit (U8B): per brick of B^3 cells a (lo, scale) float2 and
+//  (B+3)^3 codes for local nodes -1..B+1 (replicated beyond the volume).
+struct VolDev {
+    const unsigned char* data;  // linear: padded grid; U8B: codes of brick 0
+    const float2* brick_par;    // U8B: (lo, scale) per brick
+    uint32_t data_bytes;        // size of `data` in bytes (buffer bound)
+    uint32_t sy, sz;            // linear: padded row / slice stride in bytes; U8B: (B+3), (B+3)^2
+    uint32_t brick_bytes;       // U8B: (B+3)^3
+    int32_t n[3];               // nodes per axis
+    int32_t nb[3];              // U8B: bricks per axis
+    int32_t bshift;             // U8B: log2(B)
+    int32_t kind;               // StorageKind
+};
+
+// Everything one view needs; computed on the host in binary64, rounded to
+// float-float.  Pixel (i,j) uses a = 2i+1-W, b = H-2j-1:
+//   pinhole:      origin eye,              direction normalize(w + a*U + b*V)
+//   orthographic: origin eye + a*U + b*V,  direction w
+struct ViewDesc {
+    ff eye[3];
+    ff w[3];
+    ff U[3];
+    ff V[3];
+    ff inv_sp[3];     // 1 / spacing
+    ff box_hi[3];     // (n-1) * spacing, mm
+    ff dt;            // sample spacing, mm
+    float thr;        // stop once transmittance T <= thr (= 1 - cutoff)
+    float bg[4];
+    int32_t W, H, perspective;
+    int32_t tiles_x, tiles_y;   // ray tiles (of tile_w x tile_h pixels)
+    int32_t blocks_x;           // workgroup blocks per block-row
+    int32_t nblocks;            // workgroup blocks of this view
+    int32_t ray_function;
+    float iso_lo, iso_hi;
+    VolDev vol;
+    const float4* tf;           // K entries
+    int32_t K;
+    float tf_a, tf_b;           // x = val*tf_a + tf_b, clamped to [0, K-1]
+    float* out;                 // H*W float4
+    int32_t* counts;            // nullable
+};
+
+// Launch geometry common to the plain and batched marchers.
+struct LaunchShape {
+    int tile_w, tile_h;   // tile_w * tile_h == 64
+    int waves;            // waves per workgroup
+    int bw, bh;           // workgroup block in tiles: bw * bh == waves
+};
+
+// Workspace layout of a batched launch (device memory owned by the caller).
+//  [BatchHeader | 256 B][prefix: int[kMaxBatchJobs+1], 256-aligned][ViewDesc x n]
+// prefix[i] = first workgroup block of view i, prefix[n] = total blocks.
+struct BatchHeader {
+    unsigned int queue;                 // next workgroup block to claim
+    unsigned int n_jobs;
+    unsigned int total_blocks;
+    int32_t tf_lds_entries;             // max K over the jobs, +1
+    unsigned long long* counter;        // nullable sample counter
+};
+static constexpr size_t kBatchHeaderBytes = 256;
+static constexpr int kMaxBatchJobs = 4096;
+static constexpr size_t kBatchPrefixBytes = ((size_t)(kMaxBatchJobs + 1) * sizeof(int) + 255) & ~(size_t)255;
+static constexpr int kMaxK = 4096;
+
+// Host launchers (march.hip / relayout.hip).
+hipError_t launch_march_plain(const ViewDesc& v, const LaunchShape& ls, unsigned long long* counter,
+                              hipStream_t s);
+// Views, prefix, job count and counter pointer are read from the workspace,
+// so one captured launch serves every batch that fits the workspace.
+hipError_t launch_march_batch(int kind, void* workspace, int grid, const LaunchShape& ls, int max_k,
+                              hipStream_t s);
+hipError_t launch_batch_reset(void* workspace, hipStream_t s);
+int batch_persistent_grid(const LaunchShape& ls, int max_k);
+
+hipError_t launch_relayout_linear(const void* src, int src_kind, int dst_kind, const int32_t n[3], void* dst,
+                                  hipStream_t s);
+hipError_t launch_relayout_u8b(const void* src, int src_kind, const int32_t n[3], int B, const int32_t nb[3],
+                               float2* brick_par, unsigned char* codes, hipStream_t s);
+
+}  // namespace rtv

@@ -1,0 +1,99 @@
+"""The C ABI on the CPU: the library loads, exports every symbol declared in
+include/rt.h, and its host-only paths (sizes, validation) behave as the
+header documents.  No kernel is launched here."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from conftest import ROOT
+
+
+@pytest.fixture(scope="module")
+def rt():
+    import paper_1211_5595_amd as rt
+    if not os.path.exists(rt.LIB_PATH):
+        from paper_1211_5595_amd import build
+        build.build()
+    rt.lib()
+    return rt
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "rt.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rt_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(rt):
+    names = declared_functions()
+    assert len(names) >= 15
+    L = rt.lib()
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_oracle_and_product_share_no_symbols(rt, orc):
+    L = C.CDLL(orc.LIB_PATH)
+    for n in declared_functions():
+        assert not hasattr(L, n)
+
+
+def test_volume_bytes(rt):
+    # linear: (n+2)^3 padded nodes times the element size, rounded to 256
+    assert rt.rt_volume_bytes((256, 256, 160), rt.U16) == ((258 * 258 * 162 * 2 + 255) // 256) * 256
+    assert rt.rt_volume_bytes((64, 64, 32), rt.U8) == ((66 * 66 * 34 + 255) // 256) * 256
+    assert rt.rt_volume_bytes((2, 2, 2), rt.F32) == 256
+    # brick-scaled: ceil((n-1)/B) bricks per axis, (B+3)^3 codes and 8 bytes each
+    nb = 16 * 16 * 10
+    assert rt.rt_volume_bytes((256, 256, 160), rt.U8_BRICKSCALED, 16) == \
+        ((((nb * 8 + 255) // 256) * 256 + nb * 19 ** 3 + 255) // 256) * 256
+
+
+@pytest.mark.parametrize("dims,storage,brick,exc", [
+    ((1, 4, 4), 1, 0, "InvalidArgument"),
+    ((4, 4, 4), 4, 12, "InvalidArgument"),
+    ((4, 4, 4), 1, 8, "InvalidArgument"),
+    ((4, 4, 4), 9, 0, "InvalidArgument"),
+    ((5000, 5000, 4), 1, 0, "Unsupported"),
+])
+def test_volume_bytes_errors(rt, dims, storage, brick, exc):
+    with pytest.raises(getattr(rt, exc)):
+        rt.rt_volume_bytes(dims, storage, brick)
+
+
+def test_tf_and_workspace_bytes(rt):
+    assert rt.rt_tf_bytes(4096) == 65536 and rt.rt_tf_bytes(2) == 256
+    for K in (1, 4097):
+        with pytest.raises(rt.InvalidArgument):
+            rt.rt_tf_bytes(K)
+    assert rt.rt_batch_workspace_bytes(1) < rt.rt_batch_workspace_bytes(128)
+    with pytest.raises(rt.InvalidArgument):
+        rt.rt_batch_workspace_bytes(0)
+
+
+def test_null_arguments_are_reported_not_fatal(rt):
+    L = rt.lib()
+    dims = (C.c_int64 * 3)(4, 4, 4)
+    assert L.rt_render(None, dims, None, None, None, 8, 8, 0.5, 0.99, None, None, None, None) == 1
+    assert b"NULL" in L.rt_last_error()
+    h = C.c_void_p()
+    sp = (C.c_double * 3)(1, 1, 1)
+    assert L.rt_create_volume(None, 1, dims, sp, 1, 0, None, 0, None, C.byref(h)) == 1
+    assert L.rt_render_batch(None, 0, None, 0, None, None, None) == 1
+    assert L.rt_batch_plan_launch(None, None, 0, None, None) == 1
+    assert L.rt_destroy_volume(None) == 0 and L.rt_destroy_tf(None) == 0 and L.rt_batch_plan_destroy(None) == 0
+    assert L.rt_status_string(2) == b"buffer too small"
+    assert L.rt_version().startswith(b"rtvol")
+
+
+def test_product_path_does_not_import_oracle():
+    """The product package never imports the oracle nor the generators."""
+    pkg = os.path.join(ROOT, "paper_1211_5595_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".cpp", ".hip", ".h")):
+                src = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in src and "from oracle" not in src and "oracle.h" not in src, f
+                assert "import workloads" not in src and "from workloads" not in src, f

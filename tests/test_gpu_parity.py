@@ -1,0 +1,333 @@
+"""GPU path (through the C ABI) against the FP64 oracle, element by element.
+
+Tolerance: max-abs RGBA error 1e-5 on the binary32 path.  Early ray
+termination is a threshold on accumulated opacity, so where the binary32 and
+binary64 opacities sit within 1e-6 of the cutoff either stopping point is
+correct: the oracle reports the per-channel range of all such outputs (its
+tie band) and a GPU value passes when it lies inside that range widened by
+the tolerance.  Sample counts must match exactly except on pixels the oracle
+flags as ties.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from workloads import Camera
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+DELTA = 1e-6
+
+
+@pytest.fixture(scope="module")
+def rt():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1211_5595_amd as rt
+    rt.lib()
+    return rt
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    import torch
+    return torch
+
+
+def gpu_render(rt, torch, vol, tf, cam, W_, H_, step, cutoff, bg=(0, 0, 0, 0), **kw):
+    counts = torch.zeros((H_, W_), dtype=torch.int32, device="cuda")
+    counter = torch.zeros(1, dtype=torch.int64, device="cuda")
+    img = rt.render(vol, tf, cam, W_, H_, step, cutoff, bg, pixel_counts=counts, sample_counter=counter, **kw)
+    torch.cuda.synchronize()
+    c = counts.cpu().numpy()
+    assert int(counter.item()) == int(c.astype(np.int64).sum())
+    return img.cpu().numpy().astype(np.float64), c
+
+
+def check(got, ref, counts=None, what=""):
+    """got: [..., 4] float64 GPU values; ref: oracle result with band."""
+    lo, hi = ref.band_lo, ref.band_hi
+    dist = np.maximum(np.maximum(lo - got, got - hi), 0.0)
+    worst = float(dist.max()) if dist.size else 0.0
+    tie = ref.tie != 0
+    plain = ~tie
+    err_plain = float(np.abs(got - ref.image)[plain].max()) if plain.any() else 0.0
+    assert worst <= TOL, f"{what}: max distance to the oracle's tie band {worst:.3g} (max abs err off ties {err_plain:.3g})"
+    assert err_plain <= TOL, f"{what}: max abs err {err_plain:.3g}"
+    if counts is not None:
+        et_tie = (ref.tie & 1) != 0
+        lat_tie = (ref.tie & 6) != 0
+        exact = ~(et_tie | lat_tie)
+        mism = (counts != ref.counts) & exact
+        assert not mism.any(), f"{what}: {mism.sum()} sample counts differ off ties"
+        assert (np.abs(counts - ref.counts)[lat_tie & ~et_tie] <= 1).all()
+    return worst, err_plain
+
+
+# ---------------------------------------------------------------------------
+# workloads
+# ---------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def small(rt, orc):
+    v = W.phantom_small(1)
+    t = W.random_tf(256, 2)
+    return dict(np=v, tf_np=t, gv=rt.Volume(v, (1, 1, 2), storage=rt.U8), gtf=rt.TransferFunction(t, 0, 255),
+                ov=orc.Volume(v, (1, 1, 2)), otf=orc.TF(t, 0, 255))
+
+
+@pytest.fixture(scope="module")
+def brain(rt, orc):
+    dims, sp = (256, 256, 160), (0.9, 0.9, 1.2)
+    v = W.phantom_brain(11)
+    t = W.random_tf(4096, 12, alpha_max=0.05)
+    return dict(np=v, tf_np=t, dims=dims, sp=sp, gv=rt.Volume(v, sp, storage=rt.U16),
+                gtf=rt.TransferFunction(t, 0, 4095), ov=orc.Volume(v, sp), otf=orc.TF(t, 0, 4095),
+                cams=W.orbit_cameras(dims, sp, 36))
+
+
+def test_small_ortho_full_image(rt, torch_mod, orc, small):
+    cam = W.ortho_camera_small()
+    got, c = gpu_render(rt, torch_mod, small["gv"], small["gtf"], cam, 128, 128, 0.5, 0.99)
+    ref = orc.render(small["ov"], small["otf"], cam, 128, 128, 0.5, 0.99, tie_delta=DELTA, want_band=True)
+    w, e = check(got, ref, c, "small ortho")
+    print(f"small ortho 128x128: max err {e:.3g}, band dist {w:.3g}, ties {(ref.tie & 1).sum()}")
+
+
+@pytest.mark.parametrize("view", [0, 9, 22, 31])
+def test_brain_views_full_image(rt, torch_mod, orc, brain, view):
+    cam = brain["cams"][view]
+    got, c = gpu_render(rt, torch_mod, brain["gv"], brain["gtf"], cam, 512, 512, 0.5, 0.99)
+    ref = orc.render(brain["ov"], brain["otf"], cam, 512, 512, 0.5, 0.99, tie_delta=DELTA, want_band=True)
+    w, e = check(got, ref, c, f"brain view {view}")
+    print(f"brain view {view} 512x512: max err {e:.3g}, band dist {w:.3g}, ties {(ref.tie & 1).sum()}, "
+          f"samples {c.sum()}")
+
+
+def test_brain_orbit_sampled(rt, torch_mod, orc, brain):
+    """All 36 orbit views at full size, 2048 pixels each checked one by one."""
+    rng = np.random.default_rng(77)
+    worst = 0.0
+    for vi, cam in enumerate(brain["cams"]):
+        got, c = gpu_render(rt, torch_mod, brain["gv"], brain["gtf"], cam, 512, 512, 0.5, 0.99)
+        px = rng.choice(512 * 512, size=2048, replace=False)
+        ref = orc.render(brain["ov"], brain["otf"], cam, 512, 512, 0.5, 0.99, pixels=px, tie_delta=DELTA,
+                         want_band=True)
+        w, _ = check(got.reshape(-1, 4)[px], ref, c.reshape(-1)[px], f"brain view {vi}")
+        worst = max(worst, w)
+    print(f"36 views sampled: worst band distance {worst:.3g}")
+
+
+# ---------------------------------------------------------------------------
+# ragged, degenerate and random cases
+# ---------------------------------------------------------------------------
+def _random_case(seed):
+    rng = np.random.default_rng(seed)
+    dims = tuple(int(x) for x in rng.integers(2, 40, size=3))
+    sp = tuple(float(x) for x in rng.uniform(0.3, 2.5, size=3))
+    v = rng.integers(0, 4096, size=dims[::-1]).astype(np.uint16)
+    if seed % 3 == 0:  # smooth content as well as noise
+        v = W.phantom_brain(seed, dims=dims, spacing=sp) if min(dims) > 4 else v
+    c = W.box_center(dims, sp)
+    R = W.bounding_radius(dims, sp)
+    kind = seed % 4
+    if kind == 0:      # perspective from outside
+        cam = W.random_camera(rng, dims, sp)
+    elif kind == 1:    # eye inside the volume
+        eye = c + rng.uniform(-0.3, 0.3, 3) * np.array([(n - 1) * s for n, s in zip(dims, sp)])
+        cam = Camera(tuple(eye), tuple(eye + rng.normal(size=3)), (0, 0, 1), True, float(rng.uniform(30, 120)))
+    elif kind == 2:    # orthographic, oblique
+        d = rng.normal(size=3)
+        d /= np.linalg.norm(d)
+        cam = Camera(tuple(c - 3 * R * d), tuple(c), (0, 1, 0) if abs(d[1]) < 0.9 else (1, 0, 0), False, 0.0,
+                     float(rng.uniform(0.5, 1.5) * R))
+    else:              # perspective, close and wide
+        cam = Camera(tuple(c + 1.3 * R * np.array([0.3, -1, 0.4])), tuple(c), (0, 0, 1), True, 100.0)
+    Wd, Hd = [(1, 1), (7, 13), (65, 33), (130, 67), (64, 64), (3, 200)][seed % 6]
+    step = float(rng.uniform(0.3, 1.7))
+    cutoff = [0.5, 0.99, 1.0][seed % 3]
+    tf = W.random_tf(4096, seed, alpha_max=float(rng.uniform(0.02, 0.6)))
+    bg = tuple(float(x) for x in rng.uniform(0, 1, 4)) if seed % 2 else (0, 0, 0, 0)
+    return v, dims, sp, cam, Wd, Hd, step, cutoff, tf, bg
+
+
+@pytest.mark.parametrize("seed", range(24))
+def test_random_small_cases(rt, torch_mod, orc, seed):
+    v, dims, sp, cam, Wd, Hd, step, cutoff, tf, bg = _random_case(seed)
+    gv = rt.Volume(v, sp, storage=rt.U16)
+    gtf = rt.TransferFunction(tf, 0, 4095)
+    got, c = gpu_render(rt, torch_mod, gv, gtf, cam, Wd, Hd, step, cutoff, bg)
+    ref = orc.render(orc.Volume(v, sp), orc.TF(tf, 0, 4095), cam, Wd, Hd, step, cutoff, bg=bg, tie_delta=DELTA,
+                     want_band=True)
+    check(got, ref, c, f"case {seed} dims {dims} {Wd}x{Hd}")
+
+
+def test_minimal_volume_and_axis_rays(rt, torch_mod, orc):
+    """2x2x2 volume; rays exactly parallel to the axes (zero direction
+    components) through a 4x4 orthographic image and a perspective one."""
+    v = np.array([[[0, 4095], [1000, 3000]], [[2000, 500], [4095, 100]]], dtype=np.uint16)
+    tf = W.random_tf(4096, 5, alpha_max=0.8)
+    gv, gtf = rt.Volume(v, (1, 1, 1), storage=rt.U16), rt.TransferFunction(tf, 0, 4095)
+    ov, otf = orc.Volume(v, (1, 1, 1)), orc.TF(tf, 0, 4095)
+    cams = [Camera((0.5, 0.5, -5), (0.5, 0.5, 0), (0, 1, 0), False, 0.0, 0.4),
+            Camera((0.5, 7, 0.5), (0.5, 0, 0.5), (0, 0, 1), False, 0.0, 0.45),
+            Camera((0.5, 0.5, 6), (0.5, 0.5, 0.5), (0, 1, 0), True, 20.0)]
+    for cam in cams:
+        for step in (0.25, 0.3, 1.0):
+            got, c = gpu_render(rt, torch_mod, gv, gtf, cam, 4, 4, step, 1.0)
+            ref = orc.render(ov, otf, cam, 4, 4, step, 1.0, tie_delta=DELTA, want_band=True)
+            check(got, ref, c, f"2x2x2 {cam} step {step}")
+
+
+def test_transparent_tf_gives_background_exactly(rt, torch_mod, small):
+    tf0 = rt.TransferFunction(np.zeros((256, 4), np.float32), 0, 255)
+    bg = (0.25, 0.5, 0.125, 0.75)
+    for cam in [W.ortho_camera_small()] + W.orbit_cameras((64, 64, 32), (1, 1, 2), 4):
+        got, _ = gpu_render(rt, torch_mod, small["gv"], tf0, cam, 70, 50, 0.5, 0.99, bg)
+        assert (got == np.array(bg, dtype=np.float32)).all()
+
+
+def test_tile_shapes_and_workgroups_bitwise(rt, torch_mod, brain):
+    cam = brain["cams"][5]
+    base, _ = gpu_render(rt, torch_mod, brain["gv"], brain["gtf"], cam, 300, 200, 0.5, 0.99)
+    for tile, waves in [((16, 4), 16), ((4, 16), 8), ((32, 2), 4), ((8, 8), 1), ((64, 1), 2)]:
+        got, _ = gpu_render(rt, torch_mod, brain["gv"], brain["gtf"], cam, 300, 200, 0.5, 0.99, tile=tile,
+                            waves_per_block=waves)
+        assert np.array_equal(got, base), (tile, waves)
+
+
+# ---------------------------------------------------------------------------
+# storage types: binary32, half, per-brick 8-bit
+# ---------------------------------------------------------------------------
+def test_f32_and_f16_storage(rt, torch_mod, orc, brain):
+    v = brain["np"]
+    cam = brain["cams"][3]
+    for storage, field in [(rt.F32, v.astype(np.float64)),
+                           (rt.F16, v.astype(np.float16).astype(np.float64))]:
+        gv = rt.Volume(v, brain["sp"], storage=storage)
+        got, c = gpu_render(rt, torch_mod, gv, brain["gtf"], cam, 256, 256, 0.5, 0.99)
+        ref = orc.render(orc.Volume(field, brain["sp"]), brain["otf"], cam, 256, 256, 0.5, 0.99,
+                         tie_delta=DELTA, want_band=True)
+        check(got, ref, c, f"storage {storage}")
+
+
+def test_f16_relayout_rounds_to_nearest_even(rt, torch_mod):
+    v = np.arange(0, 4096, dtype=np.uint16)[None, None, :].repeat(2, 0).repeat(2, 1)
+    gv = rt.Volume(v, (1, 1, 1), storage=rt.F16)
+    torch_mod.cuda.synchronize()
+    raw = gv.buf[: (4098 * 4 * 4) * 2].view(torch_mod.float16).cpu().numpy().reshape(4, 4, 4098)
+    want = v[0, 0].astype(np.float16)
+    assert np.array_equal(raw[1, 1, 1:-1].view(np.uint16), want.view(np.uint16))
+    assert raw[1, 1, 0] == want[0] and raw[1, 1, -1] == want[-1]   # replicated border
+
+
+@pytest.mark.parametrize("B", [8, 16])
+def test_u8_brick_codes_bit_exact(rt, torch_mod, orc, B):
+    v = W.phantom_brain(11, dims=(70, 45, 33))
+    dims = (70, 45, 33)
+    gv = rt.Volume(v, (0.9, 0.9, 1.2), storage=rt.U8_BRICKSCALED, brick=B)
+    torch_mod.cuda.synchronize()
+    lo, sc, codes = orc.encode_u8_bricks(v, B)
+    total, nb = orc.u8_brick_count(dims, B)
+    raw = gv.buf.cpu().numpy()
+    par = raw[: total * 8].view(np.float32).reshape(total, 2)
+    assert np.array_equal(par[:, 0].view(np.uint32), lo.view(np.uint32))
+    assert np.array_equal(par[:, 1].view(np.uint32), sc.view(np.uint32))
+    off = ((total * 8 + 255) // 256) * 256
+    S = B + 3
+    dev = raw[off: off + total * S ** 3].reshape(total, S, S, S)
+    ref = codes.reshape(total, B + 1, B + 1, B + 1)
+    for bid in range(total):
+        bx, by, bz = bid % nb[0], (bid // nb[0]) % nb[1], bid // (nb[0] * nb[1])
+        ex = min(B, dims[0] - 1 - bx * B) + 1
+        ey = min(B, dims[1] - 1 - by * B) + 1
+        ez = min(B, dims[2] - 1 - bz * B) + 1
+        assert np.array_equal(dev[bid, 1:1 + ez, 1:1 + ey, 1:1 + ex], ref[bid, :ez, :ey, :ex]), bid
+
+
+def test_u8_brick_storage_render(rt, torch_mod, orc, brain):
+    v = brain["np"]
+    cam = brain["cams"][7]
+    gv = rt.Volume(v, brain["sp"], storage=rt.U8_BRICKSCALED, brick=16)
+    got, c = gpu_render(rt, torch_mod, gv, brain["gtf"], cam, 256, 256, 0.5, 0.99)
+    ref = orc.render(orc.Volume.from_u8_bricks(v, brain["sp"], 16), brain["otf"], cam, 256, 256, 0.5, 0.99,
+                     tie_delta=DELTA, want_band=True)
+    check(got, ref, c, "u8 bricks")
+
+
+# ---------------------------------------------------------------------------
+# batching: bitwise identical to the plain per-view launch
+# ---------------------------------------------------------------------------
+def test_batch_and_plan_bitwise_equal_plain(rt, torch_mod, small, brain):
+    torch = torch_mod
+    v2 = W.phantom_brain(3, dims=(96, 80, 64))
+    gv2 = rt.Volume(v2, (0.9, 0.9, 1.2), storage=rt.U16)
+    tf2 = rt.TransferFunction(W.random_tf(1024, 9, alpha_max=0.2), 0, 4095)
+    rng = np.random.default_rng(3)
+    specs = []
+    for k in range(7):
+        if k % 2:
+            specs.append((brain["gv"], brain["gtf"], brain["cams"][k * 5], 200 + 17 * k, 150 + 9 * k))
+        else:
+            specs.append((gv2, tf2, W.random_camera(rng, (96, 80, 64), (0.9, 0.9, 1.2)), 64 + 40 * k, 97))
+    plain = []
+    for vol, tf, cam, Wd, Hd in specs:
+        img, _ = gpu_render(rt, torch, vol, tf, cam, Wd, Hd, 0.5, 0.99)
+        plain.append(img)
+    jobs = [rt.Job(vol, tf, cam, Wd, Hd, 0.5, 0.99) for vol, tf, cam, Wd, Hd in specs]
+    counter = torch.zeros(1, dtype=torch.int64, device="cuda")
+    outs = rt.render_batch(jobs, sample_counter=counter)
+    torch.cuda.synchronize()
+    for a, b in zip(plain, outs):
+        assert np.array_equal(a, b.cpu().numpy().astype(np.float64))
+    n1 = int(counter.item())
+    plan = rt.BatchPlan(16, rt.U16)
+    for rep in range(3):  # replays with eager work in between
+        for j in jobs:
+            j.out.zero_()
+        sub = jobs if rep != 1 else jobs[2:5]
+        c2 = torch.zeros(1, dtype=torch.int64, device="cuda")
+        plan.launch(sub, sample_counter=c2)
+        torch.cuda.synchronize()
+        ref = plain if rep != 1 else plain[2:5]
+        for a, j in zip(ref, sub):
+            assert np.array_equal(a, j.out.cpu().numpy().astype(np.float64)), rep
+        if rep != 1:
+            assert int(c2.item()) == n1
+
+
+# ---------------------------------------------------------------------------
+# error paths that need live handles
+# ---------------------------------------------------------------------------
+def test_abi_errors_with_handles(rt, torch_mod, small):
+    gv, gtf = small["gv"], small["gtf"]
+    out = torch_mod.empty((8, 8, 4), dtype=torch_mod.float32, device="cuda")
+    good = W.ortho_camera_small()
+    bad = [Camera((1, 2, 3), (1, 2, 3), (0, 1, 0), True, 40.0),
+           Camera((0, 0, 5), (0, 0, 0), (0, 0, 1), True, 40.0),
+           Camera((0, 0, 5), (0, 0, 0), (0, 1, 0), True, 180.0),
+           Camera((0, 0, 5), (0, 0, 0), (0, 1, 0), False, 0.0, 0.0),
+           Camera((0, 0, float("nan")), (0, 0, 0), (0, 1, 0), True, 40.0)]
+    for cam in bad:
+        with pytest.raises(rt.InvalidArgument):
+            rt.rt_render(gv.handle, gv.dims, None, gtf.handle, cam, 8, 8, 0.5, 0.99, None, out.data_ptr())
+    for W_, H_, step, cut in [(0, 8, 0.5, 0.99), (8, 8, 0.0, 0.99), (8, 8, 0.5, 0.0), (8, 8, 0.5, 1.5),
+                              (8, 8, float("inf"), 0.9)]:
+        with pytest.raises(rt.InvalidArgument):
+            rt.rt_render(gv.handle, gv.dims, None, gtf.handle, good, W_, H_, step, cut, None, out.data_ptr())
+    with pytest.raises(rt.InvalidArgument):
+        rt.rt_render(gv.handle, (64, 64, 31), None, gtf.handle, good, 8, 8, 0.5, 0.99, None, out.data_ptr())
+    with pytest.raises(rt.OutOfMemory):
+        buf = torch_mod.empty(100, dtype=torch_mod.uint8, device="cuda")
+        src = torch_mod.zeros((4, 4, 4), dtype=torch_mod.uint8, device="cuda")
+        rt.rt_create_volume(src.data_ptr(), rt.U8, (4, 4, 4), (1, 1, 1), rt.U8, 0, buf.data_ptr(), 100)
+    with pytest.raises(rt.InvalidArgument):
+        rt.TransferFunction(np.full((16, 4), 1.5, np.float32), 0, 1)
+    with pytest.raises(rt.InvalidArgument):
+        rt.TransferFunction(np.zeros((16, 4), np.float32), 1, 1)
+    with pytest.raises(rt.Unsupported):
+        rt.rt_render(gv.handle, gv.dims, None, gtf.handle, good, 8, 8, 0.5, 0.99, None, out.data_ptr(),
+                     rt.make_opts(tile=(5, 13)))
