@@ -87,17 +87,15 @@ __device__ __forceinline__ int ff_floor_int(ff a) {
     return m;
 }
 
-// Signed 32.32 fixed point of a float-float value (|a| < 2^23): returns
-// floor(a * 2^32) up to one unit.  The integer part is floor(hi); the
-// fraction hi - floor(hi) is exact in binary32 and scales to an exact
-// integer below 2^32; lo adds a small correction.
+// Signed 32.32 fixed point of a float-float value (|a| < 2^30): returns
+// round(a * 2^32) within one unit.  hi * 2^32 and lo * 2^32 are exact
+// power-of-two scalings; each is an integer-valued binary32 number (or is
+// rounded to one) and converts to int64 exactly.  Subtracting floor(hi)
+// from hi instead would drop a bit whenever -1 < hi < 0.
 __device__ __forceinline__ long long ff_to_fixed32(ff a) {
-    float fh = floorf(a.hi);
-    float fr = a.hi - fh;
-    unsigned int F = (unsigned int)rintf(fr * 4294967296.0f);
-    long long X = ((long long)(int)fh << 32) + (long long)F;
-    X += (long long)(int)rintf(a.lo * 4294967296.0f);
-    return X;
+    const long long H = (long long)rintf(a.hi * 4294967296.0f);
+    const long long L = (long long)rintf(a.lo * 4294967296.0f);
+    return H + L;
 }
 
 }  // namespace rtv
