@@ -72,6 +72,13 @@ typedef enum {
     RT_U8_BRICKSCALED = 4   /* storage only: 8-bit codes with a (lo, scale) per brick of B^3 cells */
 } rt_dtype;
 
+/* Device layouts of RT_U8/RT_U16/RT_F16/RT_F32 volumes (the `brick`
+ * argument of rt_volume_bytes / rt_create_volume for those types). */
+typedef enum {
+    RT_LAYOUT_CELLS = 0,  /* default: each cell's 8 corners contiguous, cells in 2x2x2 blocks (8x the grid) */
+    RT_LAYOUT_LINEAR = 1  /* the grid in C order with a one-node replicated border (1x the grid) */
+} rt_layout;
+
 /* Ray functions (Section 4.1 list; Section 2.4 for maximum intensity and
  * X-ray projection). */
 typedef enum {
@@ -117,17 +124,20 @@ typedef struct {
  * ------------------------------------------------------------------------- */
 
 /* Device bytes needed to hold a volume of `dims` in `storage` layout.  brick
- * is the brick edge B in cells (8, 16 or 32) for RT_U8_BRICKSCALED and must
- * be 0 for the other types.  Errors: RT_ERR_INVALID_ARG (bad dims/brick,
- * NULL), RT_ERR_UNSUPPORTED (volume too large for 32-bit addressing). */
+ * is the brick edge B in cells (8, 16 or 32) for RT_U8_BRICKSCALED and the
+ * rt_layout for the other types.  Errors: RT_ERR_INVALID_ARG (bad dims,
+ * brick or layout, NULL), RT_ERR_UNSUPPORTED (volume too large for 32-bit
+ * addressing: 4 GiB of storage). */
 rt_status rt_volume_bytes(const int64_t dims[3], int storage, int brick, size_t* bytes);
 
 /* Convert a device-resident source array (C-order [z][y][x] of src_dtype,
  * one of RT_U8/RT_U16/RT_F16/RT_F32) into the raycaster's storage layout in
  * the caller's device buffer dev_buf (>= rt_volume_bytes bytes), on `stream`.
- * The layout adds a one-node replicated border on every face (bricked with
- * per-brick scale and halo for RT_U8_BRICKSCALED: lo = brick minimum, scale =
- * (max-lo)/255, code = rint((v-lo)/scale), all binary32).  The source may be
+ * Every layout adds a one-node replicated border on every face;
+ * RT_LAYOUT_CELLS stores each cell's 8 corners contiguously, RT_LAYOUT_LINEAR
+ * the bordered grid, and RT_U8_BRICKSCALED per brick of brick^3 cells a
+ * (lo, scale) and 8-bit codes with a halo: lo = brick minimum, scale =
+ * (max-lo)/255, code = rint((v-lo)/scale), all binary32.  The source may be
  * freed once the stream has passed this call.  *out receives the handle.
  * Errors: RT_ERR_INVALID_ARG (NULL, dims < 2, non-finite or non-positive
  * spacing, storage/src combination such as F32 -> U8), RT_ERR_OUT_OF_MEMORY
@@ -188,23 +198,23 @@ typedef struct {
 rt_status rt_batch_workspace_bytes(int max_jobs, size_t* bytes);
 
 /* Render n views (of possibly different volumes, transfer functions and
- * sizes; all volumes of one storage type) in one persistent launch that pulls
+ * sizes; all volumes of one storage type and layout) in one persistent launch that pulls
  * ray tiles from a device work queue.  Copies the job table into `workspace`
  * (>= rt_batch_workspace_bytes(n)) on `stream`; the job array may be reused
  * once the call returns.  Results are bitwise identical to rt_render of each
  * view.  Errors: as rt_render, plus RT_ERR_OUT_OF_MEMORY (workspace too
- * small) and RT_ERR_UNSUPPORTED (mixed storage types). */
+ * small) and RT_ERR_UNSUPPORTED (mixed storage types or layouts). */
 rt_status rt_render_batch(const rt_render_job* jobs, int n, void* workspace, size_t ws_bytes,
                           unsigned long long* sample_counter, const rt_render_opts* opts, void* stream);
 
 /* A batch plan: the persistent launch captured once into a HIP graph over a
  * fixed workspace, replayed for every batch of up to max_jobs views of one
- * storage type.  rt_batch_plan_launch copies the job table into the
+ * storage type and layout (layout ignored for RT_U8_BRICKSCALED).  rt_batch_plan_launch copies the job table into the
  * workspace (plain stream copy, outside the graph) and launches the graph on
  * `stream`.  The plan keeps a pinned host staging buffer and waits for the
  * previous launch's copy before reusing it.  Calls on one plan must not run
  * concurrently. */
-rt_status rt_batch_plan_create(int max_jobs, int storage, void* workspace, size_t ws_bytes,
+rt_status rt_batch_plan_create(int max_jobs, int storage, int layout, void* workspace, size_t ws_bytes,
                                const rt_render_opts* opts, rt_batch_plan** out);
 rt_status rt_batch_plan_launch(rt_batch_plan* plan, const rt_render_job* jobs, int n,
                                unsigned long long* sample_counter, void* stream);

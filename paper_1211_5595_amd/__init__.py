@@ -31,6 +31,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "librtvol.so")
 
 U8, U16, F16, F32, U8_BRICKSCALED = 0, 1, 2, 3, 4
+LAYOUT_CELLS, LAYOUT_LINEAR = 0, 1
 COMPOSITE, MIP, XRAY, AVERAGE, ISO, THRESHOLD = range(6)
 _DTYPE_CODE = {np.dtype(np.uint8): U8, np.dtype(np.uint16): U16, np.dtype(np.float16): F16,
                np.dtype(np.float32): F32}
@@ -103,7 +104,8 @@ def lib():
             "rt_batch_workspace_bytes": [C.c_int, szp],
             "rt_render_batch": [C.POINTER(rt_render_job), C.c_int, vp, C.c_size_t, vp, C.POINTER(rt_render_opts),
                                 vp],
-            "rt_batch_plan_create": [C.c_int, C.c_int, vp, C.c_size_t, C.POINTER(rt_render_opts), C.POINTER(vp)],
+            "rt_batch_plan_create": [C.c_int, C.c_int, C.c_int, vp, C.c_size_t, C.POINTER(rt_render_opts),
+                                     C.POINTER(vp)],
             "rt_batch_plan_launch": [vp, C.POINTER(rt_render_job), C.c_int, vp, vp],
             "rt_batch_plan_destroy": [vp],
         }
@@ -236,10 +238,10 @@ def rt_render_batch(jobs, ws_ptr: int, ws_bytes: int, counter_ptr: Optional[int]
                                  C.byref(opts) if opts is not None else None, _stream_ptr(stream)), "rt_render_batch")
 
 
-def rt_batch_plan_create(max_jobs: int, storage: int, ws_ptr: int, ws_bytes: int,
+def rt_batch_plan_create(max_jobs: int, storage: int, layout: int, ws_ptr: int, ws_bytes: int,
                          opts: Optional[rt_render_opts] = None) -> int:
     h = C.c_void_p()
-    _check(lib().rt_batch_plan_create(int(max_jobs), int(storage), C.c_void_p(ws_ptr), int(ws_bytes),
+    _check(lib().rt_batch_plan_create(int(max_jobs), int(storage), int(layout), C.c_void_p(ws_ptr), int(ws_bytes),
                                       C.byref(opts) if opts is not None else None, C.byref(h)), "rt_batch_plan_create")
     return h.value
 
@@ -261,11 +263,12 @@ class Volume:
     """A volume resident in device memory in the raycaster's storage layout.
 
     ``values``: numpy array or CUDA tensor, C-order [z][y][x] of uint8,
-    uint16, float16 or float32.  ``storage``: one of U8, U16, F16, F32,
-    U8_BRICKSCALED (with ``brick`` 8/16/32)."""
+    uint16, float16 or float32.  ``storage``: one of U8, U16, F16, F32
+    (with ``layout`` LAYOUT_CELLS or LAYOUT_LINEAR) or U8_BRICKSCALED (with
+    ``brick`` 8/16/32)."""
 
     def __init__(self, values, spacing: Sequence[float], storage: Optional[int] = None, brick: int = 0,
-                 stream=None, device="cuda"):
+                 stream=None, device="cuda", layout: int = LAYOUT_CELLS):
         torch = _torch()
         if isinstance(values, np.ndarray):
             arr = np.ascontiguousarray(values)
@@ -286,7 +289,8 @@ class Volume:
         self.dims = (nx, ny, nz)
         self.spacing = tuple(float(s) for s in spacing)
         self.storage = src_dtype if storage is None else int(storage)
-        self.brick = int(brick)
+        self.brick = int(brick) if self.storage == U8_BRICKSCALED else int(layout)
+        self.layout = None if self.storage == U8_BRICKSCALED else int(layout)
         self.nbytes = rt_volume_bytes(self.dims, self.storage, self.brick)
         self.buf = torch.empty(self.nbytes, dtype=torch.uint8, device=src.device)
         self.handle = rt_create_volume(src.data_ptr(), src_dtype, self.dims, self.spacing, self.storage, self.brick,
@@ -409,9 +413,10 @@ def render_batch(jobs: Sequence[Job], sample_counter=None, workspace=None, tile=
 class BatchPlan:
     """The persistent batched launch captured once in a HIP graph."""
 
-    def __init__(self, max_jobs: int, storage: int, tile=(0, 0), waves_per_block=0, device="cuda"):
+    def __init__(self, max_jobs: int, storage: int, tile=(0, 0), waves_per_block=0, device="cuda",
+                 layout: int = LAYOUT_CELLS):
         self.ws = _Workspace(max_jobs, device)
-        self.handle = rt_batch_plan_create(max_jobs, storage, self.ws.buf.data_ptr(), self.ws.nbytes,
+        self.handle = rt_batch_plan_create(max_jobs, storage, layout, self.ws.buf.data_ptr(), self.ws.nbytes,
                                            make_opts(tile=tile, waves_per_block=waves_per_block))
 
     def launch(self, jobs: Sequence[Job], sample_counter=None, stream=None):

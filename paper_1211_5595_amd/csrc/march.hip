@@ -126,6 +126,17 @@ __device__ __forceinline__ bool setup_ray(const ViewDesc& V, int i, int j, Ray& 
 
 __device__ __forceinline__ float lerp(float a, float b, float t) { return fmaf(t, b - a, a); }
 
+__device__ __forceinline__ uint32_t hiword(long long Q) { return (uint32_t)((unsigned long long)Q >> 32); }
+__device__ __forceinline__ float frac32(long long Q) { return (float)(uint32_t)Q * 0x1p-32f; }
+
+// Trilinear blend of the 8 corners c[dz*4+dy*2+dx] (Section 3.2): along x,
+// then y, then z.
+__device__ __forceinline__ float trilinear8(const float c[8], float fx, float fy, float fz) {
+    const float x00 = lerp(c[0], c[1], fx), x10 = lerp(c[2], c[3], fx);
+    const float x01 = lerp(c[4], c[5], fx), x11 = lerp(c[6], c[7], fx);
+    return lerp(lerp(x00, x10, fy), lerp(x01, x11, fy), fz);
+}
+
 template <int KIND>
 struct Elem;
 template <>
@@ -160,7 +171,7 @@ struct Elem<ST_F32> {
     }
 };
 
-// Wave-uniform corner offsets of a cell, in bytes.
+// Wave-uniform corner offsets of a cell in the linear and brick layouts, in bytes.
 struct Corners {
     int c1, c2, c3, c4, c5, c6, c7;
 };
@@ -169,47 +180,167 @@ __device__ __forceinline__ Corners corners_of(uint32_t e, uint32_t sy, uint32_t 
     return Corners{(int)e, (int)sy, (int)(sy + e), (int)sz, (int)(sz + e), (int)(sz + sy), (int)(sz + sy + e)};
 }
 
-// Trilinear blend of the 8 corners at base offset `off` (Section 3.2).
-template <int KIND>
-__device__ __forceinline__ float trilinear(__amdgpu_buffer_rsrc_t r, uint32_t off, const Corners& c, float fx,
-                                           float fy, float fz) {
-    using E = Elem<KIND>;
-    const float v000 = E::load(r, off, 0), v100 = E::load(r, off, c.c1);
-    const float v010 = E::load(r, off, c.c2), v110 = E::load(r, off, c.c3);
-    const float v001 = E::load(r, off, c.c4), v101 = E::load(r, off, c.c5);
-    const float v011 = E::load(r, off, c.c6), v111 = E::load(r, off, c.c7);
-    const float x00 = lerp(v000, v100, fx), x10 = lerp(v010, v110, fx);
-    const float x01 = lerp(v001, v101, fx), x11 = lerp(v011, v111, fx);
-    return lerp(lerp(x00, x10, fy), lerp(x01, x11, fy), fz);
-}
+// Step 2 of the ray-casting process, split in two so the next sample's
+// memory request can be issued before the current sample is processed:
+// load() fetches what the sample's cell needs, value() interpolates.
+template <int KIND, int LAYOUT>
+struct Sampler;
 
-__device__ __forceinline__ float frac32(long long Q) { return (float)(uint32_t)Q * 0x1p-32f; }
-
-// Step 2 of the ray-casting process: the value at a sample.
+// Linear padded grid: 8 scalar gathers at wave-uniform corner offsets.
 template <int KIND>
-__device__ __forceinline__ float sample_value(const VolDev& vol, __amdgpu_buffer_rsrc_t rs, const Corners& cn,
-                                              const long long Q[3]) {
-    const uint32_t ix = (uint32_t)(Q[0] >> 32), iy = (uint32_t)(Q[1] >> 32), iz = (uint32_t)(Q[2] >> 32);
-    const float fx = frac32(Q[0]), fy = frac32(Q[1]), fz = frac32(Q[2]);
-    if constexpr (KIND != ST_U8B) {
-        const uint32_t off = __umul24(iz, vol.sz) + __umul24(iy, vol.sy) + ix * Elem<KIND>::bytes;
-        return trilinear<KIND>(rs, off, cn, fx, fy, fz);
-    } else {
-        // The brick that owns the (clamped) cell; local padded node = padded node - b*B.
+struct Sampler<KIND, LAYOUT_LINEAR> {
+    struct Raw {
+        float c[8];
+    };
+    static __device__ __forceinline__ Raw load(__amdgpu_buffer_rsrc_t r, const VolDev& vol, const Corners& cn,
+                                               const long long Q[3]) {
+        using E = Elem<KIND>;
+        const uint32_t off = __umul24(hiword(Q[2]), vol.sz) + __umul24(hiword(Q[1]), vol.sy) + hiword(Q[0]) * E::bytes;
+        Raw w;
+        w.c[0] = E::load(r, off, 0);
+        w.c[1] = E::load(r, off, cn.c1);
+        w.c[2] = E::load(r, off, cn.c2);
+        w.c[3] = E::load(r, off, cn.c3);
+        w.c[4] = E::load(r, off, cn.c4);
+        w.c[5] = E::load(r, off, cn.c5);
+        w.c[6] = E::load(r, off, cn.c6);
+        w.c[7] = E::load(r, off, cn.c7);
+        return w;
+    }
+    static __device__ __forceinline__ float value(const Raw& w, float fx, float fy, float fz) {
+        return trilinear8(w.c, fx, fy, fz);
+    }
+};
+
+// Cell-packed grid: one 8/16/32-byte vector load per sample.
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+template <int KIND>
+struct CellBits;
+template <>
+struct CellBits<ST_U8> {
+    static constexpr int shift = 3;
+    using Raw = u32x2;
+    static __device__ __forceinline__ Raw load(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+        return __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+    }
+    static __device__ __forceinline__ void unpack(const Raw& w, float c[8]) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) c[k] = (float)((w[k >> 2] >> (8 * (k & 3))) & 0xffu);
+    }
+};
+template <>
+struct CellBits<ST_U16> {
+    static constexpr int shift = 4;
+    using Raw = u32x4;
+    static __device__ __forceinline__ Raw load(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+        return __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+    }
+    static __device__ __forceinline__ void unpack(const Raw& w, float c[8]) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            c[2 * k] = (float)(w[k] & 0xffffu);
+            c[2 * k + 1] = (float)(w[k] >> 16);
+        }
+    }
+};
+template <>
+struct CellBits<ST_F16> {
+    static constexpr int shift = 4;
+    using Raw = u32x4;
+    static __device__ __forceinline__ Raw load(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+        return __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+    }
+    static __device__ __forceinline__ void unpack(const Raw& w, float c[8]) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            c[2 * k] = (float)__builtin_bit_cast(_Float16, (unsigned short)(w[k] & 0xffffu));
+            c[2 * k + 1] = (float)__builtin_bit_cast(_Float16, (unsigned short)(w[k] >> 16));
+        }
+    }
+};
+template <>
+struct CellBits<ST_F32> {
+    static constexpr int shift = 5;
+    struct Raw {
+        u32x4 a;
+        u32x4 b;
+    };
+    static __device__ __forceinline__ Raw load(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+        Raw w;
+        w.a = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+        w.b = __builtin_amdgcn_raw_buffer_load_b128(r, off, 16, 0);
+        return w;
+    }
+    static __device__ __forceinline__ void unpack(const Raw& w, float c[8]) {
+        // whole-vector casts: a bit cast of a single vector element lvalue
+        // reads element 0 with this compiler
+        const f32x4 fa = __builtin_bit_cast(f32x4, w.a), fb = __builtin_bit_cast(f32x4, w.b);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            c[k] = fa[k];
+            c[4 + k] = fb[k];
+        }
+    }
+};
+
+template <int KIND>
+struct Sampler<KIND, LAYOUT_CELLS> {
+    using B = CellBits<KIND>;
+    using Raw = typename B::Raw;
+    static __device__ __forceinline__ Raw load(__amdgpu_buffer_rsrc_t r, const VolDev& vol, const Corners&,
+                                               const long long Q[3]) {
+        const uint32_t ix = hiword(Q[0]), iy = hiword(Q[1]), iz = hiword(Q[2]);
+        const uint32_t blk = __umul24(__umul24(iz >> 1, (uint32_t)vol.nb[1]) + (iy >> 1), (uint32_t)vol.nb[0]) + (ix >> 1);
+        const uint32_t w = (ix & 1u) | ((iy & 1u) << 1) | ((iz & 1u) << 2);
+        return B::load(r, (blk << (B::shift + 3)) | (w << B::shift));
+    }
+    static __device__ __forceinline__ float value(const Raw& w, float fx, float fy, float fz) {
+        float c[8];
+        B::unpack(w, c);
+        return trilinear8(c, fx, fy, fz);
+    }
+};
+
+// Brick-scaled 8-bit codes: the brick owning the (clamped) cell supplies all
+// 8 corners and the (lo, scale) that decodes their blend.
+template <>
+struct Sampler<ST_U8B, LAYOUT_BRICKS> {
+    struct Raw {
+        float c[8];
+        float2 par;
+    };
+    static __device__ __forceinline__ Raw load(__amdgpu_buffer_rsrc_t r, const VolDev& vol, const Corners& cn,
+                                               const long long Q[3]) {
+        const uint32_t ix = hiword(Q[0]), iy = hiword(Q[1]), iz = hiword(Q[2]);
         const int cx = min(max((int)ix - 1, 0), vol.n[0] - 2) >> vol.bshift;
         const int cy = min(max((int)iy - 1, 0), vol.n[1] - 2) >> vol.bshift;
         const int cz = min(max((int)iz - 1, 0), vol.n[2] - 2) >> vol.bshift;
         const uint32_t lx = ix - ((uint32_t)cx << vol.bshift);
         const uint32_t ly = iy - ((uint32_t)cy << vol.bshift);
         const uint32_t lz = iz - ((uint32_t)cz << vol.bshift);
-        const uint32_t bid = __umul24(__umul24((uint32_t)cz, (uint32_t)vol.nb[1]) + (uint32_t)cy, (uint32_t)vol.nb[0]) +
-                             (uint32_t)cx;
+        const uint32_t bid =
+            __umul24(__umul24((uint32_t)cz, (uint32_t)vol.nb[1]) + (uint32_t)cy, (uint32_t)vol.nb[0]) + (uint32_t)cx;
         const uint32_t off = __umul24(bid, vol.brick_bytes) + __umul24(lz, vol.sz) + __umul24(ly, vol.sy) + lx;
-        const float t = trilinear<KIND>(rs, off, cn, fx, fy, fz);
-        const float2 par = vol.brick_par[bid];
-        return fmaf(par.y, t, par.x);
+        using E = Elem<ST_U8>;
+        Raw w;
+        w.c[0] = E::load(r, off, 0);
+        w.c[1] = E::load(r, off, cn.c1);
+        w.c[2] = E::load(r, off, cn.c2);
+        w.c[3] = E::load(r, off, cn.c3);
+        w.c[4] = E::load(r, off, cn.c4);
+        w.c[5] = E::load(r, off, cn.c5);
+        w.c[6] = E::load(r, off, cn.c6);
+        w.c[7] = E::load(r, off, cn.c7);
+        w.par = vol.brick_par[bid];
+        return w;
     }
-}
+    static __device__ __forceinline__ float value(const Raw& w, float fx, float fy, float fz) {
+        return fmaf(w.par.y, trilinear8(w.c, fx, fy, fz), w.par.x);
+    }
+};
 
 // Classification: post-classified RGBA by linear interpolation between
 // table entries (entry K duplicates entry K-1 so x = K-1 needs no clamp).
@@ -222,11 +353,13 @@ __device__ __forceinline__ float4 classify(const float4* __restrict__ s_tf, floa
     return make_float4(lerp(t0.x, t1.x, g), lerp(t0.y, t1.y, g), lerp(t0.z, t1.z, g), lerp(t0.w, t1.w, g));
 }
 
-// Step 3: compositing one pixel's ray.
-template <int KIND>
+// Step 3: compositing one pixel's ray.  The cell of sample k+1 is requested
+// before sample k is interpolated, classified and composited.
+template <int KIND, int LAYOUT>
 __device__ __forceinline__ void march_pixel(const ViewDesc& V, const float4* __restrict__ s_tf,
                                             __amdgpu_buffer_rsrc_t rs, const Corners& cn, int i, int j,
                                             float4& px, int& count) {
+    using S = Sampler<KIND, LAYOUT>;
     Ray R;
     float Cr = 0.0f, Cg = 0.0f, Cb = 0.0f, T = 1.0f;
     int k = 0;
@@ -234,8 +367,11 @@ __device__ __forceinline__ void march_pixel(const ViewDesc& V, const float4* __r
         const float Km1 = (float)(V.K - 1);
         const float ta = V.tf_a, tb = V.tf_b, thr = V.thr;
         if (R.m > 0) {
+            typename S::Raw cur = S::load(rs, V.vol, cn, R.Q);
             for (;;) {
-                const float val = sample_value<KIND>(V.vol, rs, cn, R.Q);
+                const long long Qn[3] = {R.Q[0] + R.dQ[0], R.Q[1] + R.dQ[1], R.Q[2] + R.dQ[2]};
+                const typename S::Raw nxt = S::load(rs, V.vol, cn, Qn);
+                const float val = S::value(cur, frac32(R.Q[0]), frac32(R.Q[1]), frac32(R.Q[2]));
                 const float4 c = classify(s_tf, val, ta, tb, Km1);
                 const float Ta = T * c.w;
                 Cr = fmaf(Ta, c.x, Cr);
@@ -244,13 +380,15 @@ __device__ __forceinline__ void march_pixel(const ViewDesc& V, const float4* __r
                 T = fmaf(-T, c.w, T);
                 ++k;
                 if (k >= R.m || T <= thr) break;
-                R.Q[0] += R.dQ[0];
-                R.Q[1] += R.dQ[1];
-                R.Q[2] += R.dQ[2];
+                cur = nxt;
+                R.Q[0] = Qn[0];
+                R.Q[1] = Qn[1];
+                R.Q[2] = Qn[2];
             }
         }
         if (R.wp > 0.0f && T > thr) {
-            const float val = sample_value<KIND>(V.vol, rs, cn, R.Qp);
+            const typename S::Raw w = S::load(rs, V.vol, cn, R.Qp);
+            const float val = S::value(w, frac32(R.Qp[0]), frac32(R.Qp[1]), frac32(R.Qp[2]));
             const float4 c = classify(s_tf, val, ta, tb, Km1);
             const float a = 1.0f - exp2f(R.wp * log2f(1.0f - c.w));
             const float Ta = T * a;
@@ -277,7 +415,7 @@ __device__ __forceinline__ void load_tf(float4* s_tf, const float4* __restrict__
 }
 
 // One workgroup block of a view: wave w renders tile (w % bw, w / bw) of the block.
-template <int KIND>
+template <int KIND, int LAYOUT>
 __device__ __forceinline__ void render_block(const ViewDesc& V, const float4* __restrict__ s_tf, int blk,
                                              const LaunchShape& ls, int tw_shift,
                                              unsigned long long* __restrict__ counter) {
@@ -287,11 +425,11 @@ __device__ __forceinline__ void render_block(const ViewDesc& V, const float4* __
     if (tx >= V.tiles_x || ty >= V.tiles_y) return;
     const int i = tx * ls.tile_w + (lane & (ls.tile_w - 1)), j = ty * ls.tile_h + (lane >> tw_shift);
     const __amdgpu_buffer_rsrc_t rs = make_rsrc(V.vol.data, V.vol.data_bytes);
-    const Corners cn = corners_of(Elem<KIND>::bytes, V.vol.sy, V.vol.sz);
+    const Corners cn = corners_of(LAYOUT == LAYOUT_BRICKS ? 1u : Elem<KIND>::bytes, V.vol.sy, V.vol.sz);
     int count = 0;
     if (i < V.W && j < V.H) {
         float4 px;
-        march_pixel<KIND>(V, s_tf, rs, cn, i, j, px, count);
+        march_pixel<KIND, LAYOUT>(V, s_tf, rs, cn, i, j, px, count);
         const size_t p = (size_t)j * V.W + i;
         reinterpret_cast<float4*>(V.out)[p] = px;
         if (V.counts) V.counts[p] = count;
@@ -310,22 +448,26 @@ __device__ __forceinline__ int xcd_remap(int b, int n) {
     return x * per + min(x, rem) + idx;
 }
 
-template <int KIND>
-__global__ void __launch_bounds__(1024) march_plain_kernel(const ViewDesc V, const LaunchShape ls, int tw_shift,
-                                                            unsigned long long* __restrict__ counter) {
+// Occupancy: at least 8 waves per SIMD (two 1024-lane workgroups per CU),
+// which caps the marcher at 64 VGPRs.
+#define RT_MARCH_ATTRS __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8)))
+
+template <int KIND, int LAYOUT>
+__global__ void RT_MARCH_ATTRS march_plain_kernel(const ViewDesc V, const LaunchShape ls, int tw_shift,
+                                                   unsigned long long* __restrict__ counter) {
     extern __shared__ float4 s_tf[];
     load_tf(s_tf, V.tf, V.K);
     __syncthreads();
-    render_block<KIND>(V, s_tf, xcd_remap(blockIdx.x, gridDim.x), ls, tw_shift, counter);
+    render_block<KIND, LAYOUT>(V, s_tf, xcd_remap(blockIdx.x, gridDim.x), ls, tw_shift, counter);
 }
 
 // Persistent batched marcher: workgroups claim blocks from a queue in the
 // workspace until it runs dry; the view of a block is found by binary search
 // over the per-view block prefix.  The transfer function in LDS is reloaded
 // only when the claimed view uses a different table.
-template <int KIND>
-__global__ void __launch_bounds__(1024) march_batch_kernel(char* __restrict__ ws, const LaunchShape ls, int tw_shift,
-                                                            int tf_entries) {
+template <int KIND, int LAYOUT>
+__global__ void RT_MARCH_ATTRS march_batch_kernel(char* __restrict__ ws, const LaunchShape ls, int tw_shift,
+                                                   int tf_entries) {
     extern __shared__ float4 s_tf[];
     int* s_claim = reinterpret_cast<int*>(s_tf + tf_entries);
     BatchHeader* hdr = reinterpret_cast<BatchHeader*>(ws);
@@ -353,7 +495,7 @@ __global__ void __launch_bounds__(1024) march_batch_kernel(char* __restrict__ ws
             load_tf(s_tf, V.tf, V.K);
             __syncthreads();
         }
-        render_block<KIND>(V, s_tf, g - prefix[jdx], ls, tw_shift, counter);
+        render_block<KIND, LAYOUT>(V, s_tf, g - prefix[jdx], ls, tw_shift, counter);
         __syncthreads();
     }
 }
@@ -368,33 +510,33 @@ int log2i(int x) {
     return s;
 }
 
-template <int KIND>
+template <int KIND, int LAYOUT>
 hipError_t plain_launch(const ViewDesc& v, const LaunchShape& ls, unsigned long long* counter, hipStream_t s) {
     const int nblk = v.nblocks;
     if (nblk <= 0) return hipSuccess;
     const size_t lds = (size_t)(v.K + 1) * sizeof(float4);
     static bool attr = false;
     if (!attr) {
-        (void)hipFuncSetAttribute((const void*)march_plain_kernel<KIND>, hipFuncAttributeMaxDynamicSharedMemorySize,
+        (void)hipFuncSetAttribute((const void*)march_plain_kernel<KIND, LAYOUT>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)((kMaxK + 1) * sizeof(float4)));
         attr = true;
     }
-    hipLaunchKernelGGL(march_plain_kernel<KIND>, dim3(nblk), dim3(64 * ls.waves), lds, s, v, ls, log2i(ls.tile_w),
+    hipLaunchKernelGGL((march_plain_kernel<KIND, LAYOUT>), dim3(nblk), dim3(64 * ls.waves), lds, s, v, ls, log2i(ls.tile_w),
                        counter);
     return hipGetLastError();
 }
 
-template <int KIND>
+template <int KIND, int LAYOUT>
 hipError_t batch_launch(void* ws, int grid, const LaunchShape& ls, int max_k, hipStream_t s) {
     const int tf_entries = max_k + 1;
     const size_t lds = (size_t)tf_entries * sizeof(float4) + 16;
     static bool attr = false;
     if (!attr) {
-        (void)hipFuncSetAttribute((const void*)march_batch_kernel<KIND>, hipFuncAttributeMaxDynamicSharedMemorySize,
+        (void)hipFuncSetAttribute((const void*)march_batch_kernel<KIND, LAYOUT>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)((kMaxK + 1) * sizeof(float4) + 16));
         attr = true;
     }
-    hipLaunchKernelGGL(march_batch_kernel<KIND>, dim3(grid), dim3(64 * ls.waves), lds, s, static_cast<char*>(ws), ls,
+    hipLaunchKernelGGL((march_batch_kernel<KIND, LAYOUT>), dim3(grid), dim3(64 * ls.waves), lds, s, static_cast<char*>(ws), ls,
                        log2i(ls.tile_w), tf_entries);
     return hipGetLastError();
 }
@@ -403,24 +545,42 @@ hipError_t batch_launch(void* ws, int grid, const LaunchShape& ls, int max_k, hi
 
 hipError_t launch_march_plain(const ViewDesc& v, const LaunchShape& ls, unsigned long long* counter,
                               hipStream_t s) {
+    const int L = v.vol.layout;
     switch (v.vol.kind) {
-        case ST_U8: return plain_launch<ST_U8>(v, ls, counter, s);
-        case ST_U16: return plain_launch<ST_U16>(v, ls, counter, s);
-        case ST_F16: return plain_launch<ST_F16>(v, ls, counter, s);
-        case ST_F32: return plain_launch<ST_F32>(v, ls, counter, s);
-        case ST_U8B: return plain_launch<ST_U8B>(v, ls, counter, s);
+        case ST_U8:
+            return L == LAYOUT_CELLS ? plain_launch<ST_U8, LAYOUT_CELLS>(v, ls, counter, s)
+                                     : plain_launch<ST_U8, LAYOUT_LINEAR>(v, ls, counter, s);
+        case ST_U16:
+            return L == LAYOUT_CELLS ? plain_launch<ST_U16, LAYOUT_CELLS>(v, ls, counter, s)
+                                     : plain_launch<ST_U16, LAYOUT_LINEAR>(v, ls, counter, s);
+        case ST_F16:
+            return L == LAYOUT_CELLS ? plain_launch<ST_F16, LAYOUT_CELLS>(v, ls, counter, s)
+                                     : plain_launch<ST_F16, LAYOUT_LINEAR>(v, ls, counter, s);
+        case ST_F32:
+            return L == LAYOUT_CELLS ? plain_launch<ST_F32, LAYOUT_CELLS>(v, ls, counter, s)
+                                     : plain_launch<ST_F32, LAYOUT_LINEAR>(v, ls, counter, s);
+        case ST_U8B: return plain_launch<ST_U8B, LAYOUT_BRICKS>(v, ls, counter, s);
         default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_march_batch(int kind, void* workspace, int grid, const LaunchShape& ls, int max_k,
+hipError_t launch_march_batch(int kind, int layout, void* workspace, int grid, const LaunchShape& ls, int max_k,
                               hipStream_t s) {
+    const bool C = layout == LAYOUT_CELLS;
     switch (kind) {
-        case ST_U8: return batch_launch<ST_U8>(workspace, grid, ls, max_k, s);
-        case ST_U16: return batch_launch<ST_U16>(workspace, grid, ls, max_k, s);
-        case ST_F16: return batch_launch<ST_F16>(workspace, grid, ls, max_k, s);
-        case ST_F32: return batch_launch<ST_F32>(workspace, grid, ls, max_k, s);
-        case ST_U8B: return batch_launch<ST_U8B>(workspace, grid, ls, max_k, s);
+        case ST_U8:
+            return C ? batch_launch<ST_U8, LAYOUT_CELLS>(workspace, grid, ls, max_k, s)
+                     : batch_launch<ST_U8, LAYOUT_LINEAR>(workspace, grid, ls, max_k, s);
+        case ST_U16:
+            return C ? batch_launch<ST_U16, LAYOUT_CELLS>(workspace, grid, ls, max_k, s)
+                     : batch_launch<ST_U16, LAYOUT_LINEAR>(workspace, grid, ls, max_k, s);
+        case ST_F16:
+            return C ? batch_launch<ST_F16, LAYOUT_CELLS>(workspace, grid, ls, max_k, s)
+                     : batch_launch<ST_F16, LAYOUT_LINEAR>(workspace, grid, ls, max_k, s);
+        case ST_F32:
+            return C ? batch_launch<ST_F32, LAYOUT_CELLS>(workspace, grid, ls, max_k, s)
+                     : batch_launch<ST_F32, LAYOUT_LINEAR>(workspace, grid, ls, max_k, s);
+        case ST_U8B: return batch_launch<ST_U8B, LAYOUT_BRICKS>(workspace, grid, ls, max_k, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -435,9 +595,9 @@ int batch_persistent_grid(const LaunchShape& ls, int max_k) {
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
     const size_t lds = (size_t)(max_k + 1) * sizeof(float4) + 16;
-    (void)hipFuncSetAttribute((const void*)march_batch_kernel<ST_U16>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    (void)hipFuncSetAttribute((const void*)march_batch_kernel<ST_U16, LAYOUT_CELLS>, hipFuncAttributeMaxDynamicSharedMemorySize,
                         (int)lds);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)march_batch_kernel<ST_U16>,
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)march_batch_kernel<ST_U16, LAYOUT_CELLS>,
                                                      64 * ls.waves, lds) != hipSuccess)
         per_cu = 1;
     if (per_cu < 1) per_cu = 1;

@@ -2,9 +2,9 @@
 //
 // The scalar field f(x,y,z) on a Cartesian grid (arXiv:1211.5595, Section
 // 2.1) arrives as a C-order [z][y][x] array.  The marcher reads
-//   - linear layouts: the grid with a one-node replicated border on every
-//     face, so a sample that rounding places a hair outside the box still
-//     has 8 valid corners and reproduces clamp-to-edge exactly;
+//   - cell-packed and linear layouts of the grid with a one-node replicated
+//     border on every face, so a sample that rounding places a hair outside
+//     the box still has 8 valid corners and reproduces clamp-to-edge exactly;
 //   - brick-scaled 8-bit: per brick of B^3 cells a (lo, scale) and 8-bit
 //     codes for local nodes -1..B+1 (B+3 per axis), lo = min and
 //     scale = (max-lo)/255 over the brick's nodes, code = rint((v-lo)/scale)
@@ -70,6 +70,35 @@ __global__ void __launch_bounds__(256) relayout_linear_kernel(const typename Src
         const int pj = (int)(t % py), pk = (int)(t / py);
         const int i = min(max(pi - 1, 0), nx - 1), j = min(max(pj - 1, 0), ny - 1), k = min(max(pk - 1, 0), nz - 1);
         store_elem<SRC, DST>(dst, e, src[((size_t)k * ny + j) * nx + i]);
+    }
+}
+
+// Cell-packed layout: one thread per padded cell (cx, cy, cz) of the
+// block-rounded cell grid; it writes the cell's 8 corners (padded nodes
+// c..c+1 per axis, i.e. volume nodes clamp(c-1 .. c)) contiguously at
+// ((block * 8) + within) * 8 elements, block = x-fastest index of
+// (cx/2, cy/2, cz/2) and within = (cx&1) | (cy&1)<<1 | (cz&1)<<2.
+template <int SRC, int DST>
+__global__ void __launch_bounds__(256) relayout_cells_kernel(const typename Src<SRC>::T* __restrict__ src,
+                                                              void* __restrict__ dst, int nx, int ny, int nz, int nbx,
+                                                              int nby, int nbz) {
+    const int cxn = 2 * nbx, cyn = 2 * nby, czn = 2 * nbz;
+    const size_t total = (size_t)cxn * cyn * czn;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+        // e enumerates cells in storage order: block-major, then within-block
+        const int within = (int)(e & 7);
+        const size_t blk = e >> 3;
+        const int bx = (int)(blk % nbx);
+        const size_t t = blk / nbx;
+        const int by = (int)(t % nby), bz = (int)(t / nby);
+        const int cx = 2 * bx + (within & 1), cy = 2 * by + ((within >> 1) & 1), cz = 2 * bz + (within >> 2);
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const int i = min(max(cx + (c & 1) - 1, 0), nx - 1);
+            const int j = min(max(cy + ((c >> 1) & 1) - 1, 0), ny - 1);
+            const int k = min(max(cz + (c >> 2) - 1, 0), nz - 1);
+            store_elem<SRC, DST>(dst, e * 8 + c, src[((size_t)k * ny + j) * nx + i]);
+        }
     }
 }
 
@@ -173,6 +202,41 @@ hipError_t linear_dispatch(const void* src, int dst_kind, const int32_t n[3], vo
 }
 
 template <int SRC>
+hipError_t cells_dispatch(const void* src, int dst_kind, const int32_t n[3], const int32_t nb[3], void* dst,
+                          hipStream_t s) {
+    using T = typename Src<SRC>::T;
+    const T* p = static_cast<const T*>(src);
+    const size_t total = (size_t)8 * nb[0] * nb[1] * nb[2];
+    const int g = grid_for(total, 256);
+    switch (dst_kind) {
+        case ST_U8:
+            if constexpr (SRC == ST_U8)
+                hipLaunchKernelGGL((relayout_cells_kernel<SRC, ST_U8>), dim3(g), dim3(256), 0, s, p, dst, n[0], n[1],
+                                   n[2], nb[0], nb[1], nb[2]);
+            else
+                return hipErrorInvalidValue;
+            break;
+        case ST_U16:
+            if constexpr (SRC == ST_U8 || SRC == ST_U16)
+                hipLaunchKernelGGL((relayout_cells_kernel<SRC, ST_U16>), dim3(g), dim3(256), 0, s, p, dst, n[0],
+                                   n[1], n[2], nb[0], nb[1], nb[2]);
+            else
+                return hipErrorInvalidValue;
+            break;
+        case ST_F16:
+            hipLaunchKernelGGL((relayout_cells_kernel<SRC, ST_F16>), dim3(g), dim3(256), 0, s, p, dst, n[0], n[1],
+                               n[2], nb[0], nb[1], nb[2]);
+            break;
+        case ST_F32:
+            hipLaunchKernelGGL((relayout_cells_kernel<SRC, ST_F32>), dim3(g), dim3(256), 0, s, p, dst, n[0], n[1],
+                               n[2], nb[0], nb[1], nb[2]);
+            break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <int SRC>
 hipError_t u8b_dispatch(const void* src, const int32_t n[3], int B, const int32_t nb[3], float2* par,
                         unsigned char* codes, hipStream_t s) {
     using T = typename Src<SRC>::T;
@@ -197,6 +261,17 @@ hipError_t launch_relayout_linear(const void* src, int src_kind, int dst_kind, c
         case ST_U16: return linear_dispatch<ST_U16>(src, dst_kind, n, dst, s);
         case ST_F16: return linear_dispatch<ST_F16>(src, dst_kind, n, dst, s);
         case ST_F32: return linear_dispatch<ST_F32>(src, dst_kind, n, dst, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_relayout_cells(const void* src, int src_kind, int dst_kind, const int32_t n[3],
+                                 const int32_t nb[3], void* dst, hipStream_t s) {
+    switch (src_kind) {
+        case ST_U8: return cells_dispatch<ST_U8>(src, dst_kind, n, nb, dst, s);
+        case ST_U16: return cells_dispatch<ST_U16>(src, dst_kind, n, nb, dst, s);
+        case ST_F16: return cells_dispatch<ST_F16>(src, dst_kind, n, nb, dst, s);
+        case ST_F32: return cells_dispatch<ST_F32>(src, dst_kind, n, nb, dst, s);
         default: return hipErrorInvalidValue;
     }
 }

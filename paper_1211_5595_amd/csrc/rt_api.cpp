@@ -81,6 +81,7 @@ struct Layout {
     uint32_t sy, sz, brick_bytes;
     int32_t nb[3];
     int32_t bshift;
+    int32_t layout;
 };
 
 rt_status compute_layout(const int64_t dims[3], int storage, int brick, Layout& L) {
@@ -101,6 +102,7 @@ rt_status compute_layout(const int64_t dims[3], int storage, int brick, Layout& 
         L.sz = (uint32_t)(S * S);
         L.brick_bytes = (uint32_t)(S * S * S);
         L.bshift = brick == 8 ? 3 : (brick == 16 ? 4 : 5);
+        L.layout = LAYOUT_BRICKS;
         L.data_offset = round256(nbt * sizeof(float2));
         L.data_bytes = nbt * S * S * S;
         if (nbt >= ((size_t)1 << 24) || L.data_bytes >= ((size_t)1 << 31))
@@ -108,16 +110,30 @@ rt_status compute_layout(const int64_t dims[3], int storage, int brick, Layout& 
         L.total = round256(L.data_offset + L.data_bytes);
         return RT_OK;
     }
-    if (brick != 0) return fail(RT_ERR_INVALID_ARG, "brick must be 0 for linear storage");
+    if (brick != RT_LAYOUT_CELLS && brick != RT_LAYOUT_LINEAR)
+        return fail(RT_ERR_INVALID_ARG, "layout must be RT_LAYOUT_CELLS or RT_LAYOUT_LINEAR for this storage type");
     const int e = elem_bytes(storage);
     if (!e) return fail(RT_ERR_INVALID_ARG, "unknown storage type");
     const size_t px = (size_t)dims[0] + 2, py = (size_t)dims[1] + 2, pz = (size_t)dims[2] + 2;
-    L.sy = (uint32_t)(px * e);
-    L.sz = (uint32_t)(px * py * e);
-    if (px * py * e >= ((size_t)1 << 24)) return fail(RT_ERR_UNSUPPORTED, "slice too large for 24-bit addressing");
     L.data_offset = 0;
-    L.data_bytes = px * py * pz * e;
-    if (L.data_bytes >= ((size_t)1 << 31)) return fail(RT_ERR_UNSUPPORTED, "volume larger than 2 GiB of storage");
+    if (brick == RT_LAYOUT_CELLS) {
+        L.layout = LAYOUT_CELLS;
+        size_t nbt = 1;
+        for (int a = 0; a < 3; ++a) {
+            L.nb[a] = (int32_t)((dims[a] + 2) / 2);  // padded cells 0..n, rounded up to pairs
+            nbt *= (size_t)L.nb[a];
+        }
+        L.data_bytes = nbt * 8 * 8 * (size_t)e;
+        if (nbt >= ((size_t)1 << 24) || L.data_bytes > 0xffffffffull)
+            return fail(RT_ERR_UNSUPPORTED, "volume too large for the cell-packed layout (4 GiB)");
+    } else {
+        L.layout = LAYOUT_LINEAR;
+        L.sy = (uint32_t)(px * e);
+        L.sz = (uint32_t)(px * py * e);
+        if (px * py * e >= ((size_t)1 << 24)) return fail(RT_ERR_UNSUPPORTED, "slice too large for 24-bit addressing");
+        L.data_bytes = px * py * pz * e;
+        if (L.data_bytes >= ((size_t)1 << 31)) return fail(RT_ERR_UNSUPPORTED, "volume larger than 2 GiB of storage");
+    }
     L.total = round256(L.data_bytes);
     return RT_OK;
 }
@@ -284,9 +300,9 @@ rt_status build_batch(const rt_render_job* jobs, int n, const LaunchShape& ls, i
         rt_status st = make_view(J.volume, nullptr, nullptr, J.tf, &J.camera, J.width, J.height, J.step_vox,
                                  J.alpha_cutoff, J.bg_rgba, J.out_dev, J.pixel_counts, ls, ray_function, descs[i]);
         if (st != RT_OK) return fail(st, "job " + std::to_string(i) + ": " + g_last_error);
-        if (*kind < 0) *kind = J.volume->storage == RT_U8_BRICKSCALED ? ST_U8B : J.volume->storage;
-        const int k = J.volume->storage == RT_U8_BRICKSCALED ? ST_U8B : J.volume->storage;
-        if (k != *kind) return fail(RT_ERR_UNSUPPORTED, "all volumes of a batch must share one storage type");
+        const int k = J.volume->dev.kind * 4 + J.volume->dev.layout;  // storage type and layout
+        if (*kind < 0) *kind = k;
+        if (k != *kind) return fail(RT_ERR_UNSUPPORTED, "all volumes of a batch must share one storage type and layout");
         *max_k = std::max(*max_k, J.tf->K);
         const long long next = (long long)prefix[i] + descs[i].nblocks;
         if (next >= (1LL << 31)) return fail(RT_ERR_UNSUPPORTED, "batch too large");
@@ -367,6 +383,8 @@ rt_status rt_create_volume(const void* src_dev, int src_dtype, const int64_t dim
     if (storage == RT_U8_BRICKSCALED)
         e = launch_relayout_u8b(src_dev, src_dtype, n, brick, L.nb, reinterpret_cast<float2*>(base),
                                 reinterpret_cast<unsigned char*>(base + L.data_offset), s);
+    else if (L.layout == LAYOUT_CELLS)
+        e = launch_relayout_cells(src_dev, src_dtype, storage, n, L.nb, base, s);
     else
         e = launch_relayout_linear(src_dev, src_dtype, storage, n, base, s);
     if (e != hipSuccess) return hip_fail(e, "relayout launch");
@@ -387,6 +405,7 @@ rt_status rt_create_volume(const void* src_dev, int src_dtype, const int64_t dim
     }
     v->dev.bshift = L.bshift;
     v->dev.kind = storage == RT_U8_BRICKSCALED ? ST_U8B : storage;
+    v->dev.layout = L.layout;
     v->storage = storage;
     v->brick = brick;
     *out = v;
@@ -493,13 +512,13 @@ rt_status rt_render_batch(const rt_render_job* jobs, int n, void* workspace, siz
     if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
     g_staging.pending = true;
     const int grid = std::min(batch_persistent_grid(ls, max_k), std::max(prefix.back(), 1));
-    e = launch_march_batch(kind, workspace, grid, ls, max_k, s);
+    e = launch_march_batch(kind / 4, kind % 4, workspace, grid, ls, max_k, s);
     if (e != hipSuccess) return hip_fail(e, "batch launch");
     return RT_OK;
 }
 
-rt_status rt_batch_plan_create(int max_jobs, int storage, void* workspace, size_t ws_bytes, const rt_render_opts* opts,
-                               rt_batch_plan** out) {
+rt_status rt_batch_plan_create(int max_jobs, int storage, int layout, void* workspace, size_t ws_bytes,
+                               const rt_render_opts* opts, rt_batch_plan** out) {
     if (!out) return fail(RT_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
     if (!workspace) return fail(RT_ERR_INVALID_ARG, "workspace is NULL");
@@ -507,6 +526,8 @@ rt_status rt_batch_plan_create(int max_jobs, int storage, void* workspace, size_
     if (max_jobs < 1 || max_jobs > kMaxBatchJobs) return fail(RT_ERR_INVALID_ARG, "max_jobs must be in [1, 4096]");
     if (ws_bytes < batch_ws_bytes(max_jobs)) return fail(RT_ERR_OUT_OF_MEMORY, "workspace smaller than rt_batch_workspace_bytes");
     if (storage < RT_U8 || storage > RT_U8_BRICKSCALED) return fail(RT_ERR_INVALID_ARG, "unknown storage type");
+    if (storage != RT_U8_BRICKSCALED && layout != RT_LAYOUT_CELLS && layout != RT_LAYOUT_LINEAR)
+        return fail(RT_ERR_INVALID_ARG, "unknown layout");
     LaunchShape ls;
     rt_status st = make_shape(opts, ls);
     if (st != RT_OK) return st;
@@ -515,7 +536,8 @@ rt_status rt_batch_plan_create(int max_jobs, int storage, void* workspace, size_
     if (!p) return fail(RT_ERR_OUT_OF_MEMORY, "host allocation failed");
     std::memset(p, 0, sizeof(*p));
     p->max_jobs = max_jobs;
-    p->kind = storage == RT_U8_BRICKSCALED ? ST_U8B : storage;
+    p->kind = storage == RT_U8_BRICKSCALED ? ST_U8B * 4 + LAYOUT_BRICKS
+                                           : storage * 4 + (layout == RT_LAYOUT_LINEAR ? LAYOUT_LINEAR : LAYOUT_CELLS);
     p->ls = ls;
     p->grid = batch_persistent_grid(ls, kMaxK);
     p->ws = workspace;
@@ -528,7 +550,7 @@ rt_status rt_batch_plan_create(int max_jobs, int storage, void* workspace, size_
     }
     e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) e = launch_batch_reset(workspace, cs);
-    if (e == hipSuccess) e = launch_march_batch(p->kind, workspace, p->grid, ls, kMaxK, cs);
+    if (e == hipSuccess) e = launch_march_batch(p->kind / 4, p->kind % 4, workspace, p->grid, ls, kMaxK, cs);
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(cs, &g);
     if (e == hipSuccess) e = e2;
@@ -562,7 +584,7 @@ rt_status rt_batch_plan_launch(rt_batch_plan* p, const rt_render_job* jobs, int 
     int kind, max_k;
     rt_status st = build_batch(jobs, n, p->ls, 0, &kind, &max_k, descs, prefix);
     if (st != RT_OK) return st;
-    if (kind != p->kind) return fail(RT_ERR_INVALID_ARG, "jobs' storage type differs from the plan's");
+    if (kind != p->kind) return fail(RT_ERR_INVALID_ARG, "jobs' storage type or layout differs from the plan's");
     if (p->copy_pending) {
         hipError_t e = hipEventSynchronize(p->copy_done);
         if (e != hipSuccess) return hip_fail(e, "waiting for the previous job-table copy");

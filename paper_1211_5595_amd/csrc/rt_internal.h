@@ -14,23 +14,32 @@ struct ff {
 };
 
 enum StorageKind : int { ST_U8 = 0, ST_U16 = 1, ST_F16 = 2, ST_F32 = 3, ST_U8B = 4 };
+enum LayoutKind : int { LAYOUT_CELLS = 0, LAYOUT_LINEAR = 1, LAYOUT_BRICKS = 2 };
 
-// Device view of a volume in storage layout.
-//  Linear layouts (U8/U16/F16/F32): (nx+2)(ny+2)(nz+2) elements with a
-//  one-node replicated border; element (Pi,Pj,Pk) of the padded grid holds
-//  node (clamp(Pi-1), clamp(Pj-1), clamp(Pk-1)).
-//  Brick-scaled 8-bit (U8B): per brick of B^3 cells a (lo, scale) float2 and
-//  (B+3)^3 codes for local nodes -1..B+1 (replicated beyond the volume).
+// Device view of a volume in storage layout.  All layouts work on the
+// padded grid: nodes P = 0..n+1 per axis, node P holding node clamp(P-1)
+// of the volume (one replicated border node on every face), so a sample a
+// hair outside the box still finds 8 valid corners and clamp-to-edge holds.
+//  LAYOUT_CELLS (U8/U16/F16/F32, default): every padded cell C = 0..n
+//    stores its 8 corners contiguously (x fastest: c000 c100 c010 c110
+//    c001 c101 c011 c111); cells are grouped in 2x2x2 blocks (one 128-byte
+//    line for 16-bit storage), blocks in x-fastest order.  One vector load
+//    per sample, and the cache lines a ray tile touches do not depend on
+//    the viewing direction.
+//  LAYOUT_LINEAR (U8/U16/F16/F32): the padded grid in C order.
+//  LAYOUT_BRICKS (U8B): per brick of B^3 cells a (lo, scale) float2 and
+//    (B+3)^3 codes for local nodes -1..B+1 (replicated beyond the volume).
 struct VolDev {
-    const unsigned char* data;  // linear: padded grid; U8B: codes of brick 0
+    const unsigned char* data;  // grid, cells or codes
     const float2* brick_par;    // U8B: (lo, scale) per brick
     uint32_t data_bytes;        // size of `data` in bytes (buffer bound)
-    uint32_t sy, sz;            // linear: padded row / slice stride in bytes; U8B: (B+3), (B+3)^2
-    uint32_t brick_bytes;       // U8B: (B+3)^3
+    uint32_t sy, sz;            // LINEAR: row / slice stride in bytes; BRICKS: (B+3), (B+3)^2
+    uint32_t brick_bytes;       // BRICKS: (B+3)^3
     int32_t n[3];               // nodes per axis
-    int32_t nb[3];              // U8B: bricks per axis
-    int32_t bshift;             // U8B: log2(B)
+    int32_t nb[3];              // CELLS: 2x2x2 cell blocks per axis; BRICKS: bricks per axis
+    int32_t bshift;             // BRICKS: log2(B)
     int32_t kind;               // StorageKind
+    int32_t layout;             // LayoutKind
 };
 
 // Everything one view needs; computed on the host in binary64, rounded to
@@ -88,13 +97,15 @@ hipError_t launch_march_plain(const ViewDesc& v, const LaunchShape& ls, unsigned
                               hipStream_t s);
 // Views, prefix, job count and counter pointer are read from the workspace,
 // so one captured launch serves every batch that fits the workspace.
-hipError_t launch_march_batch(int kind, void* workspace, int grid, const LaunchShape& ls, int max_k,
+hipError_t launch_march_batch(int kind, int layout, void* workspace, int grid, const LaunchShape& ls, int max_k,
                               hipStream_t s);
 hipError_t launch_batch_reset(void* workspace, hipStream_t s);
 int batch_persistent_grid(const LaunchShape& ls, int max_k);
 
 hipError_t launch_relayout_linear(const void* src, int src_kind, int dst_kind, const int32_t n[3], void* dst,
                                   hipStream_t s);
+hipError_t launch_relayout_cells(const void* src, int src_kind, int dst_kind, const int32_t n[3],
+                                 const int32_t nb[3], void* dst, hipStream_t s);
 hipError_t launch_relayout_u8b(const void* src, int src_kind, const int32_t n[3], int B, const int32_t nb[3],
                                float2* brick_par, unsigned char* codes, hipStream_t s);
 

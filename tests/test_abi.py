@@ -42,9 +42,15 @@ def test_oracle_and_product_share_no_symbols(rt, orc):
 
 def test_volume_bytes(rt):
     # linear: (n+2)^3 padded nodes times the element size, rounded to 256
-    assert rt.rt_volume_bytes((256, 256, 160), rt.U16) == ((258 * 258 * 162 * 2 + 255) // 256) * 256
-    assert rt.rt_volume_bytes((64, 64, 32), rt.U8) == ((66 * 66 * 34 + 255) // 256) * 256
-    assert rt.rt_volume_bytes((2, 2, 2), rt.F32) == 256
+    L = rt.LAYOUT_LINEAR
+    assert rt.rt_volume_bytes((256, 256, 160), rt.U16, L) == ((258 * 258 * 162 * 2 + 255) // 256) * 256
+    assert rt.rt_volume_bytes((64, 64, 32), rt.U8, L) == ((66 * 66 * 34 + 255) // 256) * 256
+    assert rt.rt_volume_bytes((2, 2, 2), rt.F32, L) == 256
+    # cells: padded cells 0..n per axis rounded up to 2x2x2 blocks, 8 corners each
+    r256 = lambda x: (x + 255) // 256 * 256
+    assert rt.rt_volume_bytes((256, 256, 160), rt.U16) == r256(129 * 129 * 81 * 8 * 8 * 2)
+    assert rt.rt_volume_bytes((64, 64, 32), rt.U8) == r256(33 * 33 * 17 * 8 * 8)
+    assert rt.rt_volume_bytes((2, 2, 2), rt.F32) == r256(2 * 2 * 2 * 8 * 8 * 4)
     # brick-scaled: ceil((n-1)/B) bricks per axis, (B+3)^3 codes and 8 bytes each
     nb = 16 * 16 * 10
     assert rt.rt_volume_bytes((256, 256, 160), rt.U8_BRICKSCALED, 16) == \
@@ -55,6 +61,8 @@ def test_volume_bytes(rt):
     ((1, 4, 4), 1, 0, "InvalidArgument"),
     ((4, 4, 4), 4, 12, "InvalidArgument"),
     ((4, 4, 4), 1, 8, "InvalidArgument"),
+    ((4, 4, 4), 1, 2, "InvalidArgument"),
+    ((2048, 2048, 1024), 1, 0, "Unsupported"),
     ((4, 4, 4), 9, 0, "InvalidArgument"),
     ((5000, 5000, 4), 1, 0, "Unsupported"),
 ])

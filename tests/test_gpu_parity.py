@@ -214,9 +214,27 @@ def test_f32_and_f16_storage(rt, torch_mod, orc, brain):
         check(got, ref, c, f"storage {storage}")
 
 
+@pytest.mark.parametrize("storage", ["U8", "U16", "F16", "F32"])
+def test_linear_and_cell_layouts_bitwise_equal(rt, torch_mod, storage):
+    """Both layouts hold the same corner values and the marcher blends them
+    in the same order, so the images agree bit for bit."""
+    v = W.phantom_brain(5, dims=(61, 47, 38))
+    if storage == "U8":
+        v = (v >> 4).astype(np.uint8)
+    st = getattr(rt, storage)
+    imgs = []
+    for layout in (rt.LAYOUT_CELLS, rt.LAYOUT_LINEAR):
+        gv = rt.Volume(v, (0.9, 0.9, 1.2), storage=st, layout=layout)
+        gtf = rt.TransferFunction(W.random_tf(4096, 3, alpha_max=0.1), 0, 4095 if storage != "U8" else 255)
+        cam = W.orbit_cameras((61, 47, 38), (0.9, 0.9, 1.2), 7)[3]
+        img, c = gpu_render(rt, torch_mod, gv, gtf, cam, 97, 75, 0.5, 0.99)
+        imgs.append((img, c))
+    assert np.array_equal(imgs[0][0], imgs[1][0]) and np.array_equal(imgs[0][1], imgs[1][1])
+
+
 def test_f16_relayout_rounds_to_nearest_even(rt, torch_mod):
     v = np.arange(0, 4096, dtype=np.uint16)[None, None, :].repeat(2, 0).repeat(2, 1)
-    gv = rt.Volume(v, (1, 1, 1), storage=rt.F16)
+    gv = rt.Volume(v, (1, 1, 1), storage=rt.F16, layout=rt.LAYOUT_LINEAR)
     torch_mod.cuda.synchronize()
     raw = gv.buf[: (4098 * 4 * 4) * 2].view(torch_mod.float16).cpu().numpy().reshape(4, 4, 4098)
     want = v[0, 0].astype(np.float16)
@@ -285,6 +303,8 @@ def test_batch_and_plan_bitwise_equal_plain(rt, torch_mod, small, brain):
         assert np.array_equal(a, b.cpu().numpy().astype(np.float64))
     n1 = int(counter.item())
     plan = rt.BatchPlan(16, rt.U16)
+    with pytest.raises(rt.InvalidArgument):  # plan built for another layout
+        rt.BatchPlan(4, rt.U16, layout=rt.LAYOUT_LINEAR).launch(jobs[:1])
     for rep in range(3):  # replays with eager work in between
         for j in jobs:
             j.out.zero_()
