@@ -72,11 +72,14 @@ typedef enum {
     RT_U8_BRICKSCALED = 4   /* storage only: 8-bit codes with a (lo, scale) per brick of B^3 cells */
 } rt_dtype;
 
-/* Device layouts of RT_U8/RT_U16/RT_F16/RT_F32 volumes (the `brick`
- * argument of rt_volume_bytes / rt_create_volume for those types). */
+/* Device layouts of a volume.  All of them add a one-node replicated border
+ * on every face so that clamp-to-edge holds without per-sample clamping. */
 typedef enum {
-    RT_LAYOUT_CELLS = 0,  /* default: each cell's 8 corners contiguous, cells in 2x2x2 blocks (8x the grid) */
-    RT_LAYOUT_LINEAR = 1  /* the grid in C order with a one-node replicated border (1x the grid) */
+    RT_LAYOUT_CELLS = 0,  /* every cell's 8 corners contiguous, cells in 2x2x2 blocks; any storage type.
+                           * 8 values per cell (8x the grid); for RT_U8_BRICKSCALED the codes of a
+                           * cell use its owning brick's (lo, scale), kept once per 2x2x2 block */
+    RT_LAYOUT_LINEAR = 1, /* RT_U8/RT_U16/RT_F16/RT_F32: the bordered grid in C order (1x the grid) */
+    RT_LAYOUT_BRICKS = 2  /* RT_U8_BRICKSCALED: per brick the codes of local nodes -1..B+1 ((B+3)^3) */
 } rt_layout;
 
 /* Ray functions (Section 4.1 list; Section 2.4 for maximum intensity and
@@ -123,27 +126,27 @@ typedef struct {
  * with thickness and gaps, Section 1, give an anisotropic spacing).
  * ------------------------------------------------------------------------- */
 
-/* Device bytes needed to hold a volume of `dims` in `storage` layout.  brick
- * is the brick edge B in cells (8, 16 or 32) for RT_U8_BRICKSCALED and the
- * rt_layout for the other types.  Errors: RT_ERR_INVALID_ARG (bad dims,
- * brick or layout, NULL), RT_ERR_UNSUPPORTED (volume too large for 32-bit
- * addressing: 4 GiB of storage). */
-rt_status rt_volume_bytes(const int64_t dims[3], int storage, int brick, size_t* bytes);
+/* Device bytes needed to hold a volume of `dims` with element type `storage`
+ * in `layout`.  brick is the brick edge B in cells (8, 16 or 32) for
+ * RT_U8_BRICKSCALED and must be 0 otherwise.  Errors: RT_ERR_INVALID_ARG
+ * (bad dims, layout or brick, NULL), RT_ERR_UNSUPPORTED (volume too large for
+ * 32-bit addressing: 4 GiB of storage). */
+rt_status rt_volume_bytes(const int64_t dims[3], int storage, int layout, int brick, size_t* bytes);
 
 /* Convert a device-resident source array (C-order [z][y][x] of src_dtype,
- * one of RT_U8/RT_U16/RT_F16/RT_F32) into the raycaster's storage layout in
- * the caller's device buffer dev_buf (>= rt_volume_bytes bytes), on `stream`.
- * Every layout adds a one-node replicated border on every face;
- * RT_LAYOUT_CELLS stores each cell's 8 corners contiguously, RT_LAYOUT_LINEAR
- * the bordered grid, and RT_U8_BRICKSCALED per brick of brick^3 cells a
- * (lo, scale) and 8-bit codes with a halo: lo = brick minimum, scale =
- * (max-lo)/255, code = rint((v-lo)/scale), all binary32.  The source may be
- * freed once the stream has passed this call.  *out receives the handle.
+ * one of RT_U8/RT_U16/RT_F16/RT_F32) into element type `storage` and
+ * `layout` (rt_layout) in the caller's device buffer dev_buf
+ * (>= rt_volume_bytes bytes, 256-byte aligned), on `stream`.  For
+ * RT_U8_BRICKSCALED each brick of brick^3 cells gets lo = minimum and
+ * scale = (maximum-lo)/255 over its nodes (high halo included) and every
+ * node the code rint((v-lo)/scale), all binary32; a sample is decoded with
+ * the brick that owns its cell.  The source may be freed once the stream has
+ * passed this call.  *out receives the handle.
  * Errors: RT_ERR_INVALID_ARG (NULL, dims < 2, non-finite or non-positive
  * spacing, storage/src combination such as F32 -> U8), RT_ERR_OUT_OF_MEMORY
  * (dev_buf_bytes too small), RT_ERR_DEVICE (launch failure). */
 rt_status rt_create_volume(const void* src_dev, int src_dtype, const int64_t dims[3], const double spacing[3],
-                           int storage, int brick, void* dev_buf, size_t dev_buf_bytes, void* stream,
+                           int storage, int layout, int brick, void* dev_buf, size_t dev_buf_bytes, void* stream,
                            rt_volume** out);
 rt_status rt_destroy_volume(rt_volume* vol);
 
@@ -209,7 +212,7 @@ rt_status rt_render_batch(const rt_render_job* jobs, int n, void* workspace, siz
 
 /* A batch plan: the persistent launch captured once into a HIP graph over a
  * fixed workspace, replayed for every batch of up to max_jobs views of one
- * storage type and layout (layout ignored for RT_U8_BRICKSCALED).  rt_batch_plan_launch copies the job table into the
+ * storage type and layout.  rt_batch_plan_launch copies the job table into the
  * workspace (plain stream copy, outside the graph) and launches the graph on
  * `stream`.  The plan keeps a pinned host staging buffer and waits for the
  * previous launch's copy before reusing it.  Calls on one plan must not run

@@ -31,7 +31,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "librtvol.so")
 
 U8, U16, F16, F32, U8_BRICKSCALED = 0, 1, 2, 3, 4
-LAYOUT_CELLS, LAYOUT_LINEAR = 0, 1
+LAYOUT_CELLS, LAYOUT_LINEAR, LAYOUT_BRICKS = 0, 1, 2
 COMPOSITE, MIP, XRAY, AVERAGE, ISO, THRESHOLD = range(6)
 _DTYPE_CODE = {np.dtype(np.uint8): U8, np.dtype(np.uint16): U16, np.dtype(np.float16): F16,
                np.dtype(np.float32): F32}
@@ -92,8 +92,9 @@ def lib():
         i64p, vp, szp = C.POINTER(C.c_int64), C.c_void_p, C.POINTER(C.c_size_t)
         dp = C.POINTER(C.c_double)
         sigs = {
-            "rt_volume_bytes": [i64p, C.c_int, C.c_int, szp],
-            "rt_create_volume": [vp, C.c_int, i64p, dp, C.c_int, C.c_int, vp, C.c_size_t, vp, C.POINTER(vp)],
+            "rt_volume_bytes": [i64p, C.c_int, C.c_int, C.c_int, szp],
+            "rt_create_volume": [vp, C.c_int, i64p, dp, C.c_int, C.c_int, C.c_int, vp, C.c_size_t, vp,
+                                 C.POINTER(vp)],
             "rt_destroy_volume": [vp],
             "rt_tf_bytes": [C.c_int, szp],
             "rt_set_transfer_function": [C.POINTER(vp), C.POINTER(C.c_float), C.c_int, C.c_double, C.c_double, vp,
@@ -174,18 +175,18 @@ def make_opts(sample_counter=None, pixel_counts=None, ray_function=COMPOSITE, is
 # ---------------------------------------------------------------------------
 # C-named entry points (marshalling only)
 # ---------------------------------------------------------------------------
-def rt_volume_bytes(dims, storage: int, brick: int = 0) -> int:
+def rt_volume_bytes(dims, storage: int, layout: int = LAYOUT_CELLS, brick: int = 0) -> int:
     n = C.c_size_t()
-    _check(lib().rt_volume_bytes(_i64x3(dims), int(storage), int(brick), C.byref(n)), "rt_volume_bytes")
+    _check(lib().rt_volume_bytes(_i64x3(dims), int(storage), int(layout), int(brick), C.byref(n)), "rt_volume_bytes")
     return n.value
 
 
-def rt_create_volume(src_ptr: int, src_dtype: int, dims, spacing, storage: int, brick: int, dev_buf_ptr: int,
-                     dev_buf_bytes: int, stream=None) -> int:
+def rt_create_volume(src_ptr: int, src_dtype: int, dims, spacing, storage: int, layout: int, brick: int,
+                     dev_buf_ptr: int, dev_buf_bytes: int, stream=None) -> int:
     h = C.c_void_p()
     _check(lib().rt_create_volume(C.c_void_p(src_ptr), int(src_dtype), _i64x3(dims), _f64x3(spacing), int(storage),
-                                  int(brick), C.c_void_p(dev_buf_ptr), int(dev_buf_bytes), _stream_ptr(stream),
-                                  C.byref(h)), "rt_create_volume")
+                                  int(layout), int(brick), C.c_void_p(dev_buf_ptr), int(dev_buf_bytes),
+                                  _stream_ptr(stream), C.byref(h)), "rt_create_volume")
     return h.value
 
 
@@ -264,8 +265,8 @@ class Volume:
 
     ``values``: numpy array or CUDA tensor, C-order [z][y][x] of uint8,
     uint16, float16 or float32.  ``storage``: one of U8, U16, F16, F32
-    (with ``layout`` LAYOUT_CELLS or LAYOUT_LINEAR) or U8_BRICKSCALED (with
-    ``brick`` 8/16/32)."""
+    (``layout`` LAYOUT_CELLS or LAYOUT_LINEAR) or U8_BRICKSCALED (``brick``
+    8/16/32, ``layout`` LAYOUT_CELLS or LAYOUT_BRICKS)."""
 
     def __init__(self, values, spacing: Sequence[float], storage: Optional[int] = None, brick: int = 0,
                  stream=None, device="cuda", layout: int = LAYOUT_CELLS):
@@ -289,12 +290,12 @@ class Volume:
         self.dims = (nx, ny, nz)
         self.spacing = tuple(float(s) for s in spacing)
         self.storage = src_dtype if storage is None else int(storage)
-        self.brick = int(brick) if self.storage == U8_BRICKSCALED else int(layout)
-        self.layout = None if self.storage == U8_BRICKSCALED else int(layout)
-        self.nbytes = rt_volume_bytes(self.dims, self.storage, self.brick)
+        self.brick = int(brick)
+        self.layout = int(layout)
+        self.nbytes = rt_volume_bytes(self.dims, self.storage, self.layout, self.brick)
         self.buf = torch.empty(self.nbytes, dtype=torch.uint8, device=src.device)
-        self.handle = rt_create_volume(src.data_ptr(), src_dtype, self.dims, self.spacing, self.storage, self.brick,
-                                       self.buf.data_ptr(), self.nbytes, stream)
+        self.handle = rt_create_volume(src.data_ptr(), src_dtype, self.dims, self.spacing, self.storage, self.layout,
+                                       self.brick, self.buf.data_ptr(), self.nbytes, stream)
         self._src = src  # kept until the relayout on the stream has consumed it
         if stream is None:
             torch.cuda.current_stream(src.device).synchronize()

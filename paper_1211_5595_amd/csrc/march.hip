@@ -304,6 +304,31 @@ struct Sampler<KIND, LAYOUT_CELLS> {
     }
 };
 
+// Cell-packed brick-scaled 8-bit codes: cell blocks shifted by one cell so
+// each lies inside one brick; 8 codes per cell plus the block's (lo, scale).
+template <>
+struct Sampler<ST_U8B, LAYOUT_CELLS> {
+    struct Raw {
+        u32x2 w;
+        float2 par;
+    };
+    static __device__ __forceinline__ Raw load(__amdgpu_buffer_rsrc_t r, const VolDev& vol, const Corners&,
+                                               const long long Q[3]) {
+        const uint32_t ix = hiword(Q[0]) + 1u, iy = hiword(Q[1]) + 1u, iz = hiword(Q[2]) + 1u;
+        const uint32_t blk = __umul24(__umul24(iz >> 1, (uint32_t)vol.nb[1]) + (iy >> 1), (uint32_t)vol.nb[0]) + (ix >> 1);
+        const uint32_t w = (ix & 1u) | ((iy & 1u) << 1) | ((iz & 1u) << 2);
+        Raw o;
+        o.w = __builtin_amdgcn_raw_buffer_load_b64(r, (blk << 6) | (w << 3), 0, 0);
+        o.par = vol.brick_par[blk];
+        return o;
+    }
+    static __device__ __forceinline__ float value(const Raw& o, float fx, float fy, float fz) {
+        float c[8];
+        CellBits<ST_U8>::unpack(o.w, c);
+        return fmaf(o.par.y, trilinear8(c, fx, fy, fz), o.par.x);
+    }
+};
+
 // Brick-scaled 8-bit codes: the brick owning the (clamped) cell supplies all
 // 8 corners and the (lo, scale) that decodes their blend.
 template <>
@@ -559,7 +584,9 @@ hipError_t launch_march_plain(const ViewDesc& v, const LaunchShape& ls, unsigned
         case ST_F32:
             return L == LAYOUT_CELLS ? plain_launch<ST_F32, LAYOUT_CELLS>(v, ls, counter, s)
                                      : plain_launch<ST_F32, LAYOUT_LINEAR>(v, ls, counter, s);
-        case ST_U8B: return plain_launch<ST_U8B, LAYOUT_BRICKS>(v, ls, counter, s);
+        case ST_U8B:
+            return L == LAYOUT_CELLS ? plain_launch<ST_U8B, LAYOUT_CELLS>(v, ls, counter, s)
+                                     : plain_launch<ST_U8B, LAYOUT_BRICKS>(v, ls, counter, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -580,7 +607,9 @@ hipError_t launch_march_batch(int kind, int layout, void* workspace, int grid, c
         case ST_F32:
             return C ? batch_launch<ST_F32, LAYOUT_CELLS>(workspace, grid, ls, max_k, s)
                      : batch_launch<ST_F32, LAYOUT_LINEAR>(workspace, grid, ls, max_k, s);
-        case ST_U8B: return batch_launch<ST_U8B, LAYOUT_BRICKS>(workspace, grid, ls, max_k, s);
+        case ST_U8B:
+            return C ? batch_launch<ST_U8B, LAYOUT_CELLS>(workspace, grid, ls, max_k, s)
+                     : batch_launch<ST_U8B, LAYOUT_BRICKS>(workspace, grid, ls, max_k, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -161,6 +161,45 @@ __global__ void __launch_bounds__(256) brick_encode_kernel(const typename Src<SR
     }
 }
 
+// Cell-packed 8-bit codes: one thread per cell of the shifted block grid
+// (block b holds padded cells C with C+1 in {2b, 2b+1}); the owner brick of
+// unpadded cell c = C-1 is clamp(c, 0, n-2)/B, the same for all 8 cells of a
+// block.  Each cell gets its 8 corner codes (nodes clamp(c..c+1)) quantised
+// with the owner's (lo, scale); the block's first cell also stores that pair.
+template <int SRC>
+__global__ void __launch_bounds__(256) brick_cells_kernel(const typename Src<SRC>::T* __restrict__ src, int nx,
+                                                           int ny, int nz, int B, int nbx, int nby,
+                                                           const float2* __restrict__ par, int cbx, int cby, int cbz,
+                                                           float2* __restrict__ block_par,
+                                                           unsigned char* __restrict__ codes) {
+    const size_t total = (size_t)8 * cbx * cby * cbz;
+    const int n[3] = {nx, ny, nz};
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+        const int within = (int)(e & 7);
+        const size_t blk = e >> 3;
+        const int b[3] = {(int)(blk % cbx), (int)((blk / cbx) % cby), (int)(blk / ((size_t)cbx * cby))};
+        int c[3], owner[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            c[a] = 2 * b[a] + ((within >> a) & 1) - 2;  // unpadded cell index, -2..n
+            owner[a] = min(max(c[a], 0), n[a] - 2) / B;
+        }
+        const float2 p = par[(owner[2] * nby + owner[1]) * nbx + owner[0]];
+        unsigned long long word = 0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int i = min(max(c[0] + (k & 1), 0), nx - 1);
+            const int j = min(max(c[1] + ((k >> 1) & 1), 0), ny - 1);
+            const int l = min(max(c[2] + (k >> 2), 0), nz - 1);
+            const float v = Src<SRC>::f(src[((size_t)l * ny + j) * nx + i]);
+            const float q = fminf(fmaxf(rintf((v - p.x) / p.y), 0.0f), 255.0f);
+            word |= (unsigned long long)(unsigned int)q << (8 * k);
+        }
+        reinterpret_cast<unsigned long long*>(codes)[e] = word;
+        if (within == 0) block_par[blk] = p;
+    }
+}
+
 int grid_for(size_t total, int block) {
     size_t g = (total + block - 1) / block;
     if (g > (size_t)1 << 20) g = (size_t)1 << 20;
@@ -252,7 +291,35 @@ hipError_t u8b_dispatch(const void* src, const int32_t n[3], int B, const int32_
     return hipGetLastError();
 }
 
+template <int SRC>
+hipError_t u8b_cells_dispatch(const void* src, const int32_t n[3], int B, const int32_t nb[3], float2* par,
+                              const int32_t ncb[3], float2* block_par, unsigned char* codes, hipStream_t s) {
+    using T = typename Src<SRC>::T;
+    const T* p = static_cast<const T*>(src);
+    const int nbt = nb[0] * nb[1] * nb[2];
+    hipLaunchKernelGGL(brick_minmax_kernel<SRC>, dim3(nbt), dim3(256), 0, s, p, n[0], n[1], n[2], B, nb[0], nb[1],
+                       par);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const size_t total = (size_t)8 * ncb[0] * ncb[1] * ncb[2];
+    hipLaunchKernelGGL(brick_cells_kernel<SRC>, dim3(grid_for(total, 256)), dim3(256), 0, s, p, n[0], n[1], n[2], B,
+                       nb[0], nb[1], par, ncb[0], ncb[1], ncb[2], block_par, codes);
+    return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t launch_relayout_u8b_cells(const void* src, int src_kind, const int32_t n[3], int B, const int32_t nb[3],
+                                     float2* brick_par, const int32_t ncb[3], float2* block_par,
+                                     unsigned char* codes, hipStream_t s) {
+    switch (src_kind) {
+        case ST_U8: return u8b_cells_dispatch<ST_U8>(src, n, B, nb, brick_par, ncb, block_par, codes, s);
+        case ST_U16: return u8b_cells_dispatch<ST_U16>(src, n, B, nb, brick_par, ncb, block_par, codes, s);
+        case ST_F16: return u8b_cells_dispatch<ST_F16>(src, n, B, nb, brick_par, ncb, block_par, codes, s);
+        case ST_F32: return u8b_cells_dispatch<ST_F32>(src, n, B, nb, brick_par, ncb, block_par, codes, s);
+        default: return hipErrorInvalidValue;
+    }
+}
 
 hipError_t launch_relayout_linear(const void* src, int src_kind, int dst_kind, const int32_t n[3], void* dst,
                                   hipStream_t s) {

@@ -75,23 +75,35 @@ int elem_bytes(int kind) {
 size_t round256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t total;         // bytes
-    size_t data_offset;   // start of the grid / codes
+    size_t total;             // bytes
+    size_t data_offset;       // start of the grid / cells / codes
     size_t data_bytes;
+    size_t par_bytes;         // U8B cells: per-block (lo, scale)
+    size_t brick_par_offset;  // U8B cells: per-brick (lo, scale) used while encoding
     uint32_t sy, sz, brick_bytes;
-    int32_t nb[3];
+    int32_t nb[3];            // cell blocks (CELLS) or bricks (BRICKS) per axis
+    int32_t brick_nb[3];      // U8B cells: bricks per axis
     int32_t bshift;
     int32_t layout;
 };
 
-rt_status compute_layout(const int64_t dims[3], int storage, int brick, Layout& L) {
+rt_status compute_layout(const int64_t dims[3], int storage, int layout, int brick, Layout& L) {
     if (!dims) return fail(RT_ERR_INVALID_ARG, "dims is NULL");
     for (int a = 0; a < 3; ++a)
         if (dims[a] < 2 || dims[a] > (1 << 20)) return fail(RT_ERR_INVALID_ARG, "each dimension must be in [2, 2^20]");
     std::memset(&L, 0, sizeof(L));
-    if (storage == RT_U8_BRICKSCALED) {
+    if (storage < RT_U8 || storage > RT_U8_BRICKSCALED) return fail(RT_ERR_INVALID_ARG, "unknown storage type");
+    const bool u8b = storage == RT_U8_BRICKSCALED;
+    if (u8b ? (layout != RT_LAYOUT_CELLS && layout != RT_LAYOUT_BRICKS)
+            : (layout != RT_LAYOUT_CELLS && layout != RT_LAYOUT_LINEAR))
+        return fail(RT_ERR_INVALID_ARG, "layout not available for this storage type");
+    if (u8b) {
         if (brick != 8 && brick != 16 && brick != 32)
             return fail(RT_ERR_INVALID_ARG, "brick-scaled storage needs brick 8, 16 or 32");
+    } else if (brick != 0) {
+        return fail(RT_ERR_INVALID_ARG, "brick must be 0 unless the storage is brick-scaled");
+    }
+    if (u8b && layout == RT_LAYOUT_BRICKS) {
         size_t nbt = 1;
         for (int a = 0; a < 3; ++a) {
             L.nb[a] = (int32_t)((dims[a] - 1 + brick - 1) / brick);
@@ -110,13 +122,30 @@ rt_status compute_layout(const int64_t dims[3], int storage, int brick, Layout& 
         L.total = round256(L.data_offset + L.data_bytes);
         return RT_OK;
     }
-    if (brick != RT_LAYOUT_CELLS && brick != RT_LAYOUT_LINEAR)
-        return fail(RT_ERR_INVALID_ARG, "layout must be RT_LAYOUT_CELLS or RT_LAYOUT_LINEAR for this storage type");
+    if (u8b) {
+        // [block (lo, scale) x ncb][codes 64 B x ncb][brick (lo, scale) x nbricks]
+        size_t nbt = 1, ncb = 1;
+        for (int a = 0; a < 3; ++a) {
+            L.nb[a] = (int32_t)((dims[a] + 1) / 2 + 1);  // shifted cell blocks covering padded cells 0..n
+            L.brick_nb[a] = (int32_t)((dims[a] - 1 + brick - 1) / brick);
+            ncb *= (size_t)L.nb[a];
+            nbt *= (size_t)L.brick_nb[a];
+        }
+        L.bshift = brick == 8 ? 3 : (brick == 16 ? 4 : 5);
+        L.layout = LAYOUT_CELLS;
+        L.par_bytes = round256(ncb * sizeof(float2));
+        L.data_offset = L.par_bytes;
+        L.data_bytes = ncb * 64;
+        L.brick_par_offset = round256(L.data_offset + L.data_bytes);
+        if (ncb >= ((size_t)1 << 24) || L.data_bytes > 0xffffffffull)
+            return fail(RT_ERR_UNSUPPORTED, "volume too large for the cell-packed layout (4 GiB)");
+        L.total = round256(L.brick_par_offset + nbt * sizeof(float2));
+        return RT_OK;
+    }
     const int e = elem_bytes(storage);
-    if (!e) return fail(RT_ERR_INVALID_ARG, "unknown storage type");
     const size_t px = (size_t)dims[0] + 2, py = (size_t)dims[1] + 2, pz = (size_t)dims[2] + 2;
     L.data_offset = 0;
-    if (brick == RT_LAYOUT_CELLS) {
+    if (layout == RT_LAYOUT_CELLS) {
         L.layout = LAYOUT_CELLS;
         size_t nbt = 1;
         for (int a = 0; a < 3; ++a) {
@@ -348,17 +377,17 @@ const char* rt_last_error(void) { return g_last_error.c_str(); }
 
 const char* rt_version(void) { return "rtvol 0.1 gfx950"; }
 
-rt_status rt_volume_bytes(const int64_t dims[3], int storage, int brick, size_t* bytes) {
+rt_status rt_volume_bytes(const int64_t dims[3], int storage, int layout, int brick, size_t* bytes) {
     if (!bytes) return fail(RT_ERR_INVALID_ARG, "bytes is NULL");
     Layout L;
-    rt_status st = compute_layout(dims, storage, brick, L);
+    rt_status st = compute_layout(dims, storage, layout, brick, L);
     if (st != RT_OK) return st;
     *bytes = L.total;
     return RT_OK;
 }
 
 rt_status rt_create_volume(const void* src_dev, int src_dtype, const int64_t dims[3], const double spacing[3],
-                           int storage, int brick, void* dev_buf, size_t dev_buf_bytes, void* stream,
+                           int storage, int layout, int brick, void* dev_buf, size_t dev_buf_bytes, void* stream,
                            rt_volume** out) {
     if (!out) return fail(RT_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
@@ -367,7 +396,7 @@ rt_status rt_create_volume(const void* src_dev, int src_dtype, const int64_t dim
     for (int a = 0; a < 3; ++a)
         if (!(spacing[a] > 0.0) || !std::isfinite(spacing[a])) return fail(RT_ERR_INVALID_ARG, "spacing must be finite and > 0");
     Layout L;
-    rt_status st = compute_layout(dims, storage, brick, L);
+    rt_status st = compute_layout(dims, storage, layout, brick, L);
     if (st != RT_OK) return st;
     if (dev_buf_bytes < L.total) return fail(RT_ERR_OUT_OF_MEMORY, "volume buffer smaller than rt_volume_bytes");
     if (((uintptr_t)dev_buf & 255) != 0) return fail(RT_ERR_INVALID_ARG, "volume buffer must be 256-byte aligned");
@@ -380,7 +409,12 @@ rt_status rt_create_volume(const void* src_dev, int src_dtype, const int64_t dim
     hipStream_t s = static_cast<hipStream_t>(stream);
     char* base = static_cast<char*>(dev_buf);
     hipError_t e;
-    if (storage == RT_U8_BRICKSCALED)
+    if (storage == RT_U8_BRICKSCALED && L.layout == LAYOUT_CELLS)
+        e = launch_relayout_u8b_cells(src_dev, src_dtype, n, brick, L.brick_nb,
+                                      reinterpret_cast<float2*>(base + L.brick_par_offset), L.nb,
+                                      reinterpret_cast<float2*>(base),
+                                      reinterpret_cast<unsigned char*>(base + L.data_offset), s);
+    else if (storage == RT_U8_BRICKSCALED)
         e = launch_relayout_u8b(src_dev, src_dtype, n, brick, L.nb, reinterpret_cast<float2*>(base),
                                 reinterpret_cast<unsigned char*>(base + L.data_offset), s);
     else if (L.layout == LAYOUT_CELLS)
@@ -526,8 +560,9 @@ rt_status rt_batch_plan_create(int max_jobs, int storage, int layout, void* work
     if (max_jobs < 1 || max_jobs > kMaxBatchJobs) return fail(RT_ERR_INVALID_ARG, "max_jobs must be in [1, 4096]");
     if (ws_bytes < batch_ws_bytes(max_jobs)) return fail(RT_ERR_OUT_OF_MEMORY, "workspace smaller than rt_batch_workspace_bytes");
     if (storage < RT_U8 || storage > RT_U8_BRICKSCALED) return fail(RT_ERR_INVALID_ARG, "unknown storage type");
-    if (storage != RT_U8_BRICKSCALED && layout != RT_LAYOUT_CELLS && layout != RT_LAYOUT_LINEAR)
-        return fail(RT_ERR_INVALID_ARG, "unknown layout");
+    if (storage == RT_U8_BRICKSCALED ? (layout != RT_LAYOUT_CELLS && layout != RT_LAYOUT_BRICKS)
+                                     : (layout != RT_LAYOUT_CELLS && layout != RT_LAYOUT_LINEAR))
+        return fail(RT_ERR_INVALID_ARG, "layout not available for this storage type");
     LaunchShape ls;
     rt_status st = make_shape(opts, ls);
     if (st != RT_OK) return st;
@@ -536,8 +571,8 @@ rt_status rt_batch_plan_create(int max_jobs, int storage, int layout, void* work
     if (!p) return fail(RT_ERR_OUT_OF_MEMORY, "host allocation failed");
     std::memset(p, 0, sizeof(*p));
     p->max_jobs = max_jobs;
-    p->kind = storage == RT_U8_BRICKSCALED ? ST_U8B * 4 + LAYOUT_BRICKS
-                                           : storage * 4 + (layout == RT_LAYOUT_LINEAR ? LAYOUT_LINEAR : LAYOUT_CELLS);
+    p->kind = (storage == RT_U8_BRICKSCALED ? ST_U8B : storage) * 4 +
+              (layout == RT_LAYOUT_LINEAR ? LAYOUT_LINEAR : (layout == RT_LAYOUT_BRICKS ? LAYOUT_BRICKS : LAYOUT_CELLS));
     p->ls = ls;
     p->grid = batch_persistent_grid(ls, kMaxK);
     p->ws = workspace;

@@ -27,11 +27,15 @@ enum LayoutKind : int { LAYOUT_CELLS = 0, LAYOUT_LINEAR = 1, LAYOUT_BRICKS = 2 }
 //    per sample, and the cache lines a ray tile touches do not depend on
 //    the viewing direction.
 //  LAYOUT_LINEAR (U8/U16/F16/F32): the padded grid in C order.
+//    For U8B the cell blocks are shifted by one cell (block = (C+1)/2) so a
+//    block never straddles a brick (B even); each block keeps the (lo,
+//    scale) of the brick owning its cells in `brick_par` (8 B per block)
+//    next to 64 B of codes.
 //  LAYOUT_BRICKS (U8B): per brick of B^3 cells a (lo, scale) float2 and
 //    (B+3)^3 codes for local nodes -1..B+1 (replicated beyond the volume).
 struct VolDev {
     const unsigned char* data;  // grid, cells or codes
-    const float2* brick_par;    // U8B: (lo, scale) per brick
+    const float2* brick_par;    // U8B: (lo, scale) per brick (BRICKS) or per cell block (CELLS)
     uint32_t data_bytes;        // size of `data` in bytes (buffer bound)
     uint32_t sy, sz;            // LINEAR: row / slice stride in bytes; BRICKS: (B+3), (B+3)^2
     uint32_t brick_bytes;       // BRICKS: (B+3)^3
@@ -108,5 +112,10 @@ hipError_t launch_relayout_cells(const void* src, int src_kind, int dst_kind, co
                                  const int32_t nb[3], void* dst, hipStream_t s);
 hipError_t launch_relayout_u8b(const void* src, int src_kind, const int32_t n[3], int B, const int32_t nb[3],
                                float2* brick_par, unsigned char* codes, hipStream_t s);
+// Cell-packed 8-bit codes: per-brick (lo, scale) into brick_par (nbricks),
+// then codes and per-block parameters for the ncb cell blocks.
+hipError_t launch_relayout_u8b_cells(const void* src, int src_kind, const int32_t n[3], int B, const int32_t nb[3],
+                                     float2* brick_par, const int32_t ncb[3], float2* block_par,
+                                     unsigned char* codes, hipStream_t s);
 
 }  // namespace rtv

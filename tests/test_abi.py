@@ -41,34 +41,40 @@ def test_oracle_and_product_share_no_symbols(rt, orc):
 
 
 def test_volume_bytes(rt):
+    r256 = lambda x: (x + 255) // 256 * 256
     # linear: (n+2)^3 padded nodes times the element size, rounded to 256
     L = rt.LAYOUT_LINEAR
     assert rt.rt_volume_bytes((256, 256, 160), rt.U16, L) == ((258 * 258 * 162 * 2 + 255) // 256) * 256
     assert rt.rt_volume_bytes((64, 64, 32), rt.U8, L) == ((66 * 66 * 34 + 255) // 256) * 256
     assert rt.rt_volume_bytes((2, 2, 2), rt.F32, L) == 256
     # cells: padded cells 0..n per axis rounded up to 2x2x2 blocks, 8 corners each
-    r256 = lambda x: (x + 255) // 256 * 256
     assert rt.rt_volume_bytes((256, 256, 160), rt.U16) == r256(129 * 129 * 81 * 8 * 8 * 2)
     assert rt.rt_volume_bytes((64, 64, 32), rt.U8) == r256(33 * 33 * 17 * 8 * 8)
     assert rt.rt_volume_bytes((2, 2, 2), rt.F32) == r256(2 * 2 * 2 * 8 * 8 * 4)
-    # brick-scaled: ceil((n-1)/B) bricks per axis, (B+3)^3 codes and 8 bytes each
+    # brick-scaled, halo bricks: ceil((n-1)/B) bricks per axis, (B+3)^3 codes and 8 bytes each
     nb = 16 * 16 * 10
-    assert rt.rt_volume_bytes((256, 256, 160), rt.U8_BRICKSCALED, 16) == \
-        ((((nb * 8 + 255) // 256) * 256 + nb * 19 ** 3 + 255) // 256) * 256
+    assert rt.rt_volume_bytes((256, 256, 160), rt.U8_BRICKSCALED, rt.LAYOUT_BRICKS, 16) == \
+        r256(r256(nb * 8) + nb * 19 ** 3)
+    # brick-scaled, cells: (n+1)//2+1 shifted blocks per axis, 64 B of codes and 8 B each,
+    # then the per-brick parameters
+    ncb = 129 * 129 * 81
+    assert rt.rt_volume_bytes((256, 256, 160), rt.U8_BRICKSCALED, rt.LAYOUT_CELLS, 16) == \
+        r256(r256(r256(ncb * 8) + ncb * 64) + nb * 8)
 
 
-@pytest.mark.parametrize("dims,storage,brick,exc", [
-    ((1, 4, 4), 1, 0, "InvalidArgument"),
-    ((4, 4, 4), 4, 12, "InvalidArgument"),
-    ((4, 4, 4), 1, 8, "InvalidArgument"),
-    ((4, 4, 4), 1, 2, "InvalidArgument"),
-    ((2048, 2048, 1024), 1, 0, "Unsupported"),
-    ((4, 4, 4), 9, 0, "InvalidArgument"),
-    ((5000, 5000, 4), 1, 0, "Unsupported"),
+@pytest.mark.parametrize("dims,storage,layout,brick,exc", [
+    ((1, 4, 4), 1, 0, 0, "InvalidArgument"),
+    ((4, 4, 4), 4, 0, 12, "InvalidArgument"),
+    ((4, 4, 4), 1, 0, 8, "InvalidArgument"),
+    ((4, 4, 4), 1, 2, 0, "InvalidArgument"),
+    ((4, 4, 4), 4, 1, 8, "InvalidArgument"),
+    ((2048, 2048, 1024), 1, 0, 0, "Unsupported"),
+    ((4, 4, 4), 9, 0, 0, "InvalidArgument"),
+    ((5000, 5000, 4), 1, 1, 0, "Unsupported"),
 ])
-def test_volume_bytes_errors(rt, dims, storage, brick, exc):
+def test_volume_bytes_errors(rt, dims, storage, layout, brick, exc):
     with pytest.raises(getattr(rt, exc)):
-        rt.rt_volume_bytes(dims, storage, brick)
+        rt.rt_volume_bytes(dims, storage, layout, brick)
 
 
 def test_tf_and_workspace_bytes(rt):
@@ -88,7 +94,7 @@ def test_null_arguments_are_reported_not_fatal(rt):
     assert b"NULL" in L.rt_last_error()
     h = C.c_void_p()
     sp = (C.c_double * 3)(1, 1, 1)
-    assert L.rt_create_volume(None, 1, dims, sp, 1, 0, None, 0, None, C.byref(h)) == 1
+    assert L.rt_create_volume(None, 1, dims, sp, 1, 0, 0, None, 0, None, C.byref(h)) == 1
     assert L.rt_render_batch(None, 0, None, 0, None, None, None) == 1
     assert L.rt_batch_plan_launch(None, None, 0, None, None) == 1
     assert L.rt_destroy_volume(None) == 0 and L.rt_destroy_tf(None) == 0 and L.rt_batch_plan_destroy(None) == 0

@@ -246,7 +246,7 @@ def test_f16_relayout_rounds_to_nearest_even(rt, torch_mod):
 def test_u8_brick_codes_bit_exact(rt, torch_mod, orc, B):
     v = W.phantom_brain(11, dims=(70, 45, 33))
     dims = (70, 45, 33)
-    gv = rt.Volume(v, (0.9, 0.9, 1.2), storage=rt.U8_BRICKSCALED, brick=B)
+    gv = rt.Volume(v, (0.9, 0.9, 1.2), storage=rt.U8_BRICKSCALED, brick=B, layout=rt.LAYOUT_BRICKS)
     torch_mod.cuda.synchronize()
     lo, sc, codes = orc.encode_u8_bricks(v, B)
     total, nb = orc.u8_brick_count(dims, B)
@@ -266,14 +266,49 @@ def test_u8_brick_codes_bit_exact(rt, torch_mod, orc, B):
         assert np.array_equal(dev[bid, 1:1 + ez, 1:1 + ey, 1:1 + ex], ref[bid, :ez, :ey, :ex]), bid
 
 
-def test_u8_brick_storage_render(rt, torch_mod, orc, brain):
+@pytest.mark.parametrize("layout,B", [("LAYOUT_BRICKS", 16), ("LAYOUT_CELLS", 16), ("LAYOUT_CELLS", 8),
+                                      ("LAYOUT_CELLS", 32)])
+def test_u8_brick_storage_render(rt, torch_mod, orc, brain, layout, B):
     v = brain["np"]
     cam = brain["cams"][7]
-    gv = rt.Volume(v, brain["sp"], storage=rt.U8_BRICKSCALED, brick=16)
+    gv = rt.Volume(v, brain["sp"], storage=rt.U8_BRICKSCALED, brick=B, layout=getattr(rt, layout))
     got, c = gpu_render(rt, torch_mod, gv, brain["gtf"], cam, 256, 256, 0.5, 0.99)
-    ref = orc.render(orc.Volume.from_u8_bricks(v, brain["sp"], 16), brain["otf"], cam, 256, 256, 0.5, 0.99,
+    ref = orc.render(orc.Volume.from_u8_bricks(v, brain["sp"], B), brain["otf"], cam, 256, 256, 0.5, 0.99,
                      tie_delta=DELTA, want_band=True)
-    check(got, ref, c, "u8 bricks")
+    check(got, ref, c, f"u8 bricks {layout} B={B}")
+
+
+@pytest.mark.parametrize("B", [8, 16])
+def test_u8_brick_cells_codes_bit_exact(rt, torch_mod, orc, B):
+    """Every stored cell carries its 8 corner codes from the owning brick's
+    encoding and the block carries that brick's (lo, scale), bit for bit."""
+    dims = (37, 29, 21)
+    v = W.phantom_brain(13, dims=dims)
+    gv = rt.Volume(v, (0.9, 0.9, 1.2), storage=rt.U8_BRICKSCALED, brick=B, layout=rt.LAYOUT_CELLS)
+    torch_mod.cuda.synchronize()
+    lo, sc, codes = orc.encode_u8_bricks(v, B)
+    _, nb = orc.u8_brick_count(dims, B)
+    ref = codes.reshape(-1, B + 1, B + 1, B + 1)
+    cb = [(n + 1) // 2 + 1 for n in dims]
+    ncb = cb[0] * cb[1] * cb[2]
+    raw = gv.buf.cpu().numpy()
+    par = raw[: ncb * 8].view(np.float32).reshape(ncb, 2)
+    off = (ncb * 8 + 255) // 256 * 256
+    cells = raw[off: off + ncb * 64].reshape(ncb, 8, 8)
+    rng = np.random.default_rng(1)
+    for _ in range(400):
+        c = [int(rng.integers(0, n - 1)) for n in dims]          # an interior cell
+        b = [(x + 2) // 2 for x in c]                            # its shifted block
+        w = [(x + 2) % 2 for x in c]
+        blk = (b[2] * cb[1] + b[1]) * cb[0] + b[0]
+        own = [x // B for x in c]
+        bid = (own[2] * nb[1] + own[1]) * nb[0] + own[0]
+        assert par[blk, 0].view(np.uint32) == lo[bid].view(np.uint32)
+        assert par[blk, 1].view(np.uint32) == sc[bid].view(np.uint32)
+        got = cells[blk, w[0] | (w[1] << 1) | (w[2] << 2)]
+        for k in range(8):
+            dx, dy, dz = k & 1, (k >> 1) & 1, k >> 2
+            assert got[k] == ref[bid, c[2] - own[2] * B + dz, c[1] - own[1] * B + dy, c[0] - own[0] * B + dx]
 
 
 # ---------------------------------------------------------------------------
@@ -343,7 +378,7 @@ def test_abi_errors_with_handles(rt, torch_mod, small):
     with pytest.raises(rt.OutOfMemory):
         buf = torch_mod.empty(100, dtype=torch_mod.uint8, device="cuda")
         src = torch_mod.zeros((4, 4, 4), dtype=torch_mod.uint8, device="cuda")
-        rt.rt_create_volume(src.data_ptr(), rt.U8, (4, 4, 4), (1, 1, 1), rt.U8, 0, buf.data_ptr(), 100)
+        rt.rt_create_volume(src.data_ptr(), rt.U8, (4, 4, 4), (1, 1, 1), rt.U8, rt.LAYOUT_CELLS, 0, buf.data_ptr(), 100)
     with pytest.raises(rt.InvalidArgument):
         rt.TransferFunction(np.full((16, 4), 1.5, np.float32), 0, 1)
     with pytest.raises(rt.InvalidArgument):
