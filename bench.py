@@ -101,6 +101,178 @@ def probe_copy(gib: float = 1.0, reps: int = 10):
                       "GB_per_s": 2 * n / ms / 1e6}))
 
 
+def _timed(fn, steps, warmup):
+    import torch
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def _count(rt, jobs):
+    import torch
+    counter = torch.zeros(1, dtype=torch.int64, device="cuda")
+    rt.render_batch(jobs, sample_counter=counter)
+    torch.cuda.synchronize()
+    return int(counter.item())
+
+
+def _plain_caller(rt, jobs):
+    """The plain per-view launches with their ctypes arguments built once, so
+    the timed loop is one C call per view."""
+    import ctypes as C
+    L = rt.lib()
+    stream = rt._stream_ptr()
+    calls = []
+    for j in jobs:
+        dims = (C.c_int64 * 3)(*j.volume.dims)
+        bg = (C.c_float * 4)(*[float(x) for x in j.bg])
+        calls.append((C.c_void_p(j.volume.handle), dims, None, C.c_void_p(j.tf.handle),
+                      C.byref(rt.make_camera(j.camera)), j.width, j.height, C.c_double(j.step_vox),
+                      C.c_double(j.alpha_cutoff), bg, C.c_void_p(j.out.data_ptr()), None, stream))
+
+    def run():
+        for c in calls:
+            if L.rt_render(*c) != 0:
+                raise RuntimeError(L.rt_last_error().decode())
+    return run
+
+
+def _contract(metric, value, unit, args, ms_step, dtype, config, **extra):
+    line = {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": config}
+    line.update(extra)
+    return line
+
+
+def bench_precision(args):
+    """The 256x256x160 phantom stored as u16 (reference), f16 and per-brick
+    scaled 8-bit codes (B=16); 8 orbit views at 1024x1024, step 0.25 voxel.
+    Per storage type: throughput, algorithmic GB/s, and the two-part error
+    against the FP64 oracle on two of the views: arithmetic (GPU vs oracle on
+    the stored field, tie-aware) and storage (oracle on the stored field vs
+    oracle on the u16 original)."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_1211_5595_amd as rt
+    import workloads as W
+
+    cfg = W.CONFIG_BRAIN
+    vs, ts = cfg["volume"], cfg["tf"]
+    size, step, cutoff, n_views = 1024, 0.25, cfg["cutoff"], 8
+    vol_np = W.phantom_brain(vs.seed, dims=vs.dims, spacing=vs.spacing)
+    tf_np = W.random_tf(ts.K, ts.seed, alpha_max=ts.alpha_max)
+    cams = W.orbit_cameras(vs.dims, vs.spacing, n_views)
+    torch.cuda.set_device(0)
+    tf = rt.TransferFunction(tf_np, ts.vmin, ts.vmax)
+    otf = oracle.TF(tf_np, ts.vmin, ts.vmax)
+    err_views = [0, 3]
+    ref_u16 = {}
+    results = {}
+    for name, storage, brick, elem_bytes in [("u16", rt.U16, 0, 2), ("f16", rt.F16, 0, 2),
+                                             ("u8_brick16", rt.U8_BRICKSCALED, 16, 1)]:
+        vol = rt.Volume(vol_np, vs.spacing, storage=storage, brick=brick)
+        outs = [torch.empty((size, size, 4), dtype=torch.float32, device="cuda") for _ in range(n_views)]
+        jobs = [rt.Job(vol, tf, cam, size, size, step, cutoff, out=o) for cam, o in zip(cams, outs)]
+        plan = rt.BatchPlan(n_views, storage)
+        samples = _count(rt, jobs)
+        ms = _timed(lambda: plan.launch(jobs), args.steps, args.warmup)
+        algo = samples * 8 * elem_bytes + n_views * size * size * 16
+        if name == "u16":
+            ofield = oracle.Volume(vol_np, vs.spacing)
+        elif name == "f16":
+            ofield = oracle.Volume(vol_np.astype(np.float16).astype(np.float64), vs.spacing)
+        else:
+            ofield = oracle.Volume.from_u8_bricks(vol_np, vs.spacing, 16)
+        plan.launch(jobs)
+        torch.cuda.synchronize()
+        arith_max, arith_sum, stor_max, stor_sum, npx = 0.0, 0.0, 0.0, 0.0, 0
+        for vi in err_views:
+            got = outs[vi].cpu().numpy().astype(np.float64)
+            r = oracle.render(ofield, otf, cams[vi], size, size, step, cutoff, tie_delta=1e-6, want_band=True)
+            dist = np.maximum(np.maximum(r.band_lo - got, got - r.band_hi), 0.0)
+            arith_max = max(arith_max, float(dist.max()))
+            arith_sum += float(np.abs(got - r.image).sum())
+            if name == "u16":
+                ref_u16[vi] = r.image
+            stor = np.abs(r.image - ref_u16[vi])
+            stor_max = max(stor_max, float(stor.max()))
+            stor_sum += float(stor.sum())
+            npx += got.size
+        results[name] = {
+            "gsamples_per_s": round(samples / (ms * 1e-3) / 1e9, 3), "fps": round(n_views / (ms * 1e-3), 1),
+            "ms_per_launch": round(ms, 4), "samples_per_launch": samples,
+            "algorithmic_GB_per_s": round(algo / (ms * 1e-3) / 1e9, 1),
+            "volume_bytes": vol.nbytes,
+            "error_vs_fp64_oracle": {"arithmetic_max": arith_max, "arithmetic_mean": arith_sum / npx,
+                                     "storage_max": stor_max, "storage_mean": stor_sum / npx,
+                                     "views_checked": err_views}}
+        del plan, vol
+    line = _contract("ray samples/sec (G/s) per storage type at 1024x1024 over 256x256x160, step 0.25; "
+                     "max/mean RGBA error vs FP64 oracle", results["u16"]["gsamples_per_s"], "Gsamples/s", args,
+                     results["u16"]["ms_per_launch"], "u16/f16/u8",
+                     {"workload": "brain-precision-8x1024x1024-step0.25", "volume": list(vs.dims),
+                      "views": n_views, "image": [size, size], "step_vox": step, "alpha_cutoff": cutoff,
+                      "tf_entries": ts.K, "storage": ["u16", "f16", "u8_brick16"], "launch": "graph"},
+                     by_storage=results)
+    print(json.dumps(line), flush=True)
+
+
+def bench_batch(args):
+    """32 seeded phantoms of uneven sizes (u16), 4 random views each at
+    256..1024 square, one transfer function per phantom: one persistent
+    graph-captured launch against 128 plain per-view launches."""
+    import torch
+
+    import paper_1211_5595_amd as rt
+    import workloads as W
+
+    torch.cuda.set_device(0)
+    specs, views = W.random_views(seed=4)
+    t0 = time.perf_counter()
+    vols, tfs = [], []
+    for i, sp in enumerate(specs):
+        v = W.phantom_brain(sp.seed, dims=sp.dims, spacing=sp.spacing)
+        vols.append(rt.Volume(v, sp.spacing, storage=rt.U16))
+        tfs.append(rt.TransferFunction(W.random_tf(4096, 1000 + i, alpha_max=0.05), 0.0, 4095.0))
+        print(f"volume {i} {sp.dims} ready", file=sys.stderr, flush=True)
+    gen_s = time.perf_counter() - t0
+    jobs = [rt.Job(vols[vi], tfs[vi], cam, side, side, 0.5, 0.99) for vi, cam, side in views]
+    plan = rt.BatchPlan(len(jobs), rt.U16)
+    samples = _count(rt, jobs)
+
+    plain = _plain_caller(rt, jobs)
+    ms_graph = _timed(lambda: plan.launch(jobs), args.steps, args.warmup)
+    ms_plain = _timed(plain, args.steps, args.warmup)
+    pixels = sum(j.width * j.height for j in jobs)
+    algo = samples * 16 + pixels * 16
+    g = samples / (ms_graph * 1e-3) / 1e9
+    line = _contract("ray samples/sec (G/s): 128 views of 32 uneven u16 volumes, one persistent graph launch vs "
+                     "128 plain launches", round(g, 3), "Gsamples/s", args, ms_graph, "u16",
+                     {"workload": "uneven-batch-32vol-128views-u16", "volumes": len(specs), "views": len(jobs),
+                      "sizes": sorted({s.dims for s in specs}), "image_sides": [min(j.width for j in jobs),
+                                                                              max(j.width for j in jobs)],
+                      "step_vox": 0.5, "alpha_cutoff": 0.99, "tf_entries": 4096, "launch": "graph"},
+                     samples_per_step=samples, pixels_per_step=pixels,
+                     ms_per_step_by_form={"graph": round(ms_graph, 4), "plain_128_launches": round(ms_plain, 4)},
+                     gsamples_per_s_by_form={"graph": round(g, 3),
+                                             "plain_128_launches": round(samples / (ms_plain * 1e-3) / 1e9, 3)},
+                     speedup_vs_plain=round(ms_plain / ms_graph, 3),
+                     algorithmic_GB_per_s=round(algo / (ms_graph * 1e-3) / 1e9, 1),
+                     volume_bytes_total=sum(v.nbytes for v in vols), generation_s=round(gen_s, 1))
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -111,6 +283,10 @@ def main():
     ap.add_argument("--probe-copy", action="store_true")
     ap.add_argument("--only", choices=["batch", "plain", "graph"], default=None,
                     help="time one launch form only (for profiling)")
+    ap.add_argument("--workload", choices=["orbit", "precision", "batch"], default="orbit",
+                    help="orbit: 36 views of the 256x256x160 u16 phantom at 512^2 (default); precision: "
+                         "the same phantom as u16/f16/8-bit bricks at 1024^2, step 0.25; batch: 32 uneven "
+                         "volumes x 4 views in one launch vs 128 launches")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -127,6 +303,10 @@ def main():
     if args.probe_copy:
         probe_copy()
         return
+    if args.workload == "precision":
+        return bench_precision(args)
+    if args.workload == "batch":
+        return bench_batch(args)
 
     cfg = W.CONFIG_BRAIN
     vs, ts = cfg["volume"], cfg["tf"]
@@ -155,9 +335,7 @@ def main():
     def step_graph():
         plan.launch(jobs)
 
-    def step_plain():
-        for cam, o in zip(cams, outs):
-            rt.render(vol, tf, cam, width, height, step, cutoff, out=o)
+    step_plain = _plain_caller(rt, jobs)
 
     def timed(fn, steps, warmup):
         for _ in range(warmup):
@@ -183,11 +361,18 @@ def main():
     # single-view latency of the plain per-frame renderer (enqueue -> done, device clock)
     lat = []
     if not args.only:
+        import ctypes as C
+        L = rt.lib()
+        calls = []
+        for cam, o in zip(cams, outs):
+            calls.append((C.c_void_p(vol.handle), (C.c_int64 * 3)(*vol.dims), None, C.c_void_p(tf.handle),
+                          C.byref(rt.make_camera(cam)), width, height, C.c_double(step), C.c_double(cutoff), None,
+                          C.c_void_p(o.data_ptr()), None, rt._stream_ptr()))
         evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(3 * n_views)]
         torch.cuda.synchronize()
         for k, (a, b) in enumerate(evs):
             a.record(stream)
-            rt.render(vol, tf, cams[k % n_views], width, height, step, cutoff, out=outs[k % n_views])
+            L.rt_render(*calls[k % n_views])
             b.record(stream)
         torch.cuda.synchronize()
         lat = [a.elapsed_time(b) for a, b in evs]

@@ -105,17 +105,28 @@ def _inside_ellipsoid(x, y, z, centre, semi):
 def _paint(dims, spacing, shapes, background: float) -> np.ndarray:
     """Paint shapes (list of (centre, semi_axes, value)) in order, later shapes
     over earlier ones; "inside" is tested at voxel nodes.  Returns float64
-    ``[z][y][x]``."""
+    ``[z][y][x]``.  Each shape is evaluated only on the bounding box of its
+    cross-section with the slice (plus one node of margin); nodes outside it
+    are outside the ellipsoid, so the result equals a full evaluation."""
     nx, ny, nz = dims
+    c = box_center(dims, spacing)
     out = np.full((nz, ny, nx), background, dtype=np.float64)
     for k in range(nz):
         x, y, z = _node_coords(dims, spacing, k)
         sl = out[k]
         for centre, semi, value in shapes:
-            if abs(z - centre[2]) > semi[2]:
+            dz = (z - centre[2]) / semi[2]
+            if abs(dz) > 1.0:
                 continue
-            m = _inside_ellipsoid(x, y, z, centre, semi)
-            sl[m] = value
+            r = math.sqrt(max(0.0, 1.0 - dz * dz))
+            i0 = max(0, int(math.floor((centre[0] - semi[0] * r + c[0]) / spacing[0])) - 1)
+            i1 = min(nx, int(math.ceil((centre[0] + semi[0] * r + c[0]) / spacing[0])) + 2)
+            j0 = max(0, int(math.floor((centre[1] - semi[1] * r + c[1]) / spacing[1])) - 1)
+            j1 = min(ny, int(math.ceil((centre[1] + semi[1] * r + c[1]) / spacing[1])) + 2)
+            if i0 >= i1 or j0 >= j1:
+                continue
+            m = _inside_ellipsoid(x[:, i0:i1], y[j0:j1, :], z, centre, semi)
+            sl[j0:j1, i0:i1][m] = value
     return out
 
 
