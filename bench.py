@@ -273,6 +273,110 @@ def bench_batch(args):
     print(json.dumps(line), flush=True)
 
 
+def bench_serve(args):
+    """Poisson stream (200 req/s, seed 300) over 16 resident u16 volumes (4 of
+    each batch size, seeds 200+i); each request has its own camera, square
+    size in 256..1024 and transfer function.  Served with continuous batching
+    under a loose and a tight HBM budget, and serially (one plain render at a
+    time, in arrival order) on the same GPU; the first 200 requests are
+    warm-up.  A second, 20x faster stream shows saturation."""
+    import numpy as np
+    import torch
+
+    import paper_1211_5595_amd as rt
+    import workloads as W
+    from paper_1211_5595_amd.serve import GpuExecutor, RenderRequest, Server
+
+    torch.cuda.set_device(0)
+    sp = (0.9, 0.9, 1.2)
+    dims = [d for d in W.BATCH_SIZES for _ in range(4)]
+    ex = GpuExecutor(n_streams=3, max_batch=64)
+    for i, d in enumerate(dims):
+        ex.add_volume(i, W.phantom_brain(200 + i, dims=d, spacing=sp), sp)
+        print(f"volume {i} {d} resident", file=sys.stderr, flush=True)
+    n_req, warm = args.requests, min(200, args.requests // 10)
+    trace = W.poisson_requests(300, n_req, rate_hz=200.0, n_volumes=len(dims), volume_dims=dims, spacing=sp)
+    reqs = [RenderRequest(r["volume"], r["camera"], r["side"], r["side"],
+                          W.random_tf(4096, r["tf_seed"], alpha_max=0.05), 0.0, 4095.0, 0.5, 0.99) for r in trace]
+
+    def wait_until(t):
+        while True:
+            d = t - time.perf_counter()
+            if d <= 0:
+                return
+            time.sleep(d - 2e-4 if d > 5e-4 else 0)
+
+    def summarize(lat, samples, t_first, t_last, n):
+        a = np.array(lat) * 1e3
+        span = t_last - t_first
+        return {"p50_ms": round(float(np.percentile(a, 50)), 4), "p99_ms": round(float(np.percentile(a, 99)), 4),
+                "mean_ms": round(float(a.mean()), 4), "max_ms": round(float(a.max()), 4),
+                "requests_per_s": round(n / span, 1), "gsamples_per_s": round(samples / span / 1e9, 3),
+                "requests": n}
+
+    def served(budget, speed=1.0, n=None):
+        n = n or n_req
+        srv = Server(ex, budget, max_batch=64)
+        srv.start()
+        t0 = time.perf_counter() + 0.05
+        futs = []
+        for k in range(n):
+            target = t0 + trace[k]["t"] / speed
+            wait_until(target)
+            futs.append((target, srv.submit(reqs[k])))
+        srv.stop(drain=True)
+        w = warm if speed == 1.0 else 0
+        lat = [f.t_done - tgt for tgt, f in futs[w:]]
+        samples = sum(f.samples or 0 for _, f in futs[w:])
+        for _, f in futs:
+            f.result(0)
+        out = summarize(lat, samples, futs[w][0], max(f.t_done for _, f in futs[w:]), n - w)
+        out.update({"budget_bytes": budget, "peak_bytes": srv.peak_bytes, "batches": srv.batches,
+                    "mean_batch": round((n) / max(srv.batches, 1), 2)})
+        return out
+
+    def serial(speed=1.0, n=None):
+        n = n or n_req
+        tfs = rt.TransferFunction(reqs[0].tf_rgba, 0.0, 4095.0)
+        counter = torch.zeros(1, dtype=torch.int64, device="cuda")
+        t0 = time.perf_counter() + 0.05
+        lat, done, targets = [], [], []
+        for k in range(n):
+            r = reqs[k]
+            target = t0 + trace[k]["t"] / speed
+            wait_until(target)
+            tfs.update(r.tf_rgba)
+            if k == warm and speed == 1.0:
+                counter.zero_()
+            rt.render(ex.volumes[r.volume_id], tfs, r.camera, r.width, r.height, 0.5, 0.99, sample_counter=counter)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            lat.append(t - target)
+            done.append(t)
+            targets.append(target)
+        w = warm if speed == 1.0 else 0
+        if speed != 1.0:
+            pass
+        return summarize(lat[w:], int(counter.item()), targets[w], done[-1], n - w)
+
+    resident = ex.resident_bytes()
+    loose = served(resident + (4 << 30))
+    tight = served(resident + (64 << 20))
+    ser = serial()
+    fast_n = min(1000, n_req)
+    sat = {"speedup_of_arrivals": 20, "served": served(resident + (4 << 30), 20.0, fast_n),
+           "serial": serial(20.0, fast_n)}
+    line = _contract("p50/p99 render latency (ms), Poisson 200 req/s over 16 resident u16 volumes, continuous "
+                     "batching", loose["p99_ms"], "ms", args, loose["mean_ms"], "u16",
+                     {"workload": "serve-poisson200-16vol-u16", "volumes": len(dims), "sizes": W.BATCH_SIZES,
+                      "requests": n_req, "warmup_requests": warm, "image_sides": [256, 1024], "streams": 3,
+                      "max_batch": 64, "step_vox": 0.5, "alpha_cutoff": 0.99, "tf_entries": 4096},
+                     resident_bytes=resident, served_loose_budget=loose, served_tight_budget=tight,
+                     serial_plain=ser, saturation=sat)
+    line["higher_is_better"] = False
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -283,7 +387,8 @@ def main():
     ap.add_argument("--probe-copy", action="store_true")
     ap.add_argument("--only", choices=["batch", "plain", "graph"], default=None,
                     help="time one launch form only (for profiling)")
-    ap.add_argument("--workload", choices=["orbit", "precision", "batch"], default="orbit",
+    ap.add_argument("--requests", type=int, default=4000, help="serve workload: number of requests")
+    ap.add_argument("--workload", choices=["orbit", "precision", "batch", "serve"], default="orbit",
                     help="orbit: 36 views of the 256x256x160 u16 phantom at 512^2 (default); precision: "
                          "the same phantom as u16/f16/8-bit bricks at 1024^2, step 0.25; batch: 32 uneven "
                          "volumes x 4 views in one launch vs 128 launches")
@@ -307,6 +412,8 @@ def main():
         return bench_precision(args)
     if args.workload == "batch":
         return bench_batch(args)
+    if args.workload == "serve":
+        return bench_serve(args)
 
     cfg = W.CONFIG_BRAIN
     vs, ts = cfg["volume"], cfg["tf"]

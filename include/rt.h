@@ -160,11 +160,16 @@ rt_status rt_destroy_volume(rt_volume* vol);
 rt_status rt_tf_bytes(int K, size_t* bytes);
 
 /* Create (*tf == NULL) or update in place (*tf != NULL) a transfer function:
- * copies the host table rgba[K][4] (each value in [0,1]) into dev_buf
- * (>= rt_tf_bytes(K)) on `stream`.  An update must keep dev_buf and K.
+ * the host table rgba[K][4] (each value in [0,1]) is copied into a pinned
+ * buffer owned by the handle and uploaded to dev_buf (>= rt_tf_bytes(K),
+ * 16-byte aligned) on `stream`; the call does not wait for the upload, and
+ * the caller's table may be reused as soon as it returns.  An update keeps
+ * dev_buf and K (pass dev_buf NULL or the same buffer); it waits only for
+ * this handle's previous upload, and renders that read the table must be
+ * ordered after it (same stream, or an event).
  * Errors: RT_ERR_INVALID_ARG (NULL, K outside [2,4096], vmax <= vmin,
- * non-finite or out-of-range entries), RT_ERR_OUT_OF_MEMORY (buffer too
- * small), RT_ERR_DEVICE. */
+ * non-finite or out-of-range entries, changed buffer or K),
+ * RT_ERR_OUT_OF_MEMORY (buffer too small), RT_ERR_DEVICE. */
 rt_status rt_set_transfer_function(rt_tf** tf, const float* rgba, int K, double vmin, double vmax, void* dev_buf,
                                    size_t dev_buf_bytes, void* stream);
 rt_status rt_destroy_tf(rt_tf* tf);

@@ -30,6 +30,9 @@ struct rt_tf {
     int K;
     double vmin, vmax;
     size_t bytes;
+    void* staging;      // pinned host copy of the table for the asynchronous upload
+    hipEvent_t copied;  // recorded after the upload on the caller's stream
+    bool pending;
 };
 
 struct rt_batch_plan {
@@ -466,34 +469,57 @@ rt_status rt_set_transfer_function(rt_tf** tf, const float* rgba, int K, double 
     for (int i = 0; i < 4 * K; ++i)
         if (!(rgba[i] >= 0.0f && rgba[i] <= 1.0f)) return fail(RT_ERR_INVALID_ARG, "table entries must be in [0, 1]");
     const size_t need = (size_t)K * 16;
-    if (*tf) {
-        if ((*tf)->K != K || (dev_buf && dev_buf != (const void*)(*tf)->dev))
+    rt_tf* t = *tf;
+    if (t) {
+        if (t->K != K || (dev_buf && dev_buf != (const void*)t->dev))
             return fail(RT_ERR_INVALID_ARG, "an update must keep the buffer and K");
-        dev_buf = const_cast<float4*>((*tf)->dev);
-        dev_buf_bytes = (*tf)->bytes;
-    }
-    if (!dev_buf) return fail(RT_ERR_INVALID_ARG, "NULL device buffer");
-    if (dev_buf_bytes < need) return fail(RT_ERR_OUT_OF_MEMORY, "transfer-function buffer smaller than rt_tf_bytes");
-    if (((uintptr_t)dev_buf & 15) != 0) return fail(RT_ERR_INVALID_ARG, "transfer-function buffer must be 16-byte aligned");
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    hipError_t e = hipMemcpyAsync(dev_buf, rgba, need, hipMemcpyHostToDevice, s);
-    if (e != hipSuccess) return hip_fail(e, "transfer-function copy");
-    e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return hip_fail(e, "transfer-function copy");
-    if (!*tf) {
-        rt_tf* t = new (std::nothrow) rt_tf;
+    } else {
+        if (!dev_buf) return fail(RT_ERR_INVALID_ARG, "NULL device buffer");
+        if (dev_buf_bytes < need) return fail(RT_ERR_OUT_OF_MEMORY, "transfer-function buffer smaller than rt_tf_bytes");
+        if (((uintptr_t)dev_buf & 15) != 0) return fail(RT_ERR_INVALID_ARG, "transfer-function buffer must be 16-byte aligned");
+        t = new (std::nothrow) rt_tf;
         if (!t) return fail(RT_ERR_OUT_OF_MEMORY, "host allocation failed");
+        std::memset(t, 0, sizeof(*t));
         t->dev = static_cast<const float4*>(dev_buf);
         t->K = K;
         t->bytes = dev_buf_bytes;
-        *tf = t;
+        hipError_t e = hipHostMalloc(&t->staging, need, hipHostMallocDefault);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&t->copied, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            if (t->staging) (void)hipHostFree(t->staging);
+            delete t;
+            return hip_fail(e, "transfer-function staging");
+        }
     }
-    (*tf)->vmin = vmin;
-    (*tf)->vmax = vmax;
+    if (t->pending) {  // the previous upload of this table must have left the staging buffer
+        hipError_t e = hipEventSynchronize(t->copied);
+        if (e != hipSuccess) return hip_fail(e, "waiting for the previous table upload");
+        t->pending = false;
+    }
+    std::memcpy(t->staging, rgba, need);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = hipMemcpyAsync(const_cast<float4*>(t->dev), t->staging, need, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipEventRecord(t->copied, s);
+    if (e != hipSuccess) {
+        if (!*tf) {
+            (void)hipEventDestroy(t->copied);
+            (void)hipHostFree(t->staging);
+            delete t;
+        }
+        return hip_fail(e, "transfer-function copy");
+    }
+    t->pending = true;
+    t->vmin = vmin;
+    t->vmax = vmax;
+    *tf = t;
     return RT_OK;
 }
 
 rt_status rt_destroy_tf(rt_tf* tf) {
+    if (!tf) return RT_OK;
+    if (tf->pending) (void)hipEventSynchronize(tf->copied);
+    if (tf->copied) (void)hipEventDestroy(tf->copied);
+    if (tf->staging) (void)hipHostFree(tf->staging);
     delete tf;
     return RT_OK;
 }
