@@ -385,6 +385,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--probe-copy", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="orbit: keep the default 8x8 tiles, 16 waves")
     ap.add_argument("--only", choices=["batch", "plain", "graph"], default=None,
                     help="time one launch form only (for profiling)")
     ap.add_argument("--requests", type=int, default=4000, help="serve workload: number of requests")
@@ -428,7 +429,14 @@ def main():
     tf = rt.TransferFunction(tf_np, ts.vmin, ts.vmax)
     outs = [torch.empty((height, width, 4), dtype=torch.float32, device="cuda") for _ in range(n_views)]
     jobs = [rt.Job(vol, tf, cam, width, height, step, cutoff, out=o) for cam, o in zip(cams, outs)]
-    plan = rt.BatchPlan(n_views, rt.U16, layout=rt.LAYOUT_CELLS)
+    tuned = None
+    if not args.no_autotune:
+        from paper_1211_5595_amd import autotune
+        tuned = autotune.tune_launch(vol, tf, cams, width, height, step, cutoff, reps=3)
+        shape = dict(tile=tuple(tuned["tile"]), waves_per_block=tuned["waves_per_block"])
+    else:
+        shape = dict(tile=(8, 8), waves_per_block=16)
+    plan = rt.BatchPlan(n_views, rt.U16, layout=rt.LAYOUT_CELLS, **shape)
 
     # untimed counting pass
     counter = torch.zeros(1, dtype=torch.int64, device="cuda")
@@ -437,7 +445,7 @@ def main():
     samples_per_step = int(counter.item())
 
     def step_batch():
-        rt.render_batch(jobs)
+        rt.render_batch(jobs, **shape)
 
     def step_graph():
         plan.launch(jobs)
@@ -509,7 +517,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": workload, "volume": list(vs.dims), "spacing": list(vs.spacing), "storage": "u16",
                    "image": [width, height], "views": n_views, "step_vox": step, "alpha_cutoff": cutoff,
-                   "tf_entries": ts.K, "launch": best},
+                   "tf_entries": ts.K, "launch": best, "tile": list(shape["tile"]),
+                   "waves_per_block": shape["waves_per_block"]},
+        "autotune": tuned,
         "fps": round(fps, 1),
         "samples_per_step": samples_per_step,
         "ms_per_step_by_form": {k: round(v, 4) for k, v in ms.items()},

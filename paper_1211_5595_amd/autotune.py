@@ -1,0 +1,154 @@
+"""Autotuner for the marcher's launch shape and a volume's layout.
+
+Tunables: the ray tile of one wavefront (8x8, 16x4, 4x16, 32x2 pixels), the
+wavefronts per workgroup (4, 8, 16) and, per volume at creation, the storage
+layout (cell-packed or linear; for 8-bit brick storage the brick edge 8, 16
+or 32).  None of them changes any pixel: every candidate renders the same
+image bit for bit, so the choice is pure speed.  Each candidate is timed on
+representative views with device events; results are cached in a JSON file
+keyed by GPU architecture, storage type, layout, volume size class and image
+size class.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+import threading
+from typing import Callable, Dict, Iterable, List, Optional, Sequence, Tuple
+
+TILES: List[Tuple[int, int]] = [(8, 8), (16, 4), (4, 16), (32, 2)]
+WAVES: List[int] = [4, 8, 16]
+DEFAULT_CACHE = os.environ.get("RT_AUTOTUNE_CACHE",
+                               os.path.join(os.path.expanduser("~"), ".cache", "rtvol", "autotune.json"))
+
+
+def size_class(n: int) -> int:
+    """log2 bucket of a count (voxels or pixels)."""
+    return int(math.floor(math.log2(max(int(n), 1))))
+
+
+def launch_key(arch: str, storage: int, layout: int, dims: Sequence[int], width: int, height: int) -> str:
+    return f"{arch}|s{storage}|l{layout}|v{size_class(dims[0] * dims[1] * dims[2])}|i{size_class(width * height)}"
+
+
+class Cache:
+    """A small JSON cache, written atomically."""
+
+    def __init__(self, path: str = DEFAULT_CACHE):
+        self.path = path
+        self._lock = threading.Lock()
+        self.data: Dict[str, dict] = {}
+        try:
+            with open(path) as f:
+                self.data = json.load(f)
+        except (OSError, ValueError):
+            self.data = {}
+
+    def get(self, key: str) -> Optional[dict]:
+        return self.data.get(key)
+
+    def put(self, key: str, value: dict):
+        with self._lock:
+            self.data[key] = value
+            d = os.path.dirname(self.path)
+            if d:
+                os.makedirs(d, exist_ok=True)
+            tmp = self.path + ".tmp"
+            with open(tmp, "w") as f:
+                json.dump(self.data, f, indent=1, sort_keys=True)
+            os.replace(tmp, self.path)
+
+
+def pick_best(candidates: Iterable, measure: Callable[[object], float]) -> Tuple[object, Dict[str, float]]:
+    """Measure every candidate (milliseconds, lower is better) and return the
+    fastest with the table of timings."""
+    table, best, best_ms = {}, None, float("inf")
+    for c in candidates:
+        ms = float(measure(c))
+        table[str(c)] = ms
+        if ms < best_ms:
+            best, best_ms = c, ms
+    return best, table
+
+
+def _gpu_arch() -> str:
+    import torch
+    p = torch.cuda.get_device_properties(torch.cuda.current_device())
+    return getattr(p, "gcnArchName", p.name).split(":")[0]
+
+
+def _time_ms(fn, reps: int) -> float:
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        torch.cuda.synchronize()
+        times.append(a.elapsed_time(b))
+    times.sort()
+    return times[len(times) // 2]
+
+
+def tune_launch(volume, tf, cameras, width: int, height: int, step_vox: float = 0.5, alpha_cutoff: float = 0.99,
+                reps: int = 3, tiles: Sequence[Tuple[int, int]] = TILES, waves: Sequence[int] = WAVES,
+                cache: Optional[Cache] = None, force: bool = False) -> dict:
+    """Choose tile shape and wavefronts per workgroup for batched renders of
+    `cameras` (representative views) of this volume at width x height."""
+    from . import Job, render_batch
+    import torch
+    key = launch_key(_gpu_arch(), volume.storage, volume.layout, volume.dims, width, height)
+    if cache is not None and not force:
+        hit = cache.get(key)
+        if hit is not None:
+            return hit
+    outs = [torch.empty((height, width, 4), dtype=torch.float32, device=volume.buf.device) for _ in cameras]
+    jobs = [Job(volume, tf, c, width, height, step_vox, alpha_cutoff, out=o) for c, o in zip(cameras, outs)]
+    cands = [(t, w) for t in tiles for w in waves]
+    best, table = pick_best(cands, lambda c: _time_ms(lambda: render_batch(jobs, tile=c[0], waves_per_block=c[1]),
+                                                      reps))
+    result = {"tile": list(best[0]), "waves_per_block": best[1], "ms": table[str(best)], "timings_ms": table,
+              "key": key}
+    if cache is not None:
+        cache.put(key, result)
+    return result
+
+
+def tune_layout(values, spacing, storage: int, tf, cameras, width: int, height: int, step_vox: float = 0.5,
+                alpha_cutoff: float = 0.99, reps: int = 3, candidates: Optional[Sequence[Tuple[int, int]]] = None,
+                cache: Optional[Cache] = None, force: bool = False) -> dict:
+    """Choose the storage layout (and brick edge for 8-bit brick storage) of a
+    volume by timing batched renders of representative views.  Candidates are
+    (layout, brick) pairs."""
+    from . import Job, LAYOUT_BRICKS, LAYOUT_CELLS, LAYOUT_LINEAR, U8_BRICKSCALED, Volume, render_batch
+    import torch
+    nz, ny, nx = values.shape
+    key = f"{_gpu_arch()}|layout|s{storage}|v{size_class(nx * ny * nz)}|i{size_class(width * height)}"
+    if cache is not None and not force:
+        hit = cache.get(key)
+        if hit is not None:
+            return hit
+    if candidates is None:
+        if storage == U8_BRICKSCALED:
+            candidates = [(l, b) for l in (LAYOUT_CELLS, LAYOUT_BRICKS) for b in (8, 16, 32)]
+        else:
+            candidates = [(LAYOUT_CELLS, 0), (LAYOUT_LINEAR, 0)]
+
+    def measure(c):
+        vol = Volume(values, spacing, storage=storage, layout=c[0], brick=c[1])
+        outs = [torch.empty((height, width, 4), dtype=torch.float32, device=vol.buf.device) for _ in cameras]
+        jobs = [Job(vol, tf, cam, width, height, step_vox, alpha_cutoff, out=o) for cam, o in zip(cameras, outs)]
+        ms = _time_ms(lambda: render_batch(jobs), reps)
+        measure.bytes[str(c)] = vol.nbytes
+        return ms
+    measure.bytes = {}
+    best, table = pick_best(candidates, measure)
+    result = {"layout": best[0], "brick": best[1], "ms": table[str(best)], "timings_ms": table,
+              "bytes": measure.bytes, "key": key}
+    if cache is not None:
+        cache.put(key, result)
+    return result
