@@ -393,6 +393,8 @@ def main():
                     help="orbit: 36 views of the 256x256x160 u16 phantom at 512^2 (default); precision: "
                          "the same phantom as u16/f16/8-bit bricks at 1024^2, step 0.25; batch: 32 uneven "
                          "volumes x 4 views in one launch vs 128 launches")
+    ap.add_argument("--layout", choices=["cells", "poly", "linear"], default="cells",
+                    help="device layout of the orbit volume")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -425,7 +427,8 @@ def main():
 
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
-    vol = rt.Volume(vol_np, vs.spacing, storage=rt.U16)
+    layout = {"cells": rt.LAYOUT_CELLS, "poly": rt.LAYOUT_POLY, "linear": rt.LAYOUT_LINEAR}[args.layout]
+    vol = rt.Volume(vol_np, vs.spacing, storage=rt.U16, layout=layout)
     tf = rt.TransferFunction(tf_np, ts.vmin, ts.vmax)
     outs = [torch.empty((height, width, 4), dtype=torch.float32, device="cuda") for _ in range(n_views)]
     jobs = [rt.Job(vol, tf, cam, width, height, step, cutoff, out=o) for cam, o in zip(cams, outs)]
@@ -436,7 +439,7 @@ def main():
         shape = dict(tile=tuple(tuned["tile"]), waves_per_block=tuned["waves_per_block"])
     else:
         shape = dict(tile=(8, 8), waves_per_block=16)
-    plan = rt.BatchPlan(n_views, rt.U16, layout=rt.LAYOUT_CELLS, **shape)
+    plan = rt.BatchPlan(n_views, rt.U16, layout=layout, **shape)
 
     # untimed counting pass
     counter = torch.zeros(1, dtype=torch.int64, device="cuda")
@@ -500,7 +503,7 @@ def main():
     ms_per_launch = ms_step / launches_per_step
     achieved = bytes_per_launch / (ms_per_launch * 1e-3) / 1e9
     workload = "brain-orbit-36x512x512-u16"
-    traffic = load_traffic(workload + ":" + best)
+    traffic = load_traffic(workload + ":" + args.layout + ":" + best)
 
     line = {
         "metric": "ray samples/sec (G/s) + fps at 512x512 over 256x256x160; p50/p99 render latency",
@@ -517,7 +520,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": workload, "volume": list(vs.dims), "spacing": list(vs.spacing), "storage": "u16",
                    "image": [width, height], "views": n_views, "step_vox": step, "alpha_cutoff": cutoff,
-                   "tf_entries": ts.K, "launch": best, "tile": list(shape["tile"]),
+                   "tf_entries": ts.K, "launch": best, "layout": args.layout, "tile": list(shape["tile"]),
                    "waves_per_block": shape["waves_per_block"]},
         "autotune": tuned,
         "fps": round(fps, 1),

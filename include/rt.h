@@ -79,7 +79,10 @@ typedef enum {
                            * 8 values per cell (8x the grid); for RT_U8_BRICKSCALED the codes of a
                            * cell use its owning brick's (lo, scale), kept once per 2x2x2 block */
     RT_LAYOUT_LINEAR = 1, /* RT_U8/RT_U16/RT_F16/RT_F32: the bordered grid in C order (1x the grid) */
-    RT_LAYOUT_BRICKS = 2  /* RT_U8_BRICKSCALED: per brick the codes of local nodes -1..B+1 ((B+3)^3) */
+    RT_LAYOUT_BRICKS = 2, /* RT_U8_BRICKSCALED: per brick the codes of local nodes -1..B+1 ((B+3)^3) */
+    RT_LAYOUT_POLY = 3    /* RT_U8/RT_U16: every cell stores the 8 coefficients of its trilinear polynomial
+                           * as binary32 (exact for integer data), cells in 2x2x2 blocks (32 B per cell);
+                           * a sample then costs 7 fused multiply-adds */
 } rt_layout;
 
 /* Ray functions (Section 4.1 list; Section 2.4 for maximum intensity and

@@ -31,7 +31,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "librtvol.so")
 
 U8, U16, F16, F32, U8_BRICKSCALED = 0, 1, 2, 3, 4
-LAYOUT_CELLS, LAYOUT_LINEAR, LAYOUT_BRICKS = 0, 1, 2
+LAYOUT_CELLS, LAYOUT_LINEAR, LAYOUT_BRICKS, LAYOUT_POLY = 0, 1, 2, 3
 COMPOSITE, MIP, XRAY, AVERAGE, ISO, THRESHOLD = range(6)
 _DTYPE_CODE = {np.dtype(np.uint8): U8, np.dtype(np.uint16): U16, np.dtype(np.float16): F16,
                np.dtype(np.float32): F32}

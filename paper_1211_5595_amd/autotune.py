@@ -2,9 +2,12 @@
 
 Tunables: the ray tile of one wavefront (8x8, 16x4, 4x16, 32x2 pixels), the
 wavefronts per workgroup (4, 8, 16) and, per volume at creation, the storage
-layout (cell-packed or linear; for 8-bit brick storage the brick edge 8, 16
-or 32).  None of them changes any pixel: every candidate renders the same
-image bit for bit, so the choice is pure speed.  Each candidate is timed on
+layout (cell-packed, polynomial cells for integer data, or linear; for 8-bit
+brick storage the brick edge 8, 16 or 32).  Tile shape and wavefronts never
+change a pixel; the cell-packed and linear layouts render the same image bit
+for bit, and the polynomial layout evaluates the same interpolant in another
+rounding order (within the same tolerance of the exact result), so the choice
+is speed.  Each candidate is timed on
 representative views with device events; results are cached in a JSON file
 keyed by GPU architecture, storage type, layout, volume size class and image
 size class.
@@ -124,7 +127,8 @@ def tune_layout(values, spacing, storage: int, tf, cameras, width: int, height: 
     """Choose the storage layout (and brick edge for 8-bit brick storage) of a
     volume by timing batched renders of representative views.  Candidates are
     (layout, brick) pairs."""
-    from . import Job, LAYOUT_BRICKS, LAYOUT_CELLS, LAYOUT_LINEAR, U8_BRICKSCALED, Volume, render_batch
+    from . import (Job, LAYOUT_BRICKS, LAYOUT_CELLS, LAYOUT_LINEAR, LAYOUT_POLY, U8, U16, U8_BRICKSCALED, Volume,
+                   render_batch)
     import torch
     nz, ny, nx = values.shape
     key = f"{_gpu_arch()}|layout|s{storage}|v{size_class(nx * ny * nz)}|i{size_class(width * height)}"
@@ -135,6 +139,8 @@ def tune_layout(values, spacing, storage: int, tf, cameras, width: int, height: 
     if candidates is None:
         if storage == U8_BRICKSCALED:
             candidates = [(l, b) for l in (LAYOUT_CELLS, LAYOUT_BRICKS) for b in (8, 16, 32)]
+        elif storage in (U8, U16):
+            candidates = [(LAYOUT_CELLS, 0), (LAYOUT_POLY, 0), (LAYOUT_LINEAR, 0)]
         else:
             candidates = [(LAYOUT_CELLS, 0), (LAYOUT_LINEAR, 0)]
 

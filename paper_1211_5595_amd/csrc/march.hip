@@ -43,26 +43,33 @@ struct Ray {
 
 // Step 1 of the ray-casting process: the ray path.  Returns false for a ray
 // that misses the box [0, box_hi].
-__device__ __forceinline__ bool setup_ray(const ViewDesc& V, int i, int j, Ray& R) {
+// Member-wise copy of a float-float value from any address space.
+template <class T>
+__device__ __forceinline__ ff ldff(const T& x) {
+    return ff{x.hi, x.lo};
+}
+
+template <class VD>
+__device__ __forceinline__ bool setup_ray(const VD& V, int i, int j, Ray& R) {
     const float a = (float)(2 * i + 1 - V.W);
     const float b = (float)(V.H - 2 * j - 1);
     ff o[3], d[3];
     if (V.perspective) {
         ff r[3];
 #pragma unroll
-        for (int ax = 0; ax < 3; ++ax) r[ax] = ff_add(ff_add(V.w[ax], ff_mul_f(V.U[ax], a)), ff_mul_f(V.V[ax], b));
+        for (int ax = 0; ax < 3; ++ax) r[ax] = ff_add(ff_add(ldff(V.w[ax]), ff_mul_f(ldff(V.U[ax]), a)), ff_mul_f(ldff(V.V[ax]), b));
         ff n2 = ff_add(ff_add(ff_mul(r[0], r[0]), ff_mul(r[1], r[1])), ff_mul(r[2], r[2]));
         ff inv = ff_div(ff_make(1.0f), ff_sqrt(n2));
 #pragma unroll
         for (int ax = 0; ax < 3; ++ax) {
-            o[ax] = V.eye[ax];
+            o[ax] = ldff(V.eye[ax]);
             d[ax] = ff_mul(r[ax], inv);
         }
     } else {
 #pragma unroll
         for (int ax = 0; ax < 3; ++ax) {
-            o[ax] = ff_add(ff_add(V.eye[ax], ff_mul_f(V.U[ax], a)), ff_mul_f(V.V[ax], b));
-            d[ax] = V.w[ax];
+            o[ax] = ff_add(ff_add(ldff(V.eye[ax]), ff_mul_f(ldff(V.U[ax]), a)), ff_mul_f(ldff(V.V[ax]), b));
+            d[ax] = ldff(V.w[ax]);
         }
     }
     // Slab test against the closed box.
@@ -70,12 +77,12 @@ __device__ __forceinline__ bool setup_ray(const ViewDesc& V, int i, int j, Ray& 
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
         if (d[ax].hi == 0.0f) {
-            if (ff_lt(o[ax], ff_make(0.0f)) || ff_lt(V.box_hi[ax], o[ax])) return false;
+            if (ff_lt(o[ax], ff_make(0.0f)) || ff_lt(ldff(V.box_hi[ax]), o[ax])) return false;
             continue;
         }
         ff rd = ff_div(ff_make(1.0f), d[ax]);
         ff t0 = ff_mul(ff_neg(o[ax]), rd);
-        ff t1 = ff_mul(ff_sub(V.box_hi[ax], o[ax]), rd);
+        ff t1 = ff_mul(ff_sub(ldff(V.box_hi[ax]), o[ax]), rd);
         if (ff_lt(t1, t0)) {
             ff x = t0;
             t0 = t1;
@@ -88,15 +95,15 @@ __device__ __forceinline__ bool setup_ray(const ViewDesc& V, int i, int j, Ray& 
     if (!ff_lt(tnear, tout)) return false;
     // Evenly spaced samples: m segments of dt and a remainder r in [0, dt).
     const ff L = ff_sub(tout, tnear);
-    int m = ff_floor_int(ff_div(L, V.dt));
-    ff r = ff_sub(L, ff_mul_f(V.dt, (float)m));
+    int m = ff_floor_int(ff_div(L, ldff(V.dt)));
+    ff r = ff_sub(L, ff_mul_f(ldff(V.dt), (float)m));
     if (r.hi < 0.0f) {
         m -= 1;
-        r = ff_add(r, V.dt);
+        r = ff_add(r, ldff(V.dt));
     }
-    if (!ff_lt(r, V.dt)) {
+    if (!ff_lt(r, ldff(V.dt))) {
         m += 1;
-        r = ff_sub(r, V.dt);
+        r = ff_sub(r, ldff(V.dt));
     }
     if (m < 0) {
         m = 0;
@@ -104,22 +111,22 @@ __device__ __forceinline__ bool setup_ray(const ViewDesc& V, int i, int j, Ray& 
     }
     R.m = m;
     // First sample at tnear + dt/2; positions in padded index space q + 1.
-    const ff s0 = ff_add(tnear, ff_mul_f(V.dt, 0.5f));
+    const ff s0 = ff_add(tnear, ff_mul_f(ldff(V.dt), 0.5f));
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
         ff p = ff_add(o[ax], ff_mul(s0, d[ax]));
-        R.Q[ax] = ff_to_fixed32(ff_add(ff_mul(p, V.inv_sp[ax]), ff_make(1.0f)));
-        R.dQ[ax] = ff_to_fixed32(ff_mul(ff_mul(V.dt, d[ax]), V.inv_sp[ax]));
+        R.Q[ax] = ff_to_fixed32(ff_add(ff_mul(p, ldff(V.inv_sp[ax])), ff_make(1.0f)));
+        R.dQ[ax] = ff_to_fixed32(ff_mul(ff_mul(ldff(V.dt), d[ax]), ldff(V.inv_sp[ax])));
     }
     R.wp = 0.0f;
     if (r.hi > 0.0f) {
-        const ff sp = ff_add(ff_add(tnear, ff_mul_f(V.dt, (float)m)), ff_mul_f(r, 0.5f));
+        const ff sp = ff_add(ff_add(tnear, ff_mul_f(ldff(V.dt), (float)m)), ff_mul_f(r, 0.5f));
 #pragma unroll
         for (int ax = 0; ax < 3; ++ax) {
             ff p = ff_add(o[ax], ff_mul(sp, d[ax]));
-            R.Qp[ax] = ff_to_fixed32(ff_add(ff_mul(p, V.inv_sp[ax]), ff_make(1.0f)));
+            R.Qp[ax] = ff_to_fixed32(ff_add(ff_mul(p, ldff(V.inv_sp[ax])), ff_make(1.0f)));
         }
-        R.wp = r.hi / V.dt.hi;
+        R.wp = r.hi / ldff(V.dt).hi;
     }
     return true;
 }
@@ -192,7 +199,8 @@ struct Sampler<KIND, LAYOUT_LINEAR> {
     struct Raw {
         float c[8];
     };
-    static __device__ __forceinline__ Raw load(__amdgpu_buffer_rsrc_t r, const VolDev& vol, const Corners& cn,
+    template <class VOL>
+    static __device__ __forceinline__ Raw load(__amdgpu_buffer_rsrc_t r, const VOL& vol, const Corners& cn,
                                                const long long Q[3]) {
         using E = Elem<KIND>;
         const uint32_t off = __umul24(hiword(Q[2]), vol.sz) + __umul24(hiword(Q[1]), vol.sy) + hiword(Q[0]) * E::bytes;
@@ -290,7 +298,8 @@ template <int KIND>
 struct Sampler<KIND, LAYOUT_CELLS> {
     using B = CellBits<KIND>;
     using Raw = typename B::Raw;
-    static __device__ __forceinline__ Raw load(__amdgpu_buffer_rsrc_t r, const VolDev& vol, const Corners&,
+    template <class VOL>
+    static __device__ __forceinline__ Raw load(__amdgpu_buffer_rsrc_t r, const VOL& vol, const Corners&,
                                                const long long Q[3]) {
         const uint32_t ix = hiword(Q[0]), iy = hiword(Q[1]), iz = hiword(Q[2]);
         const uint32_t blk = __umul24(__umul24(iz >> 1, (uint32_t)vol.nb[1]) + (iy >> 1), (uint32_t)vol.nb[0]) + (ix >> 1);
@@ -304,6 +313,29 @@ struct Sampler<KIND, LAYOUT_CELLS> {
     }
 };
 
+// Polynomial cells (integer data): 8 binary32 coefficients per cell; the
+// trilinear value is the polynomial evaluated with 7 fused multiply-adds.
+template <int KIND>
+struct Sampler<KIND, LAYOUT_POLY> {
+    using B = CellBits<ST_F32>;
+    using Raw = typename B::Raw;
+    template <class VOL>
+    static __device__ __forceinline__ Raw load(__amdgpu_buffer_rsrc_t r, const VOL& vol, const Corners&,
+                                               const long long Q[3]) {
+        const uint32_t ix = hiword(Q[0]), iy = hiword(Q[1]), iz = hiword(Q[2]);
+        const uint32_t blk = __umul24(__umul24(iz >> 1, (uint32_t)vol.nb[1]) + (iy >> 1), (uint32_t)vol.nb[0]) + (ix >> 1);
+        const uint32_t w = (ix & 1u) | ((iy & 1u) << 1) | ((iz & 1u) << 2);
+        return B::load(r, (blk << 8) | (w << 5));
+    }
+    static __device__ __forceinline__ float value(const Raw& w, float fx, float fy, float fz) {
+        const f32x4 a = __builtin_bit_cast(f32x4, w.a), b = __builtin_bit_cast(f32x4, w.b);
+        // a = (p0, px, py, pz), b = (pxy, pxz, pyz, pxyz)
+        const float cx = fmaf(fmaf(b[3], fz, b[0]), fy, fmaf(b[1], fz, a[1]));  // coefficient of fx
+        const float c0 = fmaf(fmaf(b[2], fz, a[2]), fy, fmaf(a[3], fz, a[0]));  // value at fx = 0
+        return fmaf(cx, fx, c0);
+    }
+};
+
 // Cell-packed brick-scaled 8-bit codes: cell blocks shifted by one cell so
 // each lies inside one brick; 8 codes per cell plus the block's (lo, scale).
 template <>
@@ -312,7 +344,8 @@ struct Sampler<ST_U8B, LAYOUT_CELLS> {
         u32x2 w;
         float2 par;
     };
-    static __device__ __forceinline__ Raw load(__amdgpu_buffer_rsrc_t r, const VolDev& vol, const Corners&,
+    template <class VOL>
+    static __device__ __forceinline__ Raw load(__amdgpu_buffer_rsrc_t r, const VOL& vol, const Corners&,
                                                const long long Q[3]) {
         const uint32_t ix = hiword(Q[0]) + 1u, iy = hiword(Q[1]) + 1u, iz = hiword(Q[2]) + 1u;
         const uint32_t blk = __umul24(__umul24(iz >> 1, (uint32_t)vol.nb[1]) + (iy >> 1), (uint32_t)vol.nb[0]) + (ix >> 1);
@@ -337,7 +370,8 @@ struct Sampler<ST_U8B, LAYOUT_BRICKS> {
         float c[8];
         float2 par;
     };
-    static __device__ __forceinline__ Raw load(__amdgpu_buffer_rsrc_t r, const VolDev& vol, const Corners& cn,
+    template <class VOL>
+    static __device__ __forceinline__ Raw load(__amdgpu_buffer_rsrc_t r, const VOL& vol, const Corners& cn,
                                                const long long Q[3]) {
         const uint32_t ix = hiword(Q[0]), iy = hiword(Q[1]), iz = hiword(Q[2]);
         const int cx = min(max((int)ix - 1, 0), vol.n[0] - 2) >> vol.bshift;
@@ -378,10 +412,10 @@ __device__ __forceinline__ float4 classify(const float4* __restrict__ s_tf, floa
     return make_float4(lerp(t0.x, t1.x, g), lerp(t0.y, t1.y, g), lerp(t0.z, t1.z, g), lerp(t0.w, t1.w, g));
 }
 
-// Step 3: compositing one pixel's ray.  The cell of sample k+1 is requested
-// before sample k is interpolated, classified and composited.
-template <int KIND, int LAYOUT>
-__device__ __forceinline__ void march_pixel(const ViewDesc& V, const float4* __restrict__ s_tf,
+// Step 3: compositing one pixel's ray.  Lanes whose rays have stopped are
+// masked off; the wavefront leaves the loop when no lane is left.
+template <int KIND, int LAYOUT, class VD>
+__device__ __forceinline__ void march_pixel(const VD& V, const float4* __restrict__ s_tf,
                                             __amdgpu_buffer_rsrc_t rs, const Corners& cn, int i, int j,
                                             float4& px, int& count) {
     using S = Sampler<KIND, LAYOUT>;
@@ -440,8 +474,8 @@ __device__ __forceinline__ void load_tf(float4* s_tf, const float4* __restrict__
 }
 
 // One workgroup block of a view: wave w renders tile (w % bw, w / bw) of the block.
-template <int KIND, int LAYOUT>
-__device__ __forceinline__ void render_block(const ViewDesc& V, const float4* __restrict__ s_tf, int blk,
+template <int KIND, int LAYOUT, class VD>
+__device__ __forceinline__ void render_block(const VD& V, const float4* __restrict__ s_tf, int blk,
                                              const LaunchShape& ls, int tw_shift,
                                              unsigned long long* __restrict__ counter) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -454,7 +488,7 @@ __device__ __forceinline__ void render_block(const ViewDesc& V, const float4* __
     int count = 0;
     if (i < V.W && j < V.H) {
         float4 px;
-        march_pixel<KIND, LAYOUT>(V, s_tf, rs, cn, i, j, px, count);
+        march_pixel<KIND, LAYOUT, VD>(V, s_tf, rs, cn, i, j, px, count);
         const size_t p = (size_t)j * V.W + i;
         reinterpret_cast<float4*>(V.out)[p] = px;
         if (V.counts) V.counts[p] = count;
@@ -483,27 +517,36 @@ __global__ void RT_MARCH_ATTRS march_plain_kernel(const ViewDesc V, const Launch
     extern __shared__ float4 s_tf[];
     load_tf(s_tf, V.tf, V.K);
     __syncthreads();
-    render_block<KIND, LAYOUT>(V, s_tf, xcd_remap(blockIdx.x, gridDim.x), ls, tw_shift, counter);
+    render_block<KIND, LAYOUT, ViewDesc>(V, s_tf, xcd_remap(blockIdx.x, gridDim.x), ls, tw_shift, counter);
 }
 
 // Persistent batched marcher: workgroups claim blocks from a queue in the
 // workspace until it runs dry; the view of a block is found by binary search
 // over the per-view block prefix.  The transfer function in LDS is reloaded
 // only when the claimed view uses a different table.
+// The job table, block prefix and header do not change while a batch kernel
+// runs (only the queue word is written, and never read through these
+// pointers), so they are read through the constant address space: scalar
+// loads, and descriptors the compiler knows to be wave-uniform.
+typedef __attribute__((address_space(4))) const ViewDesc CViewDesc;
+typedef __attribute__((address_space(4))) const int CInt;
+typedef __attribute__((address_space(4))) const BatchHeader CBatchHeader;
+
 template <int KIND, int LAYOUT>
 __global__ void RT_MARCH_ATTRS march_batch_kernel(char* __restrict__ ws, const LaunchShape ls, int tw_shift,
                                                    int tf_entries) {
     extern __shared__ float4 s_tf[];
     int* s_claim = reinterpret_cast<int*>(s_tf + tf_entries);
-    BatchHeader* hdr = reinterpret_cast<BatchHeader*>(ws);
-    const int* __restrict__ prefix = reinterpret_cast<const int*>(ws + kBatchHeaderBytes);
-    const ViewDesc* __restrict__ jobs = reinterpret_cast<const ViewDesc*>(ws + kBatchHeaderBytes + kBatchPrefixBytes);
-    const int n_jobs = (int)__builtin_amdgcn_readfirstlane(hdr->n_jobs);
+    unsigned int* queue = &reinterpret_cast<BatchHeader*>(ws)->queue;
+    const CBatchHeader* hdr = (const CBatchHeader*)(ws);
+    const CInt* prefix = (const CInt*)(ws + kBatchHeaderBytes);
+    const CViewDesc* jobs = (const CViewDesc*)(ws + kBatchHeaderBytes + kBatchPrefixBytes);
+    const int n_jobs = (int)hdr->n_jobs;
     unsigned long long* counter = hdr->counter;
     const int total = prefix[n_jobs];
     const float4* cur_tf = nullptr;
     for (;;) {
-        if (threadIdx.x == 0) s_claim[0] = (int)atomicAdd(&hdr->queue, 1u);
+        if (threadIdx.x == 0) s_claim[0] = (int)atomicAdd(queue, 1u);
         __syncthreads();
         const int g = __builtin_amdgcn_readfirstlane(s_claim[0]);
         if (g >= total) break;
@@ -513,14 +556,13 @@ __global__ void RT_MARCH_ATTRS march_batch_kernel(char* __restrict__ ws, const L
             if (prefix[mid] <= g) lo = mid;
             else hi = mid;
         }
-        const int jdx = __builtin_amdgcn_readfirstlane(lo);
-        const ViewDesc& V = jobs[jdx];
+        const CViewDesc& V = jobs[lo];
         if (V.tf != cur_tf) {
             cur_tf = V.tf;
             load_tf(s_tf, V.tf, V.K);
             __syncthreads();
         }
-        render_block<KIND, LAYOUT>(V, s_tf, g - prefix[jdx], ls, tw_shift, counter);
+        render_block<KIND, LAYOUT, CViewDesc>(V, s_tf, g - prefix[lo], ls, tw_shift, counter);
         __syncthreads();
     }
 }
@@ -573,11 +615,13 @@ hipError_t launch_march_plain(const ViewDesc& v, const LaunchShape& ls, unsigned
     const int L = v.vol.layout;
     switch (v.vol.kind) {
         case ST_U8:
-            return L == LAYOUT_CELLS ? plain_launch<ST_U8, LAYOUT_CELLS>(v, ls, counter, s)
-                                     : plain_launch<ST_U8, LAYOUT_LINEAR>(v, ls, counter, s);
+            return L == LAYOUT_CELLS  ? plain_launch<ST_U8, LAYOUT_CELLS>(v, ls, counter, s)
+                   : L == LAYOUT_POLY ? plain_launch<ST_U8, LAYOUT_POLY>(v, ls, counter, s)
+                                      : plain_launch<ST_U8, LAYOUT_LINEAR>(v, ls, counter, s);
         case ST_U16:
-            return L == LAYOUT_CELLS ? plain_launch<ST_U16, LAYOUT_CELLS>(v, ls, counter, s)
-                                     : plain_launch<ST_U16, LAYOUT_LINEAR>(v, ls, counter, s);
+            return L == LAYOUT_CELLS  ? plain_launch<ST_U16, LAYOUT_CELLS>(v, ls, counter, s)
+                   : L == LAYOUT_POLY ? plain_launch<ST_U16, LAYOUT_POLY>(v, ls, counter, s)
+                                      : plain_launch<ST_U16, LAYOUT_LINEAR>(v, ls, counter, s);
         case ST_F16:
             return L == LAYOUT_CELLS ? plain_launch<ST_F16, LAYOUT_CELLS>(v, ls, counter, s)
                                      : plain_launch<ST_F16, LAYOUT_LINEAR>(v, ls, counter, s);
@@ -593,14 +637,16 @@ hipError_t launch_march_plain(const ViewDesc& v, const LaunchShape& ls, unsigned
 
 hipError_t launch_march_batch(int kind, int layout, void* workspace, int grid, const LaunchShape& ls, int max_k,
                               hipStream_t s) {
-    const bool C = layout == LAYOUT_CELLS;
+    const bool C = layout == LAYOUT_CELLS, P = layout == LAYOUT_POLY;
     switch (kind) {
         case ST_U8:
-            return C ? batch_launch<ST_U8, LAYOUT_CELLS>(workspace, grid, ls, max_k, s)
-                     : batch_launch<ST_U8, LAYOUT_LINEAR>(workspace, grid, ls, max_k, s);
+            return C   ? batch_launch<ST_U8, LAYOUT_CELLS>(workspace, grid, ls, max_k, s)
+                   : P ? batch_launch<ST_U8, LAYOUT_POLY>(workspace, grid, ls, max_k, s)
+                       : batch_launch<ST_U8, LAYOUT_LINEAR>(workspace, grid, ls, max_k, s);
         case ST_U16:
-            return C ? batch_launch<ST_U16, LAYOUT_CELLS>(workspace, grid, ls, max_k, s)
-                     : batch_launch<ST_U16, LAYOUT_LINEAR>(workspace, grid, ls, max_k, s);
+            return C   ? batch_launch<ST_U16, LAYOUT_CELLS>(workspace, grid, ls, max_k, s)
+                   : P ? batch_launch<ST_U16, LAYOUT_POLY>(workspace, grid, ls, max_k, s)
+                       : batch_launch<ST_U16, LAYOUT_LINEAR>(workspace, grid, ls, max_k, s);
         case ST_F16:
             return C ? batch_launch<ST_F16, LAYOUT_CELLS>(workspace, grid, ls, max_k, s)
                      : batch_launch<ST_F16, LAYOUT_LINEAR>(workspace, grid, ls, max_k, s);

@@ -102,6 +102,38 @@ __global__ void __launch_bounds__(256) relayout_cells_kernel(const typename Src<
     }
 }
 
+// Polynomial cells: as relayout_cells_kernel, but the 8 stored values are the
+// coefficients of the cell's trilinear polynomial, formed in integer
+// arithmetic from integer corners and stored as exact binary32 values.
+template <int SRC>
+__global__ void __launch_bounds__(256) relayout_poly_kernel(const typename Src<SRC>::T* __restrict__ src,
+                                                             float4* __restrict__ dst, int nx, int ny, int nz, int nbx,
+                                                             int nby, int nbz) {
+    const size_t total = (size_t)8 * nbx * nby * nbz;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+        const int within = (int)(e & 7);
+        const size_t blk = e >> 3;
+        const int bx = (int)(blk % nbx);
+        const size_t t = blk / nbx;
+        const int by = (int)(t % nby), bz = (int)(t / nby);
+        const int cx = 2 * bx + (within & 1), cy = 2 * by + ((within >> 1) & 1), cz = 2 * bz + (within >> 2);
+        int c[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int i = min(max(cx + (k & 1) - 1, 0), nx - 1);
+            const int j = min(max(cy + ((k >> 1) & 1) - 1, 0), ny - 1);
+            const int l = min(max(cz + (k >> 2) - 1, 0), nz - 1);
+            c[k] = (int)src[((size_t)l * ny + j) * nx + i];
+        }
+        const int p0 = c[0], px = c[1] - c[0], py = c[2] - c[0], pz = c[4] - c[0];
+        const int pxy = c[3] - c[1] - c[2] + c[0], pxz = c[5] - c[1] - c[4] + c[0];
+        const int pyz = c[6] - c[2] - c[4] + c[0];
+        const int pxyz = c[7] - c[3] - c[5] - c[6] + c[1] + c[2] + c[4] - c[0];
+        dst[2 * e] = make_float4((float)p0, (float)px, (float)py, (float)pz);
+        dst[2 * e + 1] = make_float4((float)pxy, (float)pxz, (float)pyz, (float)pxyz);
+    }
+}
+
 // One workgroup per brick: min and max over nodes [b*B, min(b*B+B, n-1)].
 template <int SRC>
 __global__ void __launch_bounds__(256) brick_minmax_kernel(const typename Src<SRC>::T* __restrict__ src, int nx,
@@ -308,6 +340,24 @@ hipError_t u8b_cells_dispatch(const void* src, const int32_t n[3], int B, const 
 }
 
 }  // namespace
+
+hipError_t launch_relayout_poly(const void* src, int src_kind, const int32_t n[3], const int32_t nb[3], void* dst,
+                                hipStream_t s) {
+    const size_t total = (size_t)8 * nb[0] * nb[1] * nb[2];
+    float4* d = static_cast<float4*>(dst);
+    switch (src_kind) {
+        case ST_U8:
+            hipLaunchKernelGGL(relayout_poly_kernel<ST_U8>, dim3(grid_for(total, 256)), dim3(256), 0, s,
+                               static_cast<const unsigned char*>(src), d, n[0], n[1], n[2], nb[0], nb[1], nb[2]);
+            break;
+        case ST_U16:
+            hipLaunchKernelGGL(relayout_poly_kernel<ST_U16>, dim3(grid_for(total, 256)), dim3(256), 0, s,
+                               static_cast<const unsigned short*>(src), d, n[0], n[1], n[2], nb[0], nb[1], nb[2]);
+            break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
 
 hipError_t launch_relayout_u8b_cells(const void* src, int src_kind, const int32_t n[3], int B, const int32_t nb[3],
                                      float2* brick_par, const int32_t ncb[3], float2* block_par,

@@ -97,8 +97,9 @@ rt_status compute_layout(const int64_t dims[3], int storage, int layout, int bri
     std::memset(&L, 0, sizeof(L));
     if (storage < RT_U8 || storage > RT_U8_BRICKSCALED) return fail(RT_ERR_INVALID_ARG, "unknown storage type");
     const bool u8b = storage == RT_U8_BRICKSCALED;
+    const bool integer = storage == RT_U8 || storage == RT_U16;
     if (u8b ? (layout != RT_LAYOUT_CELLS && layout != RT_LAYOUT_BRICKS)
-            : (layout != RT_LAYOUT_CELLS && layout != RT_LAYOUT_LINEAR))
+            : (layout != RT_LAYOUT_CELLS && layout != RT_LAYOUT_LINEAR && !(integer && layout == RT_LAYOUT_POLY)))
         return fail(RT_ERR_INVALID_ARG, "layout not available for this storage type");
     if (u8b) {
         if (brick != 8 && brick != 16 && brick != 32)
@@ -145,11 +146,11 @@ rt_status compute_layout(const int64_t dims[3], int storage, int layout, int bri
         L.total = round256(L.brick_par_offset + nbt * sizeof(float2));
         return RT_OK;
     }
-    const int e = elem_bytes(storage);
+    const int e = layout == RT_LAYOUT_POLY ? 4 : elem_bytes(storage);  // poly cells hold binary32 coefficients
     const size_t px = (size_t)dims[0] + 2, py = (size_t)dims[1] + 2, pz = (size_t)dims[2] + 2;
     L.data_offset = 0;
-    if (layout == RT_LAYOUT_CELLS) {
-        L.layout = LAYOUT_CELLS;
+    if (layout == RT_LAYOUT_CELLS || layout == RT_LAYOUT_POLY) {
+        L.layout = layout == RT_LAYOUT_POLY ? LAYOUT_POLY : LAYOUT_CELLS;
         size_t nbt = 1;
         for (int a = 0; a < 3; ++a) {
             L.nb[a] = (int32_t)((dims[a] + 2) / 2);  // padded cells 0..n, rounded up to pairs
@@ -407,6 +408,8 @@ rt_status rt_create_volume(const void* src_dev, int src_dtype, const int64_t dim
         const bool ok = storage == RT_F16 || storage == RT_F32 || (storage == RT_U16 && src_dtype <= RT_U16) ||
                         (storage == RT_U8 && src_dtype == RT_U8);
         if (!ok) return fail(RT_ERR_INVALID_ARG, "conversion to this storage type would lose information");
+        if (layout == RT_LAYOUT_POLY && src_dtype > RT_U16)
+            return fail(RT_ERR_INVALID_ARG, "the polynomial layout needs integer source data");
     }
     const int32_t n[3] = {(int32_t)dims[0], (int32_t)dims[1], (int32_t)dims[2]};
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -422,6 +425,8 @@ rt_status rt_create_volume(const void* src_dev, int src_dtype, const int64_t dim
                                 reinterpret_cast<unsigned char*>(base + L.data_offset), s);
     else if (L.layout == LAYOUT_CELLS)
         e = launch_relayout_cells(src_dev, src_dtype, storage, n, L.nb, base, s);
+    else if (L.layout == LAYOUT_POLY)
+        e = launch_relayout_poly(src_dev, src_dtype, n, L.nb, base, s);
     else
         e = launch_relayout_linear(src_dev, src_dtype, storage, n, base, s);
     if (e != hipSuccess) return hip_fail(e, "relayout launch");
@@ -587,7 +592,8 @@ rt_status rt_batch_plan_create(int max_jobs, int storage, int layout, void* work
     if (ws_bytes < batch_ws_bytes(max_jobs)) return fail(RT_ERR_OUT_OF_MEMORY, "workspace smaller than rt_batch_workspace_bytes");
     if (storage < RT_U8 || storage > RT_U8_BRICKSCALED) return fail(RT_ERR_INVALID_ARG, "unknown storage type");
     if (storage == RT_U8_BRICKSCALED ? (layout != RT_LAYOUT_CELLS && layout != RT_LAYOUT_BRICKS)
-                                     : (layout != RT_LAYOUT_CELLS && layout != RT_LAYOUT_LINEAR))
+                                     : (layout != RT_LAYOUT_CELLS && layout != RT_LAYOUT_LINEAR &&
+                                        !((storage == RT_U8 || storage == RT_U16) && layout == RT_LAYOUT_POLY)))
         return fail(RT_ERR_INVALID_ARG, "layout not available for this storage type");
     LaunchShape ls;
     rt_status st = make_shape(opts, ls);
@@ -598,7 +604,10 @@ rt_status rt_batch_plan_create(int max_jobs, int storage, int layout, void* work
     std::memset(p, 0, sizeof(*p));
     p->max_jobs = max_jobs;
     p->kind = (storage == RT_U8_BRICKSCALED ? ST_U8B : storage) * 4 +
-              (layout == RT_LAYOUT_LINEAR ? LAYOUT_LINEAR : (layout == RT_LAYOUT_BRICKS ? LAYOUT_BRICKS : LAYOUT_CELLS));
+              (layout == RT_LAYOUT_LINEAR   ? LAYOUT_LINEAR
+               : layout == RT_LAYOUT_BRICKS ? LAYOUT_BRICKS
+               : layout == RT_LAYOUT_POLY   ? LAYOUT_POLY
+                                            : LAYOUT_CELLS);
     p->ls = ls;
     p->grid = batch_persistent_grid(ls, kMaxK);
     p->ws = workspace;

@@ -14,7 +14,7 @@ struct ff {
 };
 
 enum StorageKind : int { ST_U8 = 0, ST_U16 = 1, ST_F16 = 2, ST_F32 = 3, ST_U8B = 4 };
-enum LayoutKind : int { LAYOUT_CELLS = 0, LAYOUT_LINEAR = 1, LAYOUT_BRICKS = 2 };
+enum LayoutKind : int { LAYOUT_CELLS = 0, LAYOUT_LINEAR = 1, LAYOUT_BRICKS = 2, LAYOUT_POLY = 3 };
 
 // Device view of a volume in storage layout.  All layouts work on the
 // padded grid: nodes P = 0..n+1 per axis, node P holding node clamp(P-1)
@@ -26,6 +26,10 @@ enum LayoutKind : int { LAYOUT_CELLS = 0, LAYOUT_LINEAR = 1, LAYOUT_BRICKS = 2 }
 //    line for 16-bit storage), blocks in x-fastest order.  One vector load
 //    per sample, and the cache lines a ray tile touches do not depend on
 //    the viewing direction.
+//  LAYOUT_POLY (U8/U16): like LAYOUT_CELLS, but a cell holds the binary32
+//    coefficients p0, px, py, pz, pxy, pxz, pyz, pxyz of its trilinear
+//    polynomial v = p0 + px fx + py fy + pz fz + pxy fx fy + pxz fx fz
+//    + pyz fy fz + pxyz fx fy fz (sums of at most 8 integer corners: exact).
 //  LAYOUT_LINEAR (U8/U16/F16/F32): the padded grid in C order.
 //    For U8B the cell blocks are shifted by one cell (block = (C+1)/2) so a
 //    block never straddles a brick (B even); each block keeps the (lo,
@@ -110,6 +114,8 @@ hipError_t launch_relayout_linear(const void* src, int src_kind, int dst_kind, c
                                   hipStream_t s);
 hipError_t launch_relayout_cells(const void* src, int src_kind, int dst_kind, const int32_t n[3],
                                  const int32_t nb[3], void* dst, hipStream_t s);
+hipError_t launch_relayout_poly(const void* src, int src_kind, const int32_t n[3], const int32_t nb[3], void* dst,
+                                hipStream_t s);
 hipError_t launch_relayout_u8b(const void* src, int src_kind, const int32_t n[3], int B, const int32_t nb[3],
                                float2* brick_par, unsigned char* codes, hipStream_t s);
 // Cell-packed 8-bit codes: per-brick (lo, scale) into brick_par (nbricks),

@@ -51,6 +51,9 @@ def test_volume_bytes(rt):
     assert rt.rt_volume_bytes((256, 256, 160), rt.U16) == r256(129 * 129 * 81 * 8 * 8 * 2)
     assert rt.rt_volume_bytes((64, 64, 32), rt.U8) == r256(33 * 33 * 17 * 8 * 8)
     assert rt.rt_volume_bytes((2, 2, 2), rt.F32) == r256(2 * 2 * 2 * 8 * 8 * 4)
+    # polynomial cells (integer data): as cells, 8 binary32 coefficients each
+    assert rt.rt_volume_bytes((256, 256, 160), rt.U16, rt.LAYOUT_POLY) == r256(129 * 129 * 81 * 8 * 8 * 4)
+    assert rt.rt_volume_bytes((64, 64, 32), rt.U8, rt.LAYOUT_POLY) == r256(33 * 33 * 17 * 8 * 8 * 4)
     # brick-scaled, halo bricks: ceil((n-1)/B) bricks per axis, (B+3)^3 codes and 8 bytes each
     nb = 16 * 16 * 10
     assert rt.rt_volume_bytes((256, 256, 160), rt.U8_BRICKSCALED, rt.LAYOUT_BRICKS, 16) == \
@@ -71,6 +74,9 @@ def test_volume_bytes(rt):
     ((2048, 2048, 1024), 1, 0, 0, "Unsupported"),
     ((4, 4, 4), 9, 0, 0, "InvalidArgument"),
     ((5000, 5000, 4), 1, 1, 0, "Unsupported"),
+    ((4, 4, 4), 2, 3, 0, "InvalidArgument"),    # polynomial layout: integer storage only
+    ((4, 4, 4), 3, 3, 0, "InvalidArgument"),
+    ((4, 4, 4), 4, 3, 8, "InvalidArgument"),
 ])
 def test_volume_bytes_errors(rt, dims, storage, layout, brick, exc):
     with pytest.raises(getattr(rt, exc)):

@@ -232,6 +232,90 @@ def test_linear_and_cell_layouts_bitwise_equal(rt, torch_mod, storage):
     assert np.array_equal(imgs[0][0], imgs[1][0]) and np.array_equal(imgs[0][1], imgs[1][1])
 
 
+def poly_coefficients(v):
+    """Trilinear polynomial coefficients of every padded cell (-1..n-1 per
+    axis, corners clamped to the grid), in int64."""
+    g = np.pad(v.astype(np.int64), 1, mode="edge")             # padded nodes -1..n
+    c = {}
+    for dz in (0, 1):
+        for dy in (0, 1):
+            for dx in (0, 1):
+                c[dx, dy, dz] = g[dz: dz + g.shape[0] - 1, dy: dy + g.shape[1] - 1, dx: dx + g.shape[2] - 1]
+    p0 = c[0, 0, 0]
+    px, py, pz = c[1, 0, 0] - p0, c[0, 1, 0] - p0, c[0, 0, 1] - p0
+    pxy = c[1, 1, 0] - c[1, 0, 0] - c[0, 1, 0] + p0
+    pxz = c[1, 0, 1] - c[1, 0, 0] - c[0, 0, 1] + p0
+    pyz = c[0, 1, 1] - c[0, 1, 0] - c[0, 0, 1] + p0
+    pxyz = c[1, 1, 1] - c[1, 1, 0] - c[1, 0, 1] - c[0, 1, 1] + c[1, 0, 0] + c[0, 1, 0] + c[0, 0, 1] - p0
+    return np.stack([p0, px, py, pz, pxy, pxz, pyz, pxyz], -1)   # [cz, cy, cx, 8]
+
+
+@pytest.mark.parametrize("storage", ["U8", "U16"])
+def test_poly_layout_coefficients_exact(rt, torch_mod, storage):
+    """Every stored coefficient equals the integer combination of the cell's
+    corners (all of them are exact in binary32)."""
+    dims = (13, 10, 7)
+    v = W.phantom_brain(21, dims=dims)
+    if storage == "U8":
+        v = (v >> 4).astype(np.uint8)
+    gv = rt.Volume(v, (0.9, 0.9, 1.2), storage=getattr(rt, storage), layout=rt.LAYOUT_POLY)
+    torch_mod.cuda.synchronize()
+    nb = [(n + 2) // 2 for n in dims]
+    raw = gv.buf.cpu().numpy()[: nb[0] * nb[1] * nb[2] * 8 * 32].view(np.float32)
+    blocks = raw.reshape(nb[2], nb[1], nb[0], 2, 2, 2, 8)              # [bz, by, bx, wz, wy, wx, 8]
+    cells = blocks.transpose(0, 3, 1, 4, 2, 5, 6).reshape(2 * nb[2], 2 * nb[1], 2 * nb[0], 8)
+    want = poly_coefficients(v)                                          # cells -1..n-1 per axis
+    got = cells[: dims[2] + 1, : dims[1] + 1, : dims[0] + 1]
+    assert np.array_equal(got.astype(np.int64), want) and np.array_equal(got, want.astype(np.float32))
+
+
+def test_poly_layout_render_parity(rt, torch_mod, orc, small, brain):
+    """The polynomial layout evaluates the same trilinear interpolant in a
+    different order, so it meets the oracle at the same tolerance."""
+    gv = rt.Volume(small["np"], (1, 1, 2), storage=rt.U8, layout=rt.LAYOUT_POLY)
+    cam = W.ortho_camera_small()
+    got, c = gpu_render(rt, torch_mod, gv, small["gtf"], cam, 128, 128, 0.5, 0.99)
+    ref = orc.render(small["ov"], small["otf"], cam, 128, 128, 0.5, 0.99, tie_delta=DELTA, want_band=True)
+    check(got, ref, c, "poly small")
+    gv = rt.Volume(brain["np"], brain["sp"], storage=rt.U16, layout=rt.LAYOUT_POLY)
+    for view in (0, 13):
+        cam = brain["cams"][view]
+        got, c = gpu_render(rt, torch_mod, gv, brain["gtf"], cam, 512, 512, 0.5, 0.99)
+        ref = orc.render(brain["ov"], brain["otf"], cam, 512, 512, 0.5, 0.99, tie_delta=DELTA, want_band=True)
+        w, e = check(got, ref, c, f"poly brain view {view}")
+        print(f"poly brain view {view}: max err {e:.3g}, band dist {w:.3g}")
+    rng = np.random.default_rng(5)
+    for seed in range(6):
+        dims = tuple(int(x) for x in rng.integers(2, 40, 3))
+        sp = tuple(float(x) for x in rng.uniform(0.5, 2.0, 3))
+        v = rng.integers(0, 4096, size=dims[::-1], dtype=np.uint16)
+        t = W.random_tf(512, seed + 40, alpha_max=0.3)
+        cam = W.random_camera(rng, dims, sp)
+        gv = rt.Volume(v, sp, storage=rt.U16, layout=rt.LAYOUT_POLY)
+        got, c = gpu_render(rt, torch_mod, gv, rt.TransferFunction(t, 0, 4095), cam, 67, 45, 0.37, 0.95)
+        ref = orc.render(orc.Volume(v, sp), orc.TF(t, 0, 4095), cam, 67, 45, 0.37, 0.95, tie_delta=DELTA,
+                         want_band=True)
+        check(got, ref, c, f"poly random {seed} dims {dims}")
+
+
+def test_poly_layout_batch_equals_plain(rt, torch_mod, brain):
+    torch = torch_mod
+    gv = rt.Volume(brain["np"], brain["sp"], storage=rt.U16, layout=rt.LAYOUT_POLY)
+    cams = brain["cams"][::7]
+    plain = [gpu_render(rt, torch, gv, brain["gtf"], c, 160, 128, 0.5, 0.99)[0] for c in cams]
+    jobs = [rt.Job(gv, brain["gtf"], c, 160, 128, 0.5, 0.99) for c in cams]
+    outs = rt.render_batch(jobs)
+    plan = rt.BatchPlan(8, rt.U16, layout=rt.LAYOUT_POLY)
+    with pytest.raises(rt.InvalidArgument):  # cells plan, poly volume
+        rt.BatchPlan(8, rt.U16).launch(jobs)
+    jobs2 = [rt.Job(gv, brain["gtf"], c, 160, 128, 0.5, 0.99) for c in cams]
+    plan.launch(jobs2)
+    torch.cuda.synchronize()
+    for a, b, j in zip(plain, outs, jobs2):
+        assert np.array_equal(a, b.cpu().numpy().astype(np.float64))
+        assert np.array_equal(a, j.out.cpu().numpy().astype(np.float64))
+
+
 def test_f16_relayout_rounds_to_nearest_even(rt, torch_mod):
     v = np.arange(0, 4096, dtype=np.uint16)[None, None, :].repeat(2, 0).repeat(2, 1)
     gv = rt.Volume(v, (1, 1, 1), storage=rt.F16, layout=rt.LAYOUT_LINEAR)
