@@ -294,6 +294,22 @@ struct CellBits<ST_F32> {
     }
 };
 
+// Storage index of padded cell (ix, iy, iz) in the 2x2x2-blocked cell order:
+// 8 * block + within, block = (bz * nby + by) * nbx + bx with b = i >> 1 and
+// within = (ix & 1) | (iy & 1) << 1 | (iz & 1) << 2.  Since i = 2b + (i & 1),
+//   8 bx + (ix & 1) = ix + 6 bx,  8 nbx by + 2 (iy & 1) = 2 iy + (8 nbx - 4) by,
+//   8 nbx nby bz + 4 (iz & 1) = 4 iz + (8 nbx nby - 8) bz,
+// a sum of 24-bit multiply-adds (the strides sy = 8 nbx - 4 and
+// sz = 8 nbx nby - 8 are precomputed, both below 2^24).
+template <class VOL>
+__device__ __forceinline__ uint32_t cell_index(const VOL& vol, const long long Q[3]) {
+    const uint32_t ix = hiword(Q[0]), iy = hiword(Q[1]), iz = hiword(Q[2]);
+    uint32_t c = __umul24(ix >> 1, 6u) + ix;
+    c = __umul24(iy >> 1, vol.sy) + c;
+    c = __umul24(iz >> 1, vol.sz) + c;
+    return c + 2u * iy + 4u * iz;
+}
+
 template <int KIND>
 struct Sampler<KIND, LAYOUT_CELLS> {
     using B = CellBits<KIND>;
@@ -301,10 +317,7 @@ struct Sampler<KIND, LAYOUT_CELLS> {
     template <class VOL>
     static __device__ __forceinline__ Raw load(__amdgpu_buffer_rsrc_t r, const VOL& vol, const Corners&,
                                                const long long Q[3]) {
-        const uint32_t ix = hiword(Q[0]), iy = hiword(Q[1]), iz = hiword(Q[2]);
-        const uint32_t blk = __umul24(__umul24(iz >> 1, (uint32_t)vol.nb[1]) + (iy >> 1), (uint32_t)vol.nb[0]) + (ix >> 1);
-        const uint32_t w = (ix & 1u) | ((iy & 1u) << 1) | ((iz & 1u) << 2);
-        return B::load(r, (blk << (B::shift + 3)) | (w << B::shift));
+        return B::load(r, cell_index(vol, Q) << B::shift);
     }
     static __device__ __forceinline__ float value(const Raw& w, float fx, float fy, float fz) {
         float c[8];
@@ -322,10 +335,7 @@ struct Sampler<KIND, LAYOUT_POLY> {
     template <class VOL>
     static __device__ __forceinline__ Raw load(__amdgpu_buffer_rsrc_t r, const VOL& vol, const Corners&,
                                                const long long Q[3]) {
-        const uint32_t ix = hiword(Q[0]), iy = hiword(Q[1]), iz = hiword(Q[2]);
-        const uint32_t blk = __umul24(__umul24(iz >> 1, (uint32_t)vol.nb[1]) + (iy >> 1), (uint32_t)vol.nb[0]) + (ix >> 1);
-        const uint32_t w = (ix & 1u) | ((iy & 1u) << 1) | ((iz & 1u) << 2);
-        return B::load(r, (blk << 8) | (w << 5));
+        return B::load(r, cell_index(vol, Q) << 5);
     }
     static __device__ __forceinline__ float value(const Raw& w, float fx, float fy, float fz) {
         const f32x4 a = __builtin_bit_cast(f32x4, w.a), b = __builtin_bit_cast(f32x4, w.b);
@@ -407,7 +417,7 @@ __device__ __forceinline__ float4 classify(const float4* __restrict__ s_tf, floa
                                            float Km1) {
     const float x = __builtin_amdgcn_fmed3f(fmaf(val, ta, tb), 0.0f, Km1);
     const uint32_t j0 = (uint32_t)x;
-    const float g = x - (float)j0;
+    const float g = __builtin_amdgcn_fractf(x);  // x >= 0: exactly x - j0
     const float4 t0 = s_tf[j0], t1 = s_tf[j0 + 1];
     return make_float4(lerp(t0.x, t1.x, g), lerp(t0.y, t1.y, g), lerp(t0.z, t1.z, g), lerp(t0.w, t1.w, g));
 }

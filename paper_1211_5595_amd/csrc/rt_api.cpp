@@ -159,6 +159,11 @@ rt_status compute_layout(const int64_t dims[3], int storage, int layout, int bri
         L.data_bytes = nbt * 8 * 8 * (size_t)e;
         if (nbt >= ((size_t)1 << 24) || L.data_bytes > 0xffffffffull)
             return fail(RT_ERR_UNSUPPORTED, "volume too large for the cell-packed layout (4 GiB)");
+        // cell-index strides of the y and z block coordinates (24-bit multiplies in the marcher)
+        if (8 * (size_t)L.nb[0] * L.nb[1] >= ((size_t)1 << 24))
+            return fail(RT_ERR_UNSUPPORTED, "slice too large for the cell-packed layout (24-bit strides)");
+        L.sy = (uint32_t)(8 * (size_t)L.nb[0] - 4);
+        L.sz = (uint32_t)(8 * (size_t)L.nb[0] * L.nb[1] - 8);
     } else {
         L.layout = LAYOUT_LINEAR;
         L.sy = (uint32_t)(px * e);
