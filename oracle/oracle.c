@@ -13,7 +13,10 @@
  *   step 2  the values along the ray     (trilinear resampling, Section 3.2;
  *                                         transfer-function classification,
  *                                         Sections 2.6 and 6)
- *   step 3  the ray function             (compositing, Section 4.2 eqs. 1-5)
+ *   step 3  the ray function             (compositing, Section 4.2 eqs. 1-5;
+ *                                         maximum-intensity, X-ray and
+ *                                         average-intensity projection,
+ *                                         Sections 2.4 and 4.1)
  *
  * Readings of points the paper leaves open (each is listed, with its reason,
  * in the project's design notes):
@@ -33,7 +36,11 @@
  *   R10 early termination after the first sample whose accumulated opacity
  *       reaches the cutoff (not in the paper);
  *   R11 premultiplied background behind the volume;
- *   R12 look-at camera, pixel centres, row 0 at the top, aspect W/H.
+ *   R12 look-at camera, pixel centres, row 0 at the top, aspect W/H;
+ *   R13 projections reduce every lattice sample (no early termination): the
+ *       maximum, dt times the weighted sum, or the weighted mean of the
+ *       values; the scalar is classified once and laid over the background
+ *       with the table's opacity.
  */
 #include "oracle.h"
 
@@ -326,6 +333,45 @@ static void composite_out(const double C[3], double T, const orc_params* prm, do
  * first with 1-T >= cutoff+delta (or the last sample) are all acceptable
  * stopping points for an implementation whose accumulated opacity differs by
  * less than delta; their per-channel range is reported. */
+/* Projection ray functions (Section 2.4 and the Section 4.1 list): instead of
+ * compositing, each ray reduces the interpolated values of all its lattice
+ * samples to one scalar (no early termination; R-f1):
+ *   maximum intensity projection  s = max_k v_k (the remainder sample
+ *                                  included whatever its weight),
+ *   X-ray projection              s = dt * sum_k w_k v_k, the Riemann sum of
+ *                                  the line integral of f over the chord,
+ *   average intensity projection  s = sum_k w_k v_k / sum_k w_k,
+ * with w_k = 1 for full samples and r/dt for the remainder.  The scalar is
+ * classified once and laid over the background with the table's opacity:
+ * out.rgb = a c + (1 - a) bg.rgb, out.a = a + (1 - a) bg.a. */
+static void ray_project(const orc_volume* vol, const orc_tf* tf, const orc_params* prm, const ray_path* rp,
+                        ray_result* res) {
+    const int64_t n = rp->m + (rp->r > 0.0 ? 1 : 0);
+    double vmax = -INFINITY, sum = 0.0, wsum = 0.0;
+    for (int64_t k = 0; k < n; ++k) {
+        double s, weight, q[3];
+        sample_at(rp, k, &s, &weight);
+        const double val = value_at(vol, rp, s, q);
+        if (val > vmax) vmax = val;
+        sum += weight * val;
+        wsum += weight;
+    }
+    double scalar;
+    switch (prm->ray_function) {
+        case ORC_MIP: scalar = vmax; break;
+        case ORC_XRAY: scalar = rp->dt * sum; break;
+        default: scalar = sum / wsum; break;
+    }
+    double rgba[4];
+    orc_classify(tf, scalar, rgba);
+    const double a = rgba[3];
+    for (int c = 0; c < 3; ++c) res->out[c] = a * rgba[c] + (1.0 - a) * prm->bg[c];
+    res->out[3] = a + (1.0 - a) * prm->bg[3];
+    res->count = n;
+    memcpy(res->lo, res->out, sizeof(res->out));
+    memcpy(res->hi, res->out, sizeof(res->out));
+}
+
 static void ray_composite(const orc_volume* vol, const orc_tf* tf, const orc_params* prm, const ray_path* rp,
                           ray_result* res) {
     double C[3] = {0.0, 0.0, 0.0}, T = 1.0;
@@ -387,6 +433,11 @@ static int march_pixel(const orc_volume* vol, const orc_tf* tf, const orc_camera
     switch (prm->ray_function) {
         case ORC_COMPOSITE:
             ray_composite(vol, tf, prm, &rp, res);
+            break;
+        case ORC_MIP:
+        case ORC_XRAY:
+        case ORC_AVERAGE:
+            ray_project(vol, tf, prm, &rp, res);
             break;
         default:
             return ORC_EINVAL;

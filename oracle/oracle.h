@@ -42,8 +42,11 @@ extern "C" {
 /* Ray functions (Section 4.1 list; Section 2.4 for MIP and X-ray). */
 #define ORC_COMPOSITE 0   /* front-to-back emission-absorption compositing */
 #define ORC_MIP 1         /* maximum interpolated value along the ray */
-#define ORC_XRAY 2        /* sum of interpolated values times step length */
-#define ORC_AVERAGE 3     /* mean of interpolated values */
+#define ORC_XRAY 2        /* dt times the weighted sum of the interpolated values */
+#define ORC_AVERAGE 3     /* weighted mean of the interpolated values */
+/* The three projections visit every lattice sample (weights 1, and r/dt for
+ * the remainder), classify the resulting scalar once and lay it over the
+ * background: out.rgb = a c + (1-a) bg.rgb, out.a = a + (1-a) bg.a. */
 #define ORC_ISO 4         /* first crossing of an iso-value, shaded */
 #define ORC_THRESHOLD 5   /* compositing restricted to a value window */
 
