@@ -228,6 +228,49 @@ def bench_precision(args):
     print(json.dumps(line), flush=True)
 
 
+def bench_projection(args):
+    """Maximum-intensity, X-ray and average-intensity projection of the
+    256x256x160 u16 phantom over the 36 orbit views at 512x512, step 0.5, one
+    graph-captured persistent launch per step; compositing of the same views
+    beside them.  Projections visit every lattice sample (no early
+    termination)."""
+    import torch
+
+    import paper_1211_5595_amd as rt
+    import workloads as W
+
+    cfg = W.CONFIG_BRAIN
+    vs, ts = cfg["volume"], cfg["tf"]
+    width, height, step, n_views = cfg["width"], cfg["height"], cfg["step_vox"], cfg["n_views"]
+    vol_np = W.phantom_brain(vs.seed, dims=vs.dims, spacing=vs.spacing)
+    cams = W.orbit_cameras(vs.dims, vs.spacing, n_views)
+    torch.cuda.set_device(0)
+    vol = rt.Volume(vol_np, vs.spacing, storage=rt.U16)
+    tf_np = W.random_tf(ts.K, ts.seed, alpha_max=ts.alpha_max)
+    results = {}
+    plan = rt.BatchPlan(n_views, rt.U16)
+    for name, fn, top in [("composite", rt.COMPOSITE, ts.vmax), ("mip", rt.MIP, ts.vmax),
+                          ("xray", rt.XRAY, ts.vmax * 150.0), ("average", rt.AVERAGE, ts.vmax)]:
+        tf = rt.TransferFunction(tf_np, ts.vmin, top)
+        outs = [torch.empty((height, width, 4), dtype=torch.float32, device="cuda") for _ in range(n_views)]
+        jobs = [rt.Job(vol, tf, cam, width, height, step, cfg["cutoff"], out=o, ray_function=fn)
+                for cam, o in zip(cams, outs)]
+        samples = _count(rt, jobs)
+        ms = _timed(lambda: plan.launch(jobs), args.steps, args.warmup)
+        results[name] = {"gsamples_per_s": round(samples / (ms * 1e-3) / 1e9, 3),
+                         "fps": round(n_views / (ms * 1e-3), 1), "ms_per_launch": round(ms, 4),
+                         "samples_per_launch": samples,
+                         "algorithmic_GB_per_s": round((samples * 16 + n_views * width * height * 16)
+                                                       / (ms * 1e-3) / 1e9, 1)}
+    line = _contract("ray samples/sec (G/s) + fps per ray function at 512x512 over 256x256x160",
+                     results["mip"]["gsamples_per_s"], "Gsamples/s", args, results["mip"]["ms_per_launch"], "u16",
+                     {"workload": "brain-projection-36x512x512-u16", "volume": list(vs.dims), "views": n_views,
+                      "image": [width, height], "step_vox": step, "tf_entries": ts.K,
+                      "ray_functions": list(results), "launch": "graph"},
+                     by_ray_function=results)
+    print(json.dumps(line), flush=True)
+
+
 def bench_batch(args):
     """32 seeded phantoms of uneven sizes (u16), 4 random views each at
     256..1024 square, one transfer function per phantom: one persistent
@@ -389,10 +432,11 @@ def main():
     ap.add_argument("--only", choices=["batch", "plain", "graph"], default=None,
                     help="time one launch form only (for profiling)")
     ap.add_argument("--requests", type=int, default=4000, help="serve workload: number of requests")
-    ap.add_argument("--workload", choices=["orbit", "precision", "batch", "serve"], default="orbit",
+    ap.add_argument("--workload", choices=["orbit", "precision", "batch", "serve", "projection"], default="orbit",
                     help="orbit: 36 views of the 256x256x160 u16 phantom at 512^2 (default); precision: "
                          "the same phantom as u16/f16/8-bit bricks at 1024^2, step 0.25; batch: 32 uneven "
-                         "volumes x 4 views in one launch vs 128 launches")
+                         "volumes x 4 views in one launch vs 128 launches; serve: Poisson request stream; "
+                         "projection: the orbit under maximum-intensity, X-ray and average projection")
     ap.add_argument("--layout", choices=["cells", "poly", "linear"], default="cells",
                     help="device layout of the orbit volume")
     args = ap.parse_args()
@@ -417,6 +461,8 @@ def main():
         return bench_batch(args)
     if args.workload == "serve":
         return bench_serve(args)
+    if args.workload == "projection":
+        return bench_projection(args)
 
     cfg = W.CONFIG_BRAIN
     vs, ts = cfg["volume"], cfg["tf"]

@@ -86,12 +86,17 @@ typedef enum {
 } rt_layout;
 
 /* Ray functions (Section 4.1 list; Section 2.4 for maximum intensity and
- * X-ray projection). */
+ * X-ray projection).  The three projections visit every sample of the ray's
+ * lattice (weight 1, and r/dt for the partial last segment; no early
+ * termination), reduce the interpolated values to one scalar, classify it
+ * once and lay it over the background with the table's opacity a:
+ * out.rgb = a*rgb + (1-a)*bg.rgb, out.a = a + (1-a)*bg.a (bg when the ray
+ * misses).  The maximum takes the partial sample whatever its weight. */
 typedef enum {
     RT_COMPOSITE = 0,  /* emission-absorption compositing, Section 4.2 */
     RT_MIP = 1,        /* maximum interpolated value along the ray */
-    RT_XRAY = 2,       /* sum of interpolated values times segment length */
-    RT_AVERAGE = 3,    /* mean interpolated value */
+    RT_XRAY = 2,       /* dt times the weighted sum of the values (the chord's line integral) */
+    RT_AVERAGE = 3,    /* weighted mean of the values */
     RT_ISO = 4,        /* first crossing of an iso-value, shaded */
     RT_THRESHOLD = 5   /* compositing of the samples inside a value window */
 } rt_ray_function;
@@ -203,13 +208,17 @@ typedef struct {
     float bg_rgba[4];
     float* out_dev;           /* H*W*4 float32, device */
     int32_t* pixel_counts;    /* device, nullable */
+    int ray_function;         /* rt_ray_function of this view; 0 = compositing */
+    float iso_value, iso_high;
 } rt_render_job;
 
 /* Workspace bytes for batches of up to max_jobs views (max_jobs >= 1). */
 rt_status rt_batch_workspace_bytes(int max_jobs, size_t* bytes);
 
-/* Render n views (of possibly different volumes, transfer functions and
- * sizes; all volumes of one storage type and layout) in one persistent launch that pulls
+/* Render n views (of possibly different volumes, transfer functions, ray
+ * functions and sizes; all volumes of one storage type and layout; each job
+ * selects its own ray function, the ray-function fields of opts are not used)
+ * in one persistent launch that pulls
  * ray tiles from a device work queue.  Copies the job table into `workspace`
  * (>= rt_batch_workspace_bytes(n)) on `stream`; the job array may be reused
  * once the call returns.  Results are bitwise identical to rt_render of each

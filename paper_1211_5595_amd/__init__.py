@@ -20,7 +20,7 @@ import numpy as np
 
 __all__ = [
     "RTError", "InvalidArgument", "OutOfMemory", "DeviceError", "Unsupported",
-    "U8", "U16", "F16", "F32", "U8_BRICKSCALED", "COMPOSITE",
+    "U8", "U16", "F16", "F32", "U8_BRICKSCALED", "COMPOSITE", "MIP", "XRAY", "AVERAGE", "ISO", "THRESHOLD",
     "lib", "rt_volume_bytes", "rt_create_volume", "rt_destroy_volume", "rt_tf_bytes",
     "rt_set_transfer_function", "rt_destroy_tf", "rt_render", "rt_batch_workspace_bytes",
     "rt_render_batch", "rt_batch_plan_create", "rt_batch_plan_launch", "rt_batch_plan_destroy",
@@ -74,7 +74,8 @@ class rt_render_opts(C.Structure):
 class rt_render_job(C.Structure):
     _fields_ = [("volume", C.c_void_p), ("tf", C.c_void_p), ("camera", rt_camera), ("width", C.c_int),
                 ("height", C.c_int), ("step_vox", C.c_double), ("alpha_cutoff", C.c_double),
-                ("bg_rgba", C.c_float * 4), ("out_dev", C.c_void_p), ("pixel_counts", C.c_void_p)]
+                ("bg_rgba", C.c_float * 4), ("out_dev", C.c_void_p), ("pixel_counts", C.c_void_p),
+                ("ray_function", C.c_int), ("iso_value", C.c_float), ("iso_high", C.c_float)]
 
 
 _lib = None
@@ -347,12 +348,14 @@ class TransferFunction:
 
 def render(volume: Volume, tf: TransferFunction, camera, width: int, height: int, step_vox: float = 0.5,
            alpha_cutoff: float = 0.99, bg=(0.0, 0.0, 0.0, 0.0), out=None, pixel_counts=None, sample_counter=None,
-           spacing=None, tile=(0, 0), waves_per_block=0, stream=None):
+           spacing=None, tile=(0, 0), waves_per_block=0, stream=None, ray_function=COMPOSITE, iso_value=0.0,
+           iso_high=0.0):
     """Render one view; returns the float32 [H][W][4] device image."""
     torch = _torch()
     if out is None:
         out = torch.empty((height, width, 4), dtype=torch.float32, device=volume.buf.device)
-    opts = make_opts(sample_counter, pixel_counts, COMPOSITE, tile=tile, waves_per_block=waves_per_block)
+    opts = make_opts(sample_counter, pixel_counts, ray_function, iso_value, iso_high, tile=tile,
+                     waves_per_block=waves_per_block)
     rt_render(volume.handle, volume.dims, spacing, tf.handle, camera, width, height, step_vox, alpha_cutoff, bg,
               out.data_ptr(), opts, stream)
     return out
@@ -363,9 +366,10 @@ class Job:
 
     def __init__(self, volume: Volume, tf: TransferFunction, camera, width: int, height: int,
                  step_vox: float = 0.5, alpha_cutoff: float = 0.99, bg=(0.0, 0.0, 0.0, 0.0), out=None,
-                 pixel_counts=None):
+                 pixel_counts=None, ray_function: int = COMPOSITE, iso_value: float = 0.0, iso_high: float = 0.0):
         torch = _torch()
         self.volume, self.tf, self.camera = volume, tf, camera
+        self.ray_function, self.iso_value, self.iso_high = int(ray_function), float(iso_value), float(iso_high)
         self.width, self.height = int(width), int(height)
         self.step_vox, self.alpha_cutoff, self.bg = float(step_vox), float(alpha_cutoff), tuple(bg)
         self.out = out if out is not None else torch.empty((height, width, 4), dtype=torch.float32,
@@ -381,6 +385,7 @@ class Job:
         j.bg_rgba[:] = [float(x) for x in self.bg]
         j.out_dev = self.out.data_ptr()
         j.pixel_counts = self.pixel_counts.data_ptr() if self.pixel_counts is not None else None
+        j.ray_function, j.iso_value, j.iso_high = self.ray_function, self.iso_value, self.iso_high
         return j
 
 

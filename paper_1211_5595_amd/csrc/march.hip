@@ -484,6 +484,68 @@ __device__ __forceinline__ void load_tf(float4* s_tf, const float4* __restrict__
 }
 
 // One workgroup block of a view: wave w renders tile (w % bw, w / bw) of the block.
+// Step 3 for the projection ray functions: every sample of the lattice is
+// visited (no early termination) and reduced to one scalar: the maximum, or
+// the weighted sum (X-ray: times dt; average: over the summed weights).  The
+// sum is compensated (Kahan), so its rounding error stays at a few units of
+// the last place whatever the ray length.  The scalar is classified once and
+// laid over the background with the table's opacity.
+enum { RF_MAX = 0, RF_SUM = 1 };
+
+template <int KIND, int LAYOUT, int RED, class VD>
+__device__ __forceinline__ void project_pixel(const VD& V, const float4* __restrict__ s_tf,
+                                              __amdgpu_buffer_rsrc_t rs, const Corners& cn, int i, int j,
+                                              float4& px, int& count) {
+    using S = Sampler<KIND, LAYOUT>;
+    Ray R;
+    float acc = RED == RF_MAX ? -INFINITY : 0.0f, comp = 0.0f;
+    int k = 0;
+    px = make_float4(V.bg[0], V.bg[1], V.bg[2], V.bg[3]);
+    if (!setup_ray(V, i, j, R)) {
+        count = 0;
+        return;
+    }
+    if (R.m > 0) {
+        typename S::Raw cur = S::load(rs, V.vol, cn, R.Q);
+        for (;;) {
+            const long long Qn[3] = {R.Q[0] + R.dQ[0], R.Q[1] + R.dQ[1], R.Q[2] + R.dQ[2]};
+            const typename S::Raw nxt = S::load(rs, V.vol, cn, Qn);
+            const float val = S::value(cur, frac32(R.Q[0]), frac32(R.Q[1]), frac32(R.Q[2]));
+            if (RED == RF_MAX) {
+                acc = fmaxf(acc, val);
+            } else {
+                const float y = val - comp, t = acc + y;
+                comp = (t - acc) - y;
+                acc = t;
+            }
+            if (++k >= R.m) break;
+            cur = nxt;
+            R.Q[0] = Qn[0];
+            R.Q[1] = Qn[1];
+            R.Q[2] = Qn[2];
+        }
+    }
+    if (R.wp > 0.0f) {
+        const typename S::Raw w = S::load(rs, V.vol, cn, R.Qp);
+        const float val = S::value(w, frac32(R.Qp[0]), frac32(R.Qp[1]), frac32(R.Qp[2]));
+        if (RED == RF_MAX) {
+            acc = fmaxf(acc, val);
+        } else {
+            const float y = val * R.wp - comp, t = acc + y;
+            acc = t;
+        }
+        ++k;
+    }
+    count = k;
+    float scalar = acc;
+    if (RED == RF_SUM)
+        scalar = V.ray_function == RT_FN_XRAY ? acc * V.dt.hi : acc / ((float)R.m + R.wp);
+    const float4 c = classify(s_tf, scalar, V.tf_a, V.tf_b, (float)(V.K - 1));
+    const float ia = 1.0f - c.w;
+    px = make_float4(fmaf(c.w, c.x, ia * V.bg[0]), fmaf(c.w, c.y, ia * V.bg[1]), fmaf(c.w, c.z, ia * V.bg[2]),
+                     fmaf(ia, V.bg[3], c.w));
+}
+
 template <int KIND, int LAYOUT, class VD>
 __device__ __forceinline__ void render_block(const VD& V, const float4* __restrict__ s_tf, int blk,
                                              const LaunchShape& ls, int tw_shift,
@@ -498,7 +560,13 @@ __device__ __forceinline__ void render_block(const VD& V, const float4* __restri
     int count = 0;
     if (i < V.W && j < V.H) {
         float4 px;
-        march_pixel<KIND, LAYOUT, VD>(V, s_tf, rs, cn, i, j, px, count);
+        const int fn = V.ray_function;  // uniform over the view
+        if (fn == RT_FN_COMPOSITE)
+            march_pixel<KIND, LAYOUT, VD>(V, s_tf, rs, cn, i, j, px, count);
+        else if (fn == RT_FN_MIP)
+            project_pixel<KIND, LAYOUT, RF_MAX, VD>(V, s_tf, rs, cn, i, j, px, count);
+        else
+            project_pixel<KIND, LAYOUT, RF_SUM, VD>(V, s_tf, rs, cn, i, j, px, count);
         const size_t p = (size_t)j * V.W + i;
         reinterpret_cast<float4*>(V.out)[p] = px;
         if (V.counts) V.counts[p] = count;

@@ -227,7 +227,9 @@ rt_status make_view(const rt_volume* vol, const int64_t dims[3], const double sp
     if (!(step_vox > 0.0) || !std::isfinite(step_vox)) return fail(RT_ERR_INVALID_ARG, "step must be finite and > 0");
     if (!(cutoff > 0.0 && cutoff <= 1.0)) return fail(RT_ERR_INVALID_ARG, "alpha cutoff must be in (0, 1]");
     if (((uintptr_t)out & 15) != 0) return fail(RT_ERR_INVALID_ARG, "output must be 16-byte aligned");
-    if (ray_function != RT_COMPOSITE) return fail(RT_ERR_UNSUPPORTED, "ray function not built");
+    if (ray_function < RT_COMPOSITE || ray_function > RT_THRESHOLD)
+        return fail(RT_ERR_INVALID_ARG, "unknown ray function");
+    if (ray_function > RT_AVERAGE) return fail(RT_ERR_UNSUPPORTED, "ray function not built");
     if (!finite3(cam->eye) || !finite3(cam->center) || !finite3(cam->up))
         return fail(RT_ERR_INVALID_ARG, "camera vectors must be finite");
     double f[3] = {cam->center[0] - cam->eye[0], cam->center[1] - cam->eye[1], cam->center[2] - cam->eye[2]};
@@ -324,7 +326,7 @@ size_t batch_ws_bytes(int max_jobs) { return kBatchHeaderBytes + prefix_bytes() 
 
 // Fill header, prefix and job table for n jobs into host memory `h`; returns
 // the bytes to copy.
-rt_status build_batch(const rt_render_job* jobs, int n, const LaunchShape& ls, int ray_function, int* kind,
+rt_status build_batch(const rt_render_job* jobs, int n, const LaunchShape& ls, int* kind,
                       int* max_k, std::vector<ViewDesc>& descs, std::vector<int>& prefix) {
     if (!jobs || n < 1) return fail(RT_ERR_INVALID_ARG, "empty batch");
     if (n > kMaxBatchJobs) return fail(RT_ERR_UNSUPPORTED, "too many jobs in one batch");
@@ -336,7 +338,7 @@ rt_status build_batch(const rt_render_job* jobs, int n, const LaunchShape& ls, i
         const rt_render_job& J = jobs[i];
         if (!J.volume) return fail(RT_ERR_INVALID_ARG, "job without volume");
         rt_status st = make_view(J.volume, nullptr, nullptr, J.tf, &J.camera, J.width, J.height, J.step_vox,
-                                 J.alpha_cutoff, J.bg_rgba, J.out_dev, J.pixel_counts, ls, ray_function, descs[i]);
+                                 J.alpha_cutoff, J.bg_rgba, J.out_dev, J.pixel_counts, ls, J.ray_function, descs[i]);
         if (st != RT_OK) return fail(st, "job " + std::to_string(i) + ": " + g_last_error);
         const int k = J.volume->dev.kind * 4 + J.volume->dev.layout;  // storage type and layout
         if (*kind < 0) *kind = k;
@@ -567,7 +569,7 @@ rt_status rt_render_batch(const rt_render_job* jobs, int n, void* workspace, siz
     std::vector<ViewDesc> descs;
     std::vector<int> prefix;
     int kind, max_k;
-    st = build_batch(jobs, n, ls, opts ? opts->ray_function : 0, &kind, &max_k, descs, prefix);
+    st = build_batch(jobs, n, ls, &kind, &max_k, descs, prefix);
     if (st != RT_OK) return st;
     if (ws_bytes < batch_ws_bytes(n)) return fail(RT_ERR_OUT_OF_MEMORY, "workspace smaller than rt_batch_workspace_bytes");
     const size_t bytes = batch_copy_bytes(n);
@@ -603,7 +605,6 @@ rt_status rt_batch_plan_create(int max_jobs, int storage, int layout, void* work
     LaunchShape ls;
     rt_status st = make_shape(opts, ls);
     if (st != RT_OK) return st;
-    if (opts && opts->ray_function != RT_COMPOSITE) return fail(RT_ERR_UNSUPPORTED, "ray function not built");
     rt_batch_plan* p = new (std::nothrow) rt_batch_plan;
     if (!p) return fail(RT_ERR_OUT_OF_MEMORY, "host allocation failed");
     std::memset(p, 0, sizeof(*p));
@@ -657,7 +658,7 @@ rt_status rt_batch_plan_launch(rt_batch_plan* p, const rt_render_job* jobs, int 
     std::vector<ViewDesc> descs;
     std::vector<int> prefix;
     int kind, max_k;
-    rt_status st = build_batch(jobs, n, p->ls, 0, &kind, &max_k, descs, prefix);
+    rt_status st = build_batch(jobs, n, p->ls, &kind, &max_k, descs, prefix);
     if (st != RT_OK) return st;
     if (kind != p->kind) return fail(RT_ERR_INVALID_ARG, "jobs' storage type or layout differs from the plan's");
     if (p->copy_pending) {

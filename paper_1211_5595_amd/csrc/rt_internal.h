@@ -14,6 +14,9 @@ struct ff {
 };
 
 enum StorageKind : int { ST_U8 = 0, ST_U16 = 1, ST_F16 = 2, ST_F32 = 3, ST_U8B = 4 };
+// Ray functions as stored in a view descriptor (values of rt_ray_function).
+enum RayFn : int { RT_FN_COMPOSITE = 0, RT_FN_MIP = 1, RT_FN_XRAY = 2, RT_FN_AVERAGE = 3 };
+
 enum LayoutKind : int { LAYOUT_CELLS = 0, LAYOUT_LINEAR = 1, LAYOUT_BRICKS = 2, LAYOUT_POLY = 3 };
 
 // Device view of a volume in storage layout.  All layouts work on the
