@@ -127,7 +127,20 @@ typedef struct {
     float iso_high;                     /* RT_THRESHOLD window high */
     int tile_w, tile_h;                 /* ray tile of one wavefront, tile_w*tile_h == 64; 0 = 8x8 */
     int waves_per_block;                /* wavefronts per workgroup, 1..16; 0 = default */
+    int skip_empty;                     /* compositing: nonzero leaps over empty space (see below) */
 } rt_render_opts;
+
+/* Empty-space skipping (compositing only).  Each volume keeps, per skip brick
+ * of 8^3 cells (larger for very large volumes, so that a volume has at most
+ * 65536 of them), the range of values its samples can take; each transfer
+ * function keeps a running count of its entries with nonzero opacity.  A
+ * brick whose range (widened by a few units in the last place, and by one
+ * table entry each side) touches only zero-opacity entries is empty: its
+ * samples leave the accumulated colour and transmittance unchanged, bit for
+ * bit.  With skip_empty set, a wavefront whose live rays all sit in empty
+ * bricks advances every ray to the last sample it has in its brick in one
+ * step.  Images and per-pixel sample counts (skipped samples included) are
+ * identical to rendering without it. */
 
 /* ---------------------------------------------------------------------------
  * Volume data (Section 2.1: samples f(x,y,z,d) on a Cartesian grid; slices
@@ -135,7 +148,8 @@ typedef struct {
  * ------------------------------------------------------------------------- */
 
 /* Device bytes needed to hold a volume of `dims` with element type `storage`
- * in `layout`.  brick is the brick edge B in cells (8, 16 or 32) for
+ * in `layout`, followed by the value ranges of its empty-space skip bricks
+ * (8 bytes per brick, 256-byte aligned).  brick is the brick edge B in cells (8, 16 or 32) for
  * RT_U8_BRICKSCALED and must be 0 otherwise.  Errors: RT_ERR_INVALID_ARG
  * (bad dims, layout or brick, NULL), RT_ERR_UNSUPPORTED (volume too large for
  * 32-bit addressing: 4 GiB of storage). */
@@ -164,7 +178,9 @@ rt_status rt_destroy_volume(rt_volume* vol);
  * [vmin, vmax].
  * ------------------------------------------------------------------------- */
 
-/* Device bytes for a K-entry table (K in [2, 4096]). */
+/* Device bytes for a K-entry table (K in [2, 4096]): the K x 4 float table
+ * (256-byte aligned) and K+2 int32 running counts of its nonzero-opacity
+ * entries, used by empty-space skipping. */
 rt_status rt_tf_bytes(int K, size_t* bytes);
 
 /* Create (*tf == NULL) or update in place (*tf != NULL) a transfer function:
@@ -210,6 +226,7 @@ typedef struct {
     int32_t* pixel_counts;    /* device, nullable */
     int ray_function;         /* rt_ray_function of this view; 0 = compositing */
     float iso_value, iso_high;
+    int skip_empty;           /* compositing: leap over empty space (as rt_render_opts.skip_empty) */
 } rt_render_job;
 
 /* Workspace bytes for batches of up to max_jobs views (max_jobs >= 1). */
@@ -233,7 +250,9 @@ rt_status rt_render_batch(const rt_render_job* jobs, int n, void* workspace, siz
  * workspace (plain stream copy, outside the graph) and launches the graph on
  * `stream`.  The plan keeps a pinned host staging buffer and waits for the
  * previous launch's copy before reusing it.  Calls on one plan must not run
- * concurrently. */
+ * concurrently.  A plan created with opts->skip_empty set skips empty space
+ * for the jobs whose skip_empty is set; a plan created without it never skips
+ * (the images are the same either way). */
 rt_status rt_batch_plan_create(int max_jobs, int storage, int layout, void* workspace, size_t ws_bytes,
                                const rt_render_opts* opts, rt_batch_plan** out);
 rt_status rt_batch_plan_launch(rt_batch_plan* plan, const rt_render_job* jobs, int n,

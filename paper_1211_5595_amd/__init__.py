@@ -68,14 +68,15 @@ class rt_camera(C.Structure):
 class rt_render_opts(C.Structure):
     _fields_ = [("sample_counter", C.c_void_p), ("pixel_counts", C.c_void_p), ("ray_function", C.c_int),
                 ("iso_value", C.c_float), ("iso_high", C.c_float), ("tile_w", C.c_int), ("tile_h", C.c_int),
-                ("waves_per_block", C.c_int)]
+                ("waves_per_block", C.c_int), ("skip_empty", C.c_int)]
 
 
 class rt_render_job(C.Structure):
     _fields_ = [("volume", C.c_void_p), ("tf", C.c_void_p), ("camera", rt_camera), ("width", C.c_int),
                 ("height", C.c_int), ("step_vox", C.c_double), ("alpha_cutoff", C.c_double),
                 ("bg_rgba", C.c_float * 4), ("out_dev", C.c_void_p), ("pixel_counts", C.c_void_p),
-                ("ray_function", C.c_int), ("iso_value", C.c_float), ("iso_high", C.c_float)]
+                ("ray_function", C.c_int), ("iso_value", C.c_float), ("iso_high", C.c_float),
+                ("skip_empty", C.c_int)]
 
 
 _lib = None
@@ -162,8 +163,9 @@ def make_camera(cam) -> rt_camera:
 
 
 def make_opts(sample_counter=None, pixel_counts=None, ray_function=COMPOSITE, iso_value=0.0, iso_high=0.0,
-              tile=(0, 0), waves_per_block=0) -> rt_render_opts:
+              tile=(0, 0), waves_per_block=0, skip_empty=False) -> rt_render_opts:
     o = rt_render_opts()
+    o.skip_empty = 1 if skip_empty else 0
     o.sample_counter = sample_counter.data_ptr() if sample_counter is not None else None
     o.pixel_counts = pixel_counts.data_ptr() if pixel_counts is not None else None
     o.ray_function = int(ray_function)
@@ -349,13 +351,13 @@ class TransferFunction:
 def render(volume: Volume, tf: TransferFunction, camera, width: int, height: int, step_vox: float = 0.5,
            alpha_cutoff: float = 0.99, bg=(0.0, 0.0, 0.0, 0.0), out=None, pixel_counts=None, sample_counter=None,
            spacing=None, tile=(0, 0), waves_per_block=0, stream=None, ray_function=COMPOSITE, iso_value=0.0,
-           iso_high=0.0):
+           iso_high=0.0, skip_empty=False):
     """Render one view; returns the float32 [H][W][4] device image."""
     torch = _torch()
     if out is None:
         out = torch.empty((height, width, 4), dtype=torch.float32, device=volume.buf.device)
     opts = make_opts(sample_counter, pixel_counts, ray_function, iso_value, iso_high, tile=tile,
-                     waves_per_block=waves_per_block)
+                     waves_per_block=waves_per_block, skip_empty=skip_empty)
     rt_render(volume.handle, volume.dims, spacing, tf.handle, camera, width, height, step_vox, alpha_cutoff, bg,
               out.data_ptr(), opts, stream)
     return out
@@ -366,10 +368,12 @@ class Job:
 
     def __init__(self, volume: Volume, tf: TransferFunction, camera, width: int, height: int,
                  step_vox: float = 0.5, alpha_cutoff: float = 0.99, bg=(0.0, 0.0, 0.0, 0.0), out=None,
-                 pixel_counts=None, ray_function: int = COMPOSITE, iso_value: float = 0.0, iso_high: float = 0.0):
+                 pixel_counts=None, ray_function: int = COMPOSITE, iso_value: float = 0.0, iso_high: float = 0.0,
+                 skip_empty: bool = False):
         torch = _torch()
         self.volume, self.tf, self.camera = volume, tf, camera
         self.ray_function, self.iso_value, self.iso_high = int(ray_function), float(iso_value), float(iso_high)
+        self.skip_empty = bool(skip_empty)
         self.width, self.height = int(width), int(height)
         self.step_vox, self.alpha_cutoff, self.bg = float(step_vox), float(alpha_cutoff), tuple(bg)
         self.out = out if out is not None else torch.empty((height, width, 4), dtype=torch.float32,
@@ -386,6 +390,7 @@ class Job:
         j.out_dev = self.out.data_ptr()
         j.pixel_counts = self.pixel_counts.data_ptr() if self.pixel_counts is not None else None
         j.ray_function, j.iso_value, j.iso_high = self.ray_function, self.iso_value, self.iso_high
+        j.skip_empty = 1 if self.skip_empty else 0
         return j
 
 
@@ -420,10 +425,11 @@ class BatchPlan:
     """The persistent batched launch captured once in a HIP graph."""
 
     def __init__(self, max_jobs: int, storage: int, tile=(0, 0), waves_per_block=0, device="cuda",
-                 layout: int = LAYOUT_CELLS):
+                 layout: int = LAYOUT_CELLS, skip_empty: bool = False):
         self.ws = _Workspace(max_jobs, device)
         self.handle = rt_batch_plan_create(max_jobs, storage, layout, self.ws.buf.data_ptr(), self.ws.nbytes,
-                                           make_opts(tile=tile, waves_per_block=waves_per_block))
+                                           make_opts(tile=tile, waves_per_block=waves_per_block,
+                                                     skip_empty=skip_empty))
 
     def launch(self, jobs: Sequence[Job], sample_counter=None, stream=None):
         rt_batch_plan_launch(self.handle, [j.struct() for j in jobs],

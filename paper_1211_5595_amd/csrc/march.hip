@@ -424,10 +424,75 @@ __device__ __forceinline__ float4 classify(const float4* __restrict__ s_tf, floa
 
 // Step 3: compositing one pixel's ray.  Lanes whose rays have stopped are
 // masked off; the wavefront leaves the loop when no lane is left.
-template <int KIND, int LAYOUT, class VD>
+// Empty-space skipping.  A skip brick is empty for a table when every entry
+// that a sample in it can reach has zero opacity; such samples change neither
+// the colour nor the transmittance (T * 0 = 0 and fma(-T, 0, T) = T exactly),
+// so stepping over them leaves the result unchanged bit for bit.  The value
+// range is widened by 2^-18 of its magnitude (fp32 interpolation error is a
+// few units in the last place) and by one table entry on each side.
+template <class VD>
+__device__ __forceinline__ bool range_is_empty(const VD& V, float2 r) {
+    if (!(r.x <= r.y)) return false;  // NaN corners: never skipped
+    const float slack = (fabsf(r.x) + fabsf(r.y)) * 0x1p-18f;
+    const float Km1 = (float)(V.K - 1);
+    const float x0 = __builtin_amdgcn_fmed3f(fmaf(r.x - slack, V.tf_a, V.tf_b), 0.0f, Km1);
+    const float x1 = __builtin_amdgcn_fmed3f(fmaf(r.y + slack, V.tf_a, V.tf_b), 0.0f, Km1);
+    const int j0 = max((int)x0 - 1, 0), j1 = min((int)x1 + 2, V.K);
+    return V.tf_nz[j1 + 1] == V.tf_nz[j0];
+}
+
+// One bit per skip brick of the view's volume, for its table, in LDS.
+template <class VD>
+__device__ __forceinline__ void build_skip_mask(uint32_t* s_mask, const VD& V) {
+    const int nb = V.vol.enb[0] * V.vol.enb[1] * V.vol.enb[2];
+    for (int w = threadIdx.x; w < ((nb + 31) >> 5); w += blockDim.x) {
+        uint32_t bits = 0;
+        const int b0 = w << 5, b1 = min(b0 + 32, nb);
+        for (int b = b0; b < b1; ++b)
+            if (range_is_empty(V, V.vol.ess_range[b])) bits |= 1u << (b - b0);
+        s_mask[w] = bits;
+    }
+}
+
+template <class VOL>
+__device__ __forceinline__ bool in_empty_brick(const uint32_t* s_mask, const VOL& vol, const long long Q[3]) {
+    const uint32_t es = (uint32_t)vol.eshift;
+    const uint32_t b = (hiword(Q[0]) >> es) + __umul24(hiword(Q[1]) >> es, vol.esy) +
+                       __umul24(hiword(Q[2]) >> es, vol.esz);
+    return (s_mask[b >> 5] >> (b & 31)) & 1u;
+}
+
+__device__ __forceinline__ float u64_to_float(unsigned long long x) {
+    return fmaf((float)(uint32_t)(x >> 32), 0x1p32f, (float)(uint32_t)x);
+}
+
+// A lower bound (at least 1) on the number of consecutive samples, from the
+// one at Q on, whose cells lie in Q's skip brick.  Per axis the exact count
+// is ceil(t) (moving up) or floor(t) + 1 (moving down) with t the distance to
+// the brick face over the step; t is evaluated in binary32 with relative
+// error below 2^-20 and shrunk by 2^-16 before rounding down.
+template <class VOL>
+__device__ __forceinline__ int samples_in_brick(const VOL& vol, const long long Q[3], const long long dQ[3]) {
+    const uint32_t es = (uint32_t)vol.eshift;
+    float n = 3.0e38f;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const long long d = dQ[a];
+        if (d == 0) continue;
+        const uint32_t b = hiword(Q[a]) >> es;
+        const long long face = (long long)((unsigned long long)((b + (d > 0 ? 1u : 0u)) << es) << 32);
+        const unsigned long long dist = (unsigned long long)(d > 0 ? face - Q[a] : Q[a] - face);
+        const unsigned long long ad = (unsigned long long)(d > 0 ? d : -d);
+        const float t = u64_to_float(dist) * __builtin_amdgcn_rcpf(u64_to_float(ad)) * (1.0f - 0x1p-16f);
+        n = fminf(n, floorf(t) + (d > 0 ? 0.0f : 1.0f));
+    }
+    return (int)fmaxf(fminf(n, 1.0e9f), 1.0f);
+}
+
+template <int KIND, int LAYOUT, bool SKIP, class VD>
 __device__ __forceinline__ void march_pixel(const VD& V, const float4* __restrict__ s_tf,
-                                            __amdgpu_buffer_rsrc_t rs, const Corners& cn, int i, int j,
-                                            float4& px, int& count) {
+                                            const uint32_t* __restrict__ s_mask, __amdgpu_buffer_rsrc_t rs,
+                                            const Corners& cn, int i, int j, float4& px, int& count) {
     using S = Sampler<KIND, LAYOUT>;
     Ray R;
     float Cr = 0.0f, Cg = 0.0f, Cb = 0.0f, T = 1.0f;
@@ -438,6 +503,20 @@ __device__ __forceinline__ void march_pixel(const VD& V, const float4* __restric
         if (R.m > 0) {
             typename S::Raw cur = S::load(rs, V.vol, cn, R.Q);
             for (;;) {
+                if constexpr (SKIP) {
+                    // all live rays of the wavefront in empty bricks: each leaps to
+                    // its first sample outside its brick (or to the end of its ray)
+                    if (V.skip_empty && __builtin_amdgcn_ballot_w64(!in_empty_brick(s_mask, V.vol, R.Q)) == 0) {
+                        const int n = min(samples_in_brick(V.vol, R.Q, R.dQ), R.m - k);
+                        R.Q[0] += (long long)n * R.dQ[0];
+                        R.Q[1] += (long long)n * R.dQ[1];
+                        R.Q[2] += (long long)n * R.dQ[2];
+                        k += n;
+                        if (k >= R.m) break;
+                        cur = S::load(rs, V.vol, cn, R.Q);
+                        continue;
+                    }
+                }
                 const long long Qn[3] = {R.Q[0] + R.dQ[0], R.Q[1] + R.dQ[1], R.Q[2] + R.dQ[2]};
                 const typename S::Raw nxt = S::load(rs, V.vol, cn, Qn);
                 const float val = S::value(cur, frac32(R.Q[0]), frac32(R.Q[1]), frac32(R.Q[2]));
@@ -546,10 +625,10 @@ __device__ __forceinline__ void project_pixel(const VD& V, const float4* __restr
                      fmaf(ia, V.bg[3], c.w));
 }
 
-template <int KIND, int LAYOUT, class VD>
-__device__ __forceinline__ void render_block(const VD& V, const float4* __restrict__ s_tf, int blk,
-                                             const LaunchShape& ls, int tw_shift,
-                                             unsigned long long* __restrict__ counter) {
+template <int KIND, int LAYOUT, bool SKIP, class VD>
+__device__ __forceinline__ void render_block(const VD& V, const float4* __restrict__ s_tf,
+                                             const uint32_t* __restrict__ s_mask, int blk, const LaunchShape& ls,
+                                             int tw_shift, unsigned long long* __restrict__ counter) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int by = blk / V.blocks_x, bx = blk - by * V.blocks_x;
     const int tx = bx * ls.bw + wave % ls.bw, ty = by * ls.bh + wave / ls.bw;
@@ -562,7 +641,7 @@ __device__ __forceinline__ void render_block(const VD& V, const float4* __restri
         float4 px;
         const int fn = V.ray_function;  // uniform over the view
         if (fn == RT_FN_COMPOSITE)
-            march_pixel<KIND, LAYOUT, VD>(V, s_tf, rs, cn, i, j, px, count);
+            march_pixel<KIND, LAYOUT, SKIP, VD>(V, s_tf, s_mask, rs, cn, i, j, px, count);
         else if (fn == RT_FN_MIP)
             project_pixel<KIND, LAYOUT, RF_MAX, VD>(V, s_tf, rs, cn, i, j, px, count);
         else
@@ -589,13 +668,18 @@ __device__ __forceinline__ int xcd_remap(int b, int n) {
 // which caps the marcher at 64 VGPRs.
 #define RT_MARCH_ATTRS __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8)))
 
-template <int KIND, int LAYOUT>
+// SKIP selects the compositing loop with empty-space skipping (a separate
+// kernel, so the plain loop keeps its registers).
+template <int KIND, int LAYOUT, bool SKIP>
 __global__ void RT_MARCH_ATTRS march_plain_kernel(const ViewDesc V, const LaunchShape ls, int tw_shift,
                                                    unsigned long long* __restrict__ counter) {
     extern __shared__ float4 s_tf[];
+    uint32_t* s_mask = reinterpret_cast<uint32_t*>(s_tf + V.K + 1);
     load_tf(s_tf, V.tf, V.K);
+    if (SKIP) build_skip_mask(s_mask, V);
     __syncthreads();
-    render_block<KIND, LAYOUT, ViewDesc>(V, s_tf, xcd_remap(blockIdx.x, gridDim.x), ls, tw_shift, counter);
+    render_block<KIND, LAYOUT, SKIP, ViewDesc>(V, s_tf, s_mask, xcd_remap(blockIdx.x, gridDim.x), ls, tw_shift,
+                                               counter);
 }
 
 // Persistent batched marcher: workgroups claim blocks from a queue in the
@@ -610,11 +694,12 @@ typedef __attribute__((address_space(4))) const ViewDesc CViewDesc;
 typedef __attribute__((address_space(4))) const int CInt;
 typedef __attribute__((address_space(4))) const BatchHeader CBatchHeader;
 
-template <int KIND, int LAYOUT>
+template <int KIND, int LAYOUT, bool SKIP>
 __global__ void RT_MARCH_ATTRS march_batch_kernel(char* __restrict__ ws, const LaunchShape ls, int tw_shift,
                                                    int tf_entries) {
     extern __shared__ float4 s_tf[];
-    int* s_claim = reinterpret_cast<int*>(s_tf + tf_entries);
+    uint32_t* s_mask = reinterpret_cast<uint32_t*>(s_tf + tf_entries);
+    int* s_claim = reinterpret_cast<int*>(s_mask + kSkipMaskBytes / 4);
     unsigned int* queue = &reinterpret_cast<BatchHeader*>(ws)->queue;
     const CBatchHeader* hdr = (const CBatchHeader*)(ws);
     const CInt* prefix = (const CInt*)(ws + kBatchHeaderBytes);
@@ -623,6 +708,8 @@ __global__ void RT_MARCH_ATTRS march_batch_kernel(char* __restrict__ ws, const L
     unsigned long long* counter = hdr->counter;
     const int total = prefix[n_jobs];
     const float4* cur_tf = nullptr;
+    const float2* mask_vol = nullptr;   // the (volume, table) pair the mask in LDS was built for
+    const float4* mask_tf = nullptr;
     for (;;) {
         if (threadIdx.x == 0) s_claim[0] = (int)atomicAdd(queue, 1u);
         __syncthreads();
@@ -635,14 +722,74 @@ __global__ void RT_MARCH_ATTRS march_batch_kernel(char* __restrict__ ws, const L
             else hi = mid;
         }
         const CViewDesc& V = jobs[lo];
-        if (V.tf != cur_tf) {
-            cur_tf = V.tf;
-            load_tf(s_tf, V.tf, V.K);
+        const bool new_tf = V.tf != cur_tf;
+        const bool new_mask = SKIP && V.skip_empty && (V.vol.ess_range != mask_vol || V.tf != mask_tf);
+        if (new_tf || new_mask) {
+            if (new_tf) {
+                cur_tf = V.tf;
+                load_tf(s_tf, V.tf, V.K);
+            }
+            if (new_mask) {
+                mask_vol = V.vol.ess_range;
+                mask_tf = V.tf;
+                build_skip_mask(s_mask, V);
+            }
             __syncthreads();
         }
-        render_block<KIND, LAYOUT, CViewDesc>(V, s_tf, g - prefix[lo], ls, tw_shift, counter);
+        render_block<KIND, LAYOUT, SKIP, CViewDesc>(V, s_tf, s_mask, g - prefix[lo], ls, tw_shift, counter);
         __syncthreads();
     }
+}
+
+// Value range of every skip brick, one workgroup per brick: each of its
+// padded cells is sampled by the marcher's own sampler at the cell's 8
+// corners, so the range bounds what a sample in the brick can read (up to
+// the rounding of the interpolation, which the emptiness test allows for).
+template <int KIND, int LAYOUT>
+__global__ void __launch_bounds__(256) skip_range_kernel(const VolDev vol) {
+    using S = Sampler<KIND, LAYOUT>;
+    __shared__ float s_lo[256], s_hi[256];
+    const int b = blockIdx.x;
+    const int bx = b % vol.enb[0], by = (b / vol.enb[0]) % vol.enb[1], bz = b / (vol.enb[0] * vol.enb[1]);
+    const int E = 1 << vol.eshift;
+    const int x0 = bx * E, y0 = by * E, z0 = bz * E;
+    const int ex = min(E, vol.n[0] + 1 - x0), ey = min(E, vol.n[1] + 1 - y0), ez = min(E, vol.n[2] + 1 - z0);
+    const __amdgpu_buffer_rsrc_t rs = make_rsrc(vol.data, vol.data_bytes);
+    const Corners cn = corners_of(LAYOUT == LAYOUT_BRICKS ? 1u : Elem<KIND>::bytes, vol.sy, vol.sz);
+    float lo = INFINITY, hi = -INFINITY;
+    int nan = 0;
+    for (int c = threadIdx.x; c < ex * ey * ez; c += blockDim.x) {
+        const long long Q[3] = {(long long)(x0 + c % ex) << 32, (long long)(y0 + (c / ex) % ey) << 32,
+                                (long long)(z0 + c / (ex * ey)) << 32};
+        const typename S::Raw raw = S::load(rs, vol, cn, Q);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const float v = S::value(raw, (float)(k & 1), (float)((k >> 1) & 1), (float)(k >> 2));
+            nan |= v != v;
+            lo = fminf(lo, v);
+            hi = fmaxf(hi, v);
+        }
+    }
+    nan = __syncthreads_or(nan);
+    s_lo[threadIdx.x] = lo;
+    s_hi[threadIdx.x] = hi;
+    __syncthreads();
+    for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) {
+            s_lo[threadIdx.x] = fminf(s_lo[threadIdx.x], s_lo[threadIdx.x + st]);
+            s_hi[threadIdx.x] = fmaxf(s_hi[threadIdx.x], s_hi[threadIdx.x + st]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        const_cast<float2*>(vol.ess_range)[b] = nan ? make_float2(NAN, NAN) : make_float2(s_lo[0], s_hi[0]);
+}
+
+template <int KIND, int LAYOUT>
+hipError_t skip_range_launch(const VolDev& vol, hipStream_t s) {
+    const int nb = vol.enb[0] * vol.enb[1] * vol.enb[2];
+    hipLaunchKernelGGL((skip_range_kernel<KIND, LAYOUT>), dim3(nb), dim3(256), 0, s, vol);
+    return hipGetLastError();
 }
 
 __global__ void batch_reset_kernel(unsigned int* queue) {
@@ -655,35 +802,48 @@ int log2i(int x) {
     return s;
 }
 
-template <int KIND, int LAYOUT>
-hipError_t plain_launch(const ViewDesc& v, const LaunchShape& ls, unsigned long long* counter, hipStream_t s) {
+template <int KIND, int LAYOUT, bool SKIP>
+hipError_t plain_launch_k(const ViewDesc& v, const LaunchShape& ls, unsigned long long* counter, hipStream_t s) {
     const int nblk = v.nblocks;
     if (nblk <= 0) return hipSuccess;
-    const size_t lds = (size_t)(v.K + 1) * sizeof(float4);
+    const size_t lds = (size_t)(v.K + 1) * sizeof(float4) +
+                       (v.skip_empty ? (size_t)((v.vol.enb[0] * v.vol.enb[1] * v.vol.enb[2] + 31) / 32) * 4 : 0);
     static bool attr = false;
     if (!attr) {
-        (void)hipFuncSetAttribute((const void*)march_plain_kernel<KIND, LAYOUT>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)((kMaxK + 1) * sizeof(float4)));
+        (void)hipFuncSetAttribute((const void*)march_plain_kernel<KIND, LAYOUT, SKIP>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)((kMaxK + 1) * sizeof(float4) + kSkipMaskBytes));
         attr = true;
     }
-    hipLaunchKernelGGL((march_plain_kernel<KIND, LAYOUT>), dim3(nblk), dim3(64 * ls.waves), lds, s, v, ls, log2i(ls.tile_w),
-                       counter);
+    hipLaunchKernelGGL((march_plain_kernel<KIND, LAYOUT, SKIP>), dim3(nblk), dim3(64 * ls.waves), lds, s, v, ls,
+                       log2i(ls.tile_w), counter);
     return hipGetLastError();
 }
 
 template <int KIND, int LAYOUT>
-hipError_t batch_launch(void* ws, int grid, const LaunchShape& ls, int max_k, hipStream_t s) {
+hipError_t plain_launch(const ViewDesc& v, const LaunchShape& ls, unsigned long long* counter, hipStream_t s) {
+    return v.skip_empty ? plain_launch_k<KIND, LAYOUT, true>(v, ls, counter, s)
+                        : plain_launch_k<KIND, LAYOUT, false>(v, ls, counter, s);
+}
+
+template <int KIND, int LAYOUT, bool SKIP>
+hipError_t batch_launch_k(void* ws, int grid, const LaunchShape& ls, int max_k, hipStream_t s) {
     const int tf_entries = max_k + 1;
-    const size_t lds = (size_t)tf_entries * sizeof(float4) + 16;
+    const size_t lds = (size_t)tf_entries * sizeof(float4) + kSkipMaskBytes + 16;
     static bool attr = false;
     if (!attr) {
-        (void)hipFuncSetAttribute((const void*)march_batch_kernel<KIND, LAYOUT>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)((kMaxK + 1) * sizeof(float4) + 16));
+        (void)hipFuncSetAttribute((const void*)march_batch_kernel<KIND, LAYOUT, SKIP>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)((kMaxK + 1) * sizeof(float4) + kSkipMaskBytes + 16));
         attr = true;
     }
-    hipLaunchKernelGGL((march_batch_kernel<KIND, LAYOUT>), dim3(grid), dim3(64 * ls.waves), lds, s, static_cast<char*>(ws), ls,
-                       log2i(ls.tile_w), tf_entries);
+    hipLaunchKernelGGL((march_batch_kernel<KIND, LAYOUT, SKIP>), dim3(grid), dim3(64 * ls.waves), lds, s,
+                       static_cast<char*>(ws), ls, log2i(ls.tile_w), tf_entries);
     return hipGetLastError();
+}
+
+template <int KIND, int LAYOUT>
+hipError_t batch_launch(void* ws, int grid, const LaunchShape& ls, int max_k, bool skip, hipStream_t s) {
+    return skip ? batch_launch_k<KIND, LAYOUT, true>(ws, grid, ls, max_k, s)
+                : batch_launch_k<KIND, LAYOUT, false>(ws, grid, ls, max_k, s);
 }
 
 }  // namespace
@@ -713,27 +873,51 @@ hipError_t launch_march_plain(const ViewDesc& v, const LaunchShape& ls, unsigned
     }
 }
 
+hipError_t launch_skip_ranges(const VolDev& v, hipStream_t s) {
+    const int L = v.layout;
+    switch (v.kind) {
+        case ST_U8:
+            return L == LAYOUT_CELLS  ? skip_range_launch<ST_U8, LAYOUT_CELLS>(v, s)
+                   : L == LAYOUT_POLY ? skip_range_launch<ST_U8, LAYOUT_POLY>(v, s)
+                                      : skip_range_launch<ST_U8, LAYOUT_LINEAR>(v, s);
+        case ST_U16:
+            return L == LAYOUT_CELLS  ? skip_range_launch<ST_U16, LAYOUT_CELLS>(v, s)
+                   : L == LAYOUT_POLY ? skip_range_launch<ST_U16, LAYOUT_POLY>(v, s)
+                                      : skip_range_launch<ST_U16, LAYOUT_LINEAR>(v, s);
+        case ST_F16:
+            return L == LAYOUT_CELLS ? skip_range_launch<ST_F16, LAYOUT_CELLS>(v, s)
+                                     : skip_range_launch<ST_F16, LAYOUT_LINEAR>(v, s);
+        case ST_F32:
+            return L == LAYOUT_CELLS ? skip_range_launch<ST_F32, LAYOUT_CELLS>(v, s)
+                                     : skip_range_launch<ST_F32, LAYOUT_LINEAR>(v, s);
+        case ST_U8B:
+            return L == LAYOUT_CELLS ? skip_range_launch<ST_U8B, LAYOUT_CELLS>(v, s)
+                                     : skip_range_launch<ST_U8B, LAYOUT_BRICKS>(v, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 hipError_t launch_march_batch(int kind, int layout, void* workspace, int grid, const LaunchShape& ls, int max_k,
-                              hipStream_t s) {
+                              bool skip, hipStream_t s) {
     const bool C = layout == LAYOUT_CELLS, P = layout == LAYOUT_POLY;
     switch (kind) {
         case ST_U8:
-            return C   ? batch_launch<ST_U8, LAYOUT_CELLS>(workspace, grid, ls, max_k, s)
-                   : P ? batch_launch<ST_U8, LAYOUT_POLY>(workspace, grid, ls, max_k, s)
-                       : batch_launch<ST_U8, LAYOUT_LINEAR>(workspace, grid, ls, max_k, s);
+            return C   ? batch_launch<ST_U8, LAYOUT_CELLS>(workspace, grid, ls, max_k, skip, s)
+                   : P ? batch_launch<ST_U8, LAYOUT_POLY>(workspace, grid, ls, max_k, skip, s)
+                       : batch_launch<ST_U8, LAYOUT_LINEAR>(workspace, grid, ls, max_k, skip, s);
         case ST_U16:
-            return C   ? batch_launch<ST_U16, LAYOUT_CELLS>(workspace, grid, ls, max_k, s)
-                   : P ? batch_launch<ST_U16, LAYOUT_POLY>(workspace, grid, ls, max_k, s)
-                       : batch_launch<ST_U16, LAYOUT_LINEAR>(workspace, grid, ls, max_k, s);
+            return C   ? batch_launch<ST_U16, LAYOUT_CELLS>(workspace, grid, ls, max_k, skip, s)
+                   : P ? batch_launch<ST_U16, LAYOUT_POLY>(workspace, grid, ls, max_k, skip, s)
+                       : batch_launch<ST_U16, LAYOUT_LINEAR>(workspace, grid, ls, max_k, skip, s);
         case ST_F16:
-            return C ? batch_launch<ST_F16, LAYOUT_CELLS>(workspace, grid, ls, max_k, s)
-                     : batch_launch<ST_F16, LAYOUT_LINEAR>(workspace, grid, ls, max_k, s);
+            return C ? batch_launch<ST_F16, LAYOUT_CELLS>(workspace, grid, ls, max_k, skip, s)
+                     : batch_launch<ST_F16, LAYOUT_LINEAR>(workspace, grid, ls, max_k, skip, s);
         case ST_F32:
-            return C ? batch_launch<ST_F32, LAYOUT_CELLS>(workspace, grid, ls, max_k, s)
-                     : batch_launch<ST_F32, LAYOUT_LINEAR>(workspace, grid, ls, max_k, s);
+            return C ? batch_launch<ST_F32, LAYOUT_CELLS>(workspace, grid, ls, max_k, skip, s)
+                     : batch_launch<ST_F32, LAYOUT_LINEAR>(workspace, grid, ls, max_k, skip, s);
         case ST_U8B:
-            return C ? batch_launch<ST_U8B, LAYOUT_CELLS>(workspace, grid, ls, max_k, s)
-                     : batch_launch<ST_U8B, LAYOUT_BRICKS>(workspace, grid, ls, max_k, s);
+            return C ? batch_launch<ST_U8B, LAYOUT_CELLS>(workspace, grid, ls, max_k, skip, s)
+                     : batch_launch<ST_U8B, LAYOUT_BRICKS>(workspace, grid, ls, max_k, skip, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -747,10 +931,10 @@ int batch_persistent_grid(const LaunchShape& ls, int max_k) {
     int dev = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    const size_t lds = (size_t)(max_k + 1) * sizeof(float4) + 16;
-    (void)hipFuncSetAttribute((const void*)march_batch_kernel<ST_U16, LAYOUT_CELLS>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                        (int)lds);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)march_batch_kernel<ST_U16, LAYOUT_CELLS>,
+    const size_t lds = (size_t)(max_k + 1) * sizeof(float4) + kSkipMaskBytes + 16;
+    (void)hipFuncSetAttribute((const void*)march_batch_kernel<ST_U16, LAYOUT_CELLS, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        (int)((kMaxK + 1) * sizeof(float4) + kSkipMaskBytes + 16));
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)march_batch_kernel<ST_U16, LAYOUT_CELLS, false>,
                                                      64 * ls.waves, lds) != hipSuccess)
         per_cu = 1;
     if (per_cu < 1) per_cu = 1;

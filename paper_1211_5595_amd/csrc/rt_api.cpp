@@ -77,6 +77,12 @@ int elem_bytes(int kind) {
 
 size_t round256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Transfer-function buffer: the K x 4 table, then (256-aligned) K+2 running
+// counts nz[j] of the entries i < j with nonzero opacity over the table
+// extended by a copy of its last entry (the lookup reads entries j0, j0+1).
+size_t tf_nz_offset(int K) { return round256((size_t)K * 16); }
+size_t tf_layout_bytes(int K) { return tf_nz_offset(K) + round256((size_t)(K + 2) * 4); }
+
 struct Layout {
     size_t total;             // bytes
     size_t data_offset;       // start of the grid / cells / codes
@@ -88,9 +94,33 @@ struct Layout {
     int32_t brick_nb[3];      // U8B cells: bricks per axis
     int32_t bshift;
     int32_t layout;
+    size_t ess_offset;        // skip-brick value ranges (float2 each), after everything else
+    int32_t enb[3];
+    int32_t eshift;
 };
 
+rt_status compute_data_layout(const int64_t dims[3], int storage, int layout, int brick, Layout& L);
+
+// Skip bricks: 2^eshift padded cells per axis (cells 0..n), the smallest
+// power of two from 8 up that keeps the count within kMaxSkipBricks.
 rt_status compute_layout(const int64_t dims[3], int storage, int layout, int brick, Layout& L) {
+    rt_status st = compute_data_layout(dims, storage, layout, brick, L);
+    if (st != RT_OK) return st;
+    for (L.eshift = 3;; ++L.eshift) {
+        size_t nbt = 1;
+        for (int a = 0; a < 3; ++a) {
+            L.enb[a] = (int32_t)(((size_t)dims[a] + 1 + ((size_t)1 << L.eshift) - 1) >> L.eshift);
+            nbt *= (size_t)L.enb[a];
+        }
+        if (nbt <= (size_t)kMaxSkipBricks) {
+            L.ess_offset = L.total;
+            L.total = round256(L.total + nbt * sizeof(float2));
+            return RT_OK;
+        }
+    }
+}
+
+rt_status compute_data_layout(const int64_t dims[3], int storage, int layout, int brick, Layout& L) {
     if (!dims) return fail(RT_ERR_INVALID_ARG, "dims is NULL");
     for (int a = 0; a < 3; ++a)
         if (dims[a] < 2 || dims[a] > (1 << 20)) return fail(RT_ERR_INVALID_ARG, "each dimension must be in [2, 2^20]");
@@ -213,7 +243,8 @@ rt_status make_shape(const rt_render_opts* opts, LaunchShape& ls) {
 
 rt_status make_view(const rt_volume* vol, const int64_t dims[3], const double spacing[3], const rt_tf* tf,
                     const rt_camera* cam, int W, int H, double step_vox, double cutoff, const float* bg,
-                    float* out, int32_t* counts, const LaunchShape& ls, int ray_function, ViewDesc& v) {
+                    float* out, int32_t* counts, const LaunchShape& ls, int ray_function, int skip_empty,
+                    ViewDesc& v) {
     if (!vol || !tf || !cam || !out) return fail(RT_ERR_INVALID_ARG, "NULL volume, transfer function, camera or output");
     if (dims)
         for (int a = 0; a < 3; ++a)
@@ -280,6 +311,8 @@ rt_status make_view(const rt_volume* vol, const int64_t dims[3], const double sp
     v.ray_function = ray_function;
     v.vol = vol->dev;
     v.tf = tf->dev;
+    v.tf_nz = reinterpret_cast<const int32_t*>(reinterpret_cast<const char*>(tf->dev) + tf_nz_offset(tf->K));
+    v.skip_empty = (skip_empty && ray_function == RT_COMPOSITE) ? 1 : 0;
     v.K = tf->K;
     const double ta = (double)(tf->K - 1) / (tf->vmax - tf->vmin);
     v.tf_a = (float)ta;
@@ -338,7 +371,8 @@ rt_status build_batch(const rt_render_job* jobs, int n, const LaunchShape& ls, i
         const rt_render_job& J = jobs[i];
         if (!J.volume) return fail(RT_ERR_INVALID_ARG, "job without volume");
         rt_status st = make_view(J.volume, nullptr, nullptr, J.tf, &J.camera, J.width, J.height, J.step_vox,
-                                 J.alpha_cutoff, J.bg_rgba, J.out_dev, J.pixel_counts, ls, J.ray_function, descs[i]);
+                                 J.alpha_cutoff, J.bg_rgba, J.out_dev, J.pixel_counts, ls, J.ray_function,
+                                 J.skip_empty, descs[i]);
         if (st != RT_OK) return fail(st, "job " + std::to_string(i) + ": " + g_last_error);
         const int k = J.volume->dev.kind * 4 + J.volume->dev.layout;  // storage type and layout
         if (*kind < 0) *kind = k;
@@ -455,8 +489,18 @@ rt_status rt_create_volume(const void* src_dev, int src_dtype, const int64_t dim
     v->dev.bshift = L.bshift;
     v->dev.kind = storage == RT_U8_BRICKSCALED ? ST_U8B : storage;
     v->dev.layout = L.layout;
+    v->dev.ess_range = reinterpret_cast<const float2*>(base + L.ess_offset);
+    for (int a = 0; a < 3; ++a) v->dev.enb[a] = L.enb[a];
+    v->dev.eshift = L.eshift;
+    v->dev.esy = (uint32_t)L.enb[0];
+    v->dev.esz = (uint32_t)(L.enb[0] * L.enb[1]);
     v->storage = storage;
     v->brick = brick;
+    e = launch_skip_ranges(v->dev, s);
+    if (e != hipSuccess) {
+        delete v;
+        return hip_fail(e, "skip-range launch");
+    }
     *out = v;
     return RT_OK;
 }
@@ -469,7 +513,7 @@ rt_status rt_destroy_volume(rt_volume* vol) {
 rt_status rt_tf_bytes(int K, size_t* bytes) {
     if (!bytes) return fail(RT_ERR_INVALID_ARG, "bytes is NULL");
     if (K < 2 || K > kMaxK) return fail(RT_ERR_INVALID_ARG, "K must be in [2, 4096]");
-    *bytes = round256((size_t)K * 16);
+    *bytes = tf_layout_bytes(K);
     return RT_OK;
 }
 
@@ -480,7 +524,7 @@ rt_status rt_set_transfer_function(rt_tf** tf, const float* rgba, int K, double 
     if (!std::isfinite(vmin) || !std::isfinite(vmax) || !(vmax > vmin)) return fail(RT_ERR_INVALID_ARG, "need vmin < vmax");
     for (int i = 0; i < 4 * K; ++i)
         if (!(rgba[i] >= 0.0f && rgba[i] <= 1.0f)) return fail(RT_ERR_INVALID_ARG, "table entries must be in [0, 1]");
-    const size_t need = (size_t)K * 16;
+    const size_t need = tf_layout_bytes(K);
     rt_tf* t = *tf;
     if (t) {
         if (t->K != K || (dev_buf && dev_buf != (const void*)t->dev))
@@ -508,7 +552,10 @@ rt_status rt_set_transfer_function(rt_tf** tf, const float* rgba, int K, double 
         if (e != hipSuccess) return hip_fail(e, "waiting for the previous table upload");
         t->pending = false;
     }
-    std::memcpy(t->staging, rgba, need);
+    std::memcpy(t->staging, rgba, (size_t)K * 16);
+    int32_t* nz = reinterpret_cast<int32_t*>(static_cast<char*>(t->staging) + tf_nz_offset(K));
+    nz[0] = 0;
+    for (int j = 0; j <= K; ++j) nz[j + 1] = nz[j] + (rgba[4 * std::min(j, K - 1) + 3] > 0.0f ? 1 : 0);
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipError_t e = hipMemcpyAsync(const_cast<float4*>(t->dev), t->staging, need, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipEventRecord(t->copied, s);
@@ -545,7 +592,8 @@ rt_status rt_render(const rt_volume* volume, const int64_t dims[3], const double
     if (st != RT_OK) return st;
     ViewDesc v;
     st = make_view(volume, dims, spacing, tf, camera, width, height, step_vox, alpha_cutoff, bg_rgba, out_dev,
-                   opts ? opts->pixel_counts : nullptr, ls, opts ? opts->ray_function : 0, v);
+                   opts ? opts->pixel_counts : nullptr, ls, opts ? opts->ray_function : 0,
+                   opts ? opts->skip_empty : 0, v);
     if (st != RT_OK) return st;
     hipError_t e = launch_march_plain(v, ls, opts ? opts->sample_counter : nullptr, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "render launch");
@@ -584,7 +632,9 @@ rt_status rt_render_batch(const rt_render_job* jobs, int n, void* workspace, siz
     if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
     g_staging.pending = true;
     const int grid = std::min(batch_persistent_grid(ls, max_k), std::max(prefix.back(), 1));
-    e = launch_march_batch(kind / 4, kind % 4, workspace, grid, ls, max_k, s);
+    bool skip = false;
+    for (const ViewDesc& d : descs) skip = skip || d.skip_empty;
+    e = launch_march_batch(kind / 4, kind % 4, workspace, grid, ls, max_k, skip, s);
     if (e != hipSuccess) return hip_fail(e, "batch launch");
     return RT_OK;
 }
@@ -626,7 +676,8 @@ rt_status rt_batch_plan_create(int max_jobs, int storage, int layout, void* work
     }
     e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) e = launch_batch_reset(workspace, cs);
-    if (e == hipSuccess) e = launch_march_batch(p->kind / 4, p->kind % 4, workspace, p->grid, ls, kMaxK, cs);
+    if (e == hipSuccess)
+        e = launch_march_batch(p->kind / 4, p->kind % 4, workspace, p->grid, ls, kMaxK, opts && opts->skip_empty, cs);
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(cs, &g);
     if (e == hipSuccess) e = e2;

@@ -51,7 +51,18 @@ struct VolDev {
     int32_t bshift;             // BRICKS: log2(B)
     int32_t kind;               // StorageKind
     int32_t layout;             // LayoutKind
+    // Empty-space skipping: the padded cells 0..n per axis are grouped in skip
+    // bricks of 2^eshift cells per axis; ess_range holds, per skip brick
+    // (x fastest), the smallest and largest value the sampler can return for
+    // a sample in one of its cells (NaN when a corner is NaN).
+    const float2* ess_range;
+    int32_t enb[3];             // skip bricks per axis
+    int32_t eshift;
+    uint32_t esy, esz;          // skip-brick index strides: enb[0], enb[0]*enb[1]
 };
+// At most this many skip bricks per volume (their empty bits fit in 8 KB of LDS).
+static constexpr int kMaxSkipBricks = 65536;
+static constexpr int kSkipMaskBytes = kMaxSkipBricks / 8;
 
 // Everything one view needs; computed on the host in binary64, rounded to
 // float-float.  Pixel (i,j) uses a = 2i+1-W, b = H-2j-1:
@@ -75,6 +86,8 @@ struct ViewDesc {
     float iso_lo, iso_hi;
     VolDev vol;
     const float4* tf;           // K entries
+    const int32_t* tf_nz;       // K+2 entries: nz[j] = number of table entries i < j (entry K = entry K-1) with alpha > 0
+    int32_t skip_empty;         // nonzero: leap over skip bricks whose samples all have zero opacity
     int32_t K;
     float tf_a, tf_b;           // x = val*tf_a + tf_b, clamped to [0, K-1]
     float* out;                 // H*W float4
@@ -108,10 +121,14 @@ hipError_t launch_march_plain(const ViewDesc& v, const LaunchShape& ls, unsigned
                               hipStream_t s);
 // Views, prefix, job count and counter pointer are read from the workspace,
 // so one captured launch serves every batch that fits the workspace.
+// skip: use the kernel with empty-space skipping (for the jobs that ask for it).
 hipError_t launch_march_batch(int kind, int layout, void* workspace, int grid, const LaunchShape& ls, int max_k,
-                              hipStream_t s);
+                              bool skip, hipStream_t s);
 hipError_t launch_batch_reset(void* workspace, hipStream_t s);
 int batch_persistent_grid(const LaunchShape& ls, int max_k);
+
+// Per skip brick value range of a volume in its storage layout (march.hip).
+hipError_t launch_skip_ranges(const VolDev& vol, hipStream_t s);
 
 hipError_t launch_relayout_linear(const void* src, int src_kind, int dst_kind, const int32_t n[3], void* dst,
                                   hipStream_t s);

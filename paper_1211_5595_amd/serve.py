@@ -283,7 +283,8 @@ class GpuExecutor:
 
     @staticmethod
     def request_bytes(req: RenderRequest) -> int:
-        return req.width * req.height * 16 + ((req.tf_rgba.shape[0] * 16 + 255) // 256) * 256
+        from . import rt_tf_bytes
+        return req.width * req.height * 16 + rt_tf_bytes(int(req.tf_rgba.shape[0]))
 
     # batches
     def slot_free(self) -> bool:

@@ -40,28 +40,52 @@ def test_oracle_and_product_share_no_symbols(rt, orc):
         assert not hasattr(L, n)
 
 
+def skip_bytes(dims):
+    """Skip-brick value ranges appended to every layout: bricks of 2^e padded
+    cells (0..n per axis), the smallest e >= 3 with at most 65536 bricks,
+    8 bytes each, rounded to 256."""
+    e = 3
+    while True:
+        nb = 1
+        for n in dims:
+            nb *= (n + 1 + (1 << e) - 1) >> e
+        if nb <= 65536:
+            return (nb * 8 + 255) // 256 * 256
+        e += 1
+
+
+def test_skip_brick_counts():
+    assert skip_bytes((256, 256, 160)) == (33 * 33 * 21 * 8 + 255) // 256 * 256
+    assert skip_bytes((512, 512, 256)) == (33 * 33 * 17 * 8 + 255) // 256 * 256   # 16^3-cell bricks
+    assert skip_bytes((2, 2, 2)) == 256
+
+
 def test_volume_bytes(rt):
     r256 = lambda x: (x + 255) // 256 * 256
+
+    def vb(dims, *a):
+        return rt.rt_volume_bytes(dims, *a) - skip_bytes(dims)
+
     # linear: (n+2)^3 padded nodes times the element size, rounded to 256
     L = rt.LAYOUT_LINEAR
-    assert rt.rt_volume_bytes((256, 256, 160), rt.U16, L) == ((258 * 258 * 162 * 2 + 255) // 256) * 256
-    assert rt.rt_volume_bytes((64, 64, 32), rt.U8, L) == ((66 * 66 * 34 + 255) // 256) * 256
-    assert rt.rt_volume_bytes((2, 2, 2), rt.F32, L) == 256
+    assert vb((256, 256, 160), rt.U16, L) == ((258 * 258 * 162 * 2 + 255) // 256) * 256
+    assert vb((64, 64, 32), rt.U8, L) == ((66 * 66 * 34 + 255) // 256) * 256
+    assert vb((2, 2, 2), rt.F32, L) == 256
     # cells: padded cells 0..n per axis rounded up to 2x2x2 blocks, 8 corners each
-    assert rt.rt_volume_bytes((256, 256, 160), rt.U16) == r256(129 * 129 * 81 * 8 * 8 * 2)
-    assert rt.rt_volume_bytes((64, 64, 32), rt.U8) == r256(33 * 33 * 17 * 8 * 8)
-    assert rt.rt_volume_bytes((2, 2, 2), rt.F32) == r256(2 * 2 * 2 * 8 * 8 * 4)
+    assert vb((256, 256, 160), rt.U16) == r256(129 * 129 * 81 * 8 * 8 * 2)
+    assert vb((64, 64, 32), rt.U8) == r256(33 * 33 * 17 * 8 * 8)
+    assert vb((2, 2, 2), rt.F32) == r256(2 * 2 * 2 * 8 * 8 * 4)
     # polynomial cells (integer data): as cells, 8 binary32 coefficients each
-    assert rt.rt_volume_bytes((256, 256, 160), rt.U16, rt.LAYOUT_POLY) == r256(129 * 129 * 81 * 8 * 8 * 4)
-    assert rt.rt_volume_bytes((64, 64, 32), rt.U8, rt.LAYOUT_POLY) == r256(33 * 33 * 17 * 8 * 8 * 4)
+    assert vb((256, 256, 160), rt.U16, rt.LAYOUT_POLY) == r256(129 * 129 * 81 * 8 * 8 * 4)
+    assert vb((64, 64, 32), rt.U8, rt.LAYOUT_POLY) == r256(33 * 33 * 17 * 8 * 8 * 4)
     # brick-scaled, halo bricks: ceil((n-1)/B) bricks per axis, (B+3)^3 codes and 8 bytes each
     nb = 16 * 16 * 10
-    assert rt.rt_volume_bytes((256, 256, 160), rt.U8_BRICKSCALED, rt.LAYOUT_BRICKS, 16) == \
+    assert vb((256, 256, 160), rt.U8_BRICKSCALED, rt.LAYOUT_BRICKS, 16) == \
         r256(r256(nb * 8) + nb * 19 ** 3)
     # brick-scaled, cells: (n+1)//2+1 shifted blocks per axis, 64 B of codes and 8 B each,
     # then the per-brick parameters
     ncb = 129 * 129 * 81
-    assert rt.rt_volume_bytes((256, 256, 160), rt.U8_BRICKSCALED, rt.LAYOUT_CELLS, 16) == \
+    assert vb((256, 256, 160), rt.U8_BRICKSCALED, rt.LAYOUT_CELLS, 16) == \
         r256(r256(r256(ncb * 8) + ncb * 64) + nb * 8)
 
 
@@ -84,7 +108,8 @@ def test_volume_bytes_errors(rt, dims, storage, layout, brick, exc):
 
 
 def test_tf_and_workspace_bytes(rt):
-    assert rt.rt_tf_bytes(4096) == 65536 and rt.rt_tf_bytes(2) == 256
+    # table (256-aligned) then K+2 int32 running counts (256-aligned)
+    assert rt.rt_tf_bytes(4096) == 65536 + 16640 and rt.rt_tf_bytes(2) == 512
     for K in (1, 4097):
         with pytest.raises(rt.InvalidArgument):
             rt.rt_tf_bytes(K)
