@@ -441,19 +441,37 @@ __device__ __forceinline__ bool range_is_empty(const VD& V, float2 r) {
     return V.tf_nz[j1 + 1] == V.tf_nz[j0];
 }
 
-// One bit per skip brick of the view's volume, for its table, in LDS.
+// One bit per range (empty or not for the view's table) into LDS: one range
+// per lane, four per lane in flight, words assembled by ballot.
 template <class VD>
-__device__ __forceinline__ void build_skip_mask(uint32_t* s_mask, const VD& V) {
-    const int nb = V.vol.enb[0] * V.vol.enb[1] * V.vol.enb[2];
-    for (int w = threadIdx.x; w < ((nb + 31) >> 5); w += blockDim.x) {
-        uint32_t bits = 0;
-        const int b0 = w << 5, b1 = min(b0 + 32, nb);
-        for (int b = b0; b < b1; ++b)
-            if (range_is_empty(V, V.vol.ess_range[b])) bits |= 1u << (b - b0);
-        s_mask[w] = bits;
+__device__ __forceinline__ void build_bits(uint32_t* dst, const float2* ranges, int count, const VD& V) {
+    const int words = (count + 31) >> 5;
+    const int lane = threadIdx.x & 63, step = (int)blockDim.x;
+    for (int base = (int)(threadIdx.x & ~63u); base < count; base += 4 * step) {
+        float2 r[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int b = base + u * step + lane;
+            r[u] = b < count ? ranges[b] : make_float2(1.0f, 0.0f);  // past the end: not empty
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const unsigned long long m = __builtin_amdgcn_ballot_w64(range_is_empty(V, r[u]));
+            const int w = ((base + u * step) >> 5) + (lane >> 5);
+            if ((lane & 31) == 0 && w < words) dst[w] = lane ? (uint32_t)(m >> 32) : (uint32_t)m;
+        }
     }
 }
 
+// The view's skip bricks and super-bricks (4x4x4 skip bricks, with the union
+// of their bricks' ranges), one bit each, in LDS.
+template <class VD>
+__device__ __forceinline__ void build_skip_mask(uint32_t* s_mask, const VD& V) {
+    build_bits(s_mask, V.vol.ess_range, V.vol.enb[0] * V.vol.enb[1] * V.vol.enb[2], V);
+    build_bits(s_mask + kSkipWords, V.vol.ess_super, V.vol.snb[0] * V.vol.snb[1] * V.vol.snb[2], V);
+}
+
+// Is the skip brick of the cell at Q empty?
 template <class VOL>
 __device__ __forceinline__ bool in_empty_brick(const uint32_t* s_mask, const VOL& vol, const long long Q[3]) {
     const uint32_t es = (uint32_t)vol.eshift;
@@ -462,31 +480,44 @@ __device__ __forceinline__ bool in_empty_brick(const uint32_t* s_mask, const VOL
     return (s_mask[b >> 5] >> (b & 31)) & 1u;
 }
 
-__device__ __forceinline__ float u64_to_float(unsigned long long x) {
-    return fmaf((float)(uint32_t)(x >> 32), 0x1p32f, (float)(uint32_t)x);
-}
-
 // A lower bound (at least 1) on the number of consecutive samples, from the
-// one at Q on, whose cells lie in Q's skip brick.  Per axis the exact count
-// is ceil(t) (moving up) or floor(t) + 1 (moving down) with t the distance to
-// the brick face over the step; t is evaluated in binary32 with relative
-// error below 2^-20 and shrunk by 2^-16 before rounding down.
-template <class VOL>
-__device__ __forceinline__ int samples_in_brick(const VOL& vol, const long long Q[3], const long long dQ[3]) {
-    const uint32_t es = (uint32_t)vol.eshift;
+// one at Q on, whose cells lie in Q's block of 2^sh cells per axis.  Per axis
+// the exact count is ceil(t) moving up (or not moving) and floor(t) + 1
+// moving down, t = distance to the block face in cells over the step in
+// cells.  Both are formed in binary32 and pushed down past their rounding
+// (an absolute 2^-22 cells and a relative 2^-18), so t is never overstated.
+__device__ __forceinline__ int samples_in_block(const long long Q[3], const long long dQ[3], uint32_t sh) {
     float n = 3.0e38f;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const long long d = dQ[a];
-        if (d == 0) continue;
-        const uint32_t b = hiword(Q[a]) >> es;
-        const long long face = (long long)((unsigned long long)((b + (d > 0 ? 1u : 0u)) << es) << 32);
-        const unsigned long long dist = (unsigned long long)(d > 0 ? face - Q[a] : Q[a] - face);
-        const unsigned long long ad = (unsigned long long)(d > 0 ? d : -d);
-        const float t = u64_to_float(dist) * __builtin_amdgcn_rcpf(u64_to_float(ad)) * (1.0f - 0x1p-16f);
-        n = fminf(n, floorf(t) + (d > 0 ? 0.0f : 1.0f));
+        const bool down = d < 0;
+        const uint32_t c = hiword(Q[a]);
+        const uint32_t face = ((c >> sh) + (down ? 0u : 1u)) << sh;
+        const float whole = (float)(down ? c - face : face - c);
+        const float dist = fmaf((float)(uint32_t)Q[a], down ? 0x1p-32f : -0x1p-32f, whole);
+        const unsigned long long ad = (unsigned long long)(down ? -d : d);
+        const float step = fmaf((float)(uint32_t)ad, 0x1p-32f, (float)(uint32_t)(ad >> 32));
+        const float t = fmaf(dist, 1.0f - 0x1p-20f, -0x1p-22f) * (__builtin_amdgcn_rcpf(step) * (1.0f - 0x1p-18f));
+        n = fminf(n, floorf(t) + (down ? 1.0f : 0.0f));
     }
     return (int)fmaxf(fminf(n, 1.0e9f), 1.0f);
+}
+
+// Advance Q past the samples that lie in its (empty) skip brick, or in its
+// super-brick when that is empty too; at most `left` samples.  Returns the
+// number of samples stepped over.
+template <class VOL>
+__device__ __forceinline__ int leap(const uint32_t* s_mask, const VOL& vol, long long Q[3], const long long dQ[3],
+                                    int left) {
+    const uint32_t es = (uint32_t)vol.eshift, sh = es + 2u;
+    const uint32_t q = (hiword(Q[0]) >> sh) + __umul24(hiword(Q[1]) >> sh, vol.ssy) + __umul24(hiword(Q[2]) >> sh, vol.ssz);
+    const bool super_empty = (s_mask[kSkipWords + (q >> 5)] >> (q & 31)) & 1u;
+    const uint32_t n = (uint32_t)min(samples_in_block(Q, dQ, super_empty ? sh : es), left);
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+        Q[a] = (long long)((unsigned long long)Q[a] + (unsigned long long)n * (unsigned long long)dQ[a]);
+    return (int)n;
 }
 
 template <int KIND, int LAYOUT, bool SKIP, class VD>
@@ -502,19 +533,26 @@ __device__ __forceinline__ void march_pixel(const VD& V, const float4* __restric
         const float ta = V.tf_a, tb = V.tf_b, thr = V.thr;
         if (R.m > 0) {
             typename S::Raw cur = S::load(rs, V.vol, cn, R.Q);
+            // wavefront-uniform: the bricks are looked at every 4th sample and
+            // after each leap; a leap leaves `cur` stale (reloaded only when a
+            // sample is taken, so a run of leaps never waits on memory)
+            int it = 0;
+            bool stale = false;
             for (;;) {
                 if constexpr (SKIP) {
                     // all live rays of the wavefront in empty bricks: each leaps to
                     // its first sample outside its brick (or to the end of its ray)
-                    if (V.skip_empty && __builtin_amdgcn_ballot_w64(!in_empty_brick(s_mask, V.vol, R.Q)) == 0) {
-                        const int n = min(samples_in_brick(V.vol, R.Q, R.dQ), R.m - k);
-                        R.Q[0] += (long long)n * R.dQ[0];
-                        R.Q[1] += (long long)n * R.dQ[1];
-                        R.Q[2] += (long long)n * R.dQ[2];
-                        k += n;
+                    if (V.skip_empty && (it++ & 3) == 0 &&
+                        __builtin_amdgcn_ballot_w64(!in_empty_brick(s_mask, V.vol, R.Q)) == 0) {
+                        it = 0;
+                        k += leap(s_mask, V.vol, R.Q, R.dQ, R.m - k);
                         if (k >= R.m) break;
-                        cur = S::load(rs, V.vol, cn, R.Q);
+                        stale = true;
                         continue;
+                    }
+                    if (stale) {
+                        cur = S::load(rs, V.vol, cn, R.Q);
+                        stale = false;
                     }
                 }
                 const long long Qn[3] = {R.Q[0] + R.dQ[0], R.Q[1] + R.dQ[1], R.Q[2] + R.dQ[2]};
@@ -707,9 +745,10 @@ __global__ void RT_MARCH_ATTRS march_batch_kernel(char* __restrict__ ws, const L
     const int n_jobs = (int)hdr->n_jobs;
     unsigned long long* counter = hdr->counter;
     const int total = prefix[n_jobs];
-    const float4* cur_tf = nullptr;
-    const float2* mask_vol = nullptr;   // the (volume, table) pair the mask in LDS was built for
-    const float4* mask_tf = nullptr;
+    // the table in LDS and the (volume, table) pair the mask was built for live
+    // in LDS, not in scalar registers that would stay live across the marcher
+    __shared__ const void* s_have[3];
+    if (threadIdx.x == 0) s_have[0] = s_have[1] = s_have[2] = nullptr;
     for (;;) {
         if (threadIdx.x == 0) s_claim[0] = (int)atomicAdd(queue, 1u);
         __syncthreads();
@@ -722,17 +761,19 @@ __global__ void RT_MARCH_ATTRS march_batch_kernel(char* __restrict__ ws, const L
             else hi = mid;
         }
         const CViewDesc& V = jobs[lo];
-        const bool new_tf = V.tf != cur_tf;
-        const bool new_mask = SKIP && V.skip_empty && (V.vol.ess_range != mask_vol || V.tf != mask_tf);
+        const bool new_tf = (const void*)V.tf != s_have[0];
+        const bool new_mask = SKIP && V.skip_empty && ((const void*)V.vol.ess_range != s_have[1] ||
+                                                       (const void*)V.tf != s_have[2]);
         if (new_tf || new_mask) {
-            if (new_tf) {
-                cur_tf = V.tf;
-                load_tf(s_tf, V.tf, V.K);
-            }
-            if (new_mask) {
-                mask_vol = V.vol.ess_range;
-                mask_tf = V.tf;
-                build_skip_mask(s_mask, V);
+            __syncthreads();  // every lane has read s_have
+            if (new_tf) load_tf(s_tf, V.tf, V.K);
+            if (new_mask) build_skip_mask(s_mask, V);
+            if (threadIdx.x == 0) {
+                s_have[0] = V.tf;
+                if (new_mask) {
+                    s_have[1] = V.vol.ess_range;
+                    s_have[2] = V.tf;
+                }
             }
             __syncthreads();
         }
@@ -785,10 +826,31 @@ __global__ void __launch_bounds__(256) skip_range_kernel(const VolDev vol) {
         const_cast<float2*>(vol.ess_range)[b] = nan ? make_float2(NAN, NAN) : make_float2(s_lo[0], s_hi[0]);
 }
 
+// Super-brick ranges: the union of the ranges of its (up to 64) skip bricks,
+// NaN when any of them is NaN.
+__global__ void __launch_bounds__(256) super_range_kernel(const VolDev vol) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= vol.snb[0] * vol.snb[1] * vol.snb[2]) return;
+    const int qx = q % vol.snb[0], qy = (q / vol.snb[0]) % vol.snb[1], qz = q / (vol.snb[0] * vol.snb[1]);
+    float lo = INFINITY, hi = -INFINITY;
+    bool nan = false;
+    for (int bz = 4 * qz; bz < min(4 * qz + 4, vol.enb[2]); ++bz)
+        for (int by = 4 * qy; by < min(4 * qy + 4, vol.enb[1]); ++by)
+            for (int bx = 4 * qx; bx < min(4 * qx + 4, vol.enb[0]); ++bx) {
+                const float2 r = vol.ess_range[bx + vol.enb[0] * (by + vol.enb[1] * bz)];
+                nan = nan || !(r.x <= r.y);
+                lo = fminf(lo, r.x);
+                hi = fmaxf(hi, r.y);
+            }
+    const_cast<float2*>(vol.ess_super)[q] = nan ? make_float2(NAN, NAN) : make_float2(lo, hi);
+}
+
 template <int KIND, int LAYOUT>
 hipError_t skip_range_launch(const VolDev& vol, hipStream_t s) {
     const int nb = vol.enb[0] * vol.enb[1] * vol.enb[2];
     hipLaunchKernelGGL((skip_range_kernel<KIND, LAYOUT>), dim3(nb), dim3(256), 0, s, vol);
+    const int ns = vol.snb[0] * vol.snb[1] * vol.snb[2];
+    hipLaunchKernelGGL(super_range_kernel, dim3((ns + 255) / 256), dim3(256), 0, s, vol);
     return hipGetLastError();
 }
 
@@ -806,8 +868,7 @@ template <int KIND, int LAYOUT, bool SKIP>
 hipError_t plain_launch_k(const ViewDesc& v, const LaunchShape& ls, unsigned long long* counter, hipStream_t s) {
     const int nblk = v.nblocks;
     if (nblk <= 0) return hipSuccess;
-    const size_t lds = (size_t)(v.K + 1) * sizeof(float4) +
-                       (v.skip_empty ? (size_t)((v.vol.enb[0] * v.vol.enb[1] * v.vol.enb[2] + 31) / 32) * 4 : 0);
+    const size_t lds = (size_t)(v.K + 1) * sizeof(float4) + (v.skip_empty ? (size_t)kSkipMaskBytes : 0);
     static bool attr = false;
     if (!attr) {
         (void)hipFuncSetAttribute((const void*)march_plain_kernel<KIND, LAYOUT, SKIP>, hipFuncAttributeMaxDynamicSharedMemorySize,

@@ -97,6 +97,8 @@ struct Layout {
     size_t ess_offset;        // skip-brick value ranges (float2 each), after everything else
     int32_t enb[3];
     int32_t eshift;
+    size_t sup_offset;        // super-brick ranges, after the skip-brick ranges
+    int32_t snb[3];
 };
 
 rt_status compute_data_layout(const int64_t dims[3], int storage, int layout, int brick, Layout& L);
@@ -114,7 +116,13 @@ rt_status compute_layout(const int64_t dims[3], int storage, int layout, int bri
         }
         if (nbt <= (size_t)kMaxSkipBricks) {
             L.ess_offset = L.total;
-            L.total = round256(L.total + nbt * sizeof(float2));
+            L.sup_offset = round256(L.ess_offset + nbt * sizeof(float2));
+            size_t nst = 1;
+            for (int a = 0; a < 3; ++a) {
+                L.snb[a] = (L.enb[a] + 3) / 4;
+                nst *= (size_t)L.snb[a];
+            }
+            L.total = round256(L.sup_offset + nst * sizeof(float2));
             return RT_OK;
         }
     }
@@ -494,6 +502,10 @@ rt_status rt_create_volume(const void* src_dev, int src_dtype, const int64_t dim
     v->dev.eshift = L.eshift;
     v->dev.esy = (uint32_t)L.enb[0];
     v->dev.esz = (uint32_t)(L.enb[0] * L.enb[1]);
+    v->dev.ess_super = reinterpret_cast<const float2*>(base + L.sup_offset);
+    for (int a = 0; a < 3; ++a) v->dev.snb[a] = L.snb[a];
+    v->dev.ssy = (uint32_t)L.snb[0];
+    v->dev.ssz = (uint32_t)(L.snb[0] * L.snb[1]);
     v->storage = storage;
     v->brick = brick;
     e = launch_skip_ranges(v->dev, s);

@@ -59,10 +59,18 @@ struct VolDev {
     int32_t enb[3];             // skip bricks per axis
     int32_t eshift;
     uint32_t esy, esz;          // skip-brick index strides: enb[0], enb[0]*enb[1]
+    // super-bricks of 4x4x4 skip bricks: the union of their bricks' ranges
+    const float2* ess_super;
+    int32_t snb[3];             // super-bricks per axis: ceil(enb / 4)
+    uint32_t ssy, ssz;          // super-brick index strides
 };
-// At most this many skip bricks per volume (their empty bits fit in 8 KB of LDS).
+// At most this many skip bricks per volume (their empty bits fit in 8 KB of
+// LDS).  Groups of 4x4x4 skip bricks (super-bricks) get a second mask, at most
+// 544 words for any brick-grid shape within the limit (ceil(e/4) products).
 static constexpr int kMaxSkipBricks = 65536;
-static constexpr int kSkipMaskBytes = kMaxSkipBricks / 8;
+static constexpr int kSkipWords = kMaxSkipBricks / 32;
+static constexpr int kSuperWords = 544;
+static constexpr int kSkipMaskBytes = (kSkipWords + kSuperWords) * 4;
 
 // Everything one view needs; computed on the host in binary64, rounded to
 // float-float.  Pixel (i,j) uses a = 2i+1-W, b = H-2j-1:

@@ -43,21 +43,25 @@ def test_oracle_and_product_share_no_symbols(rt, orc):
 def skip_bytes(dims):
     """Skip-brick value ranges appended to every layout: bricks of 2^e padded
     cells (0..n per axis), the smallest e >= 3 with at most 65536 bricks,
-    8 bytes each, rounded to 256."""
+    8 bytes each, rounded to 256; then the ranges of the super-bricks
+    (ceil(bricks / 4) per axis), 8 bytes each, rounded to 256."""
     e = 3
     while True:
-        nb = 1
-        for n in dims:
-            nb *= (n + 1 + (1 << e) - 1) >> e
+        per_axis = [(n + 1 + (1 << e) - 1) >> e for n in dims]
+        nb = per_axis[0] * per_axis[1] * per_axis[2]
         if nb <= 65536:
-            return (nb * 8 + 255) // 256 * 256
+            ns = 1
+            for b in per_axis:
+                ns *= (b + 3) // 4
+            return (nb * 8 + 255) // 256 * 256 + (ns * 8 + 255) // 256 * 256
         e += 1
 
 
 def test_skip_brick_counts():
-    assert skip_bytes((256, 256, 160)) == (33 * 33 * 21 * 8 + 255) // 256 * 256
-    assert skip_bytes((512, 512, 256)) == (33 * 33 * 17 * 8 + 255) // 256 * 256   # 16^3-cell bricks
-    assert skip_bytes((2, 2, 2)) == 256
+    r = lambda x: (x + 255) // 256 * 256
+    assert skip_bytes((256, 256, 160)) == r(33 * 33 * 21 * 8) + r(9 * 9 * 6 * 8)
+    assert skip_bytes((512, 512, 256)) == r(33 * 33 * 17 * 8) + r(9 * 9 * 5 * 8)   # 16^3-cell bricks
+    assert skip_bytes((2, 2, 2)) == 512
 
 
 def test_volume_bytes(rt):

@@ -133,16 +133,25 @@ def test_skip_ranges_bound_the_grid(rt, torch_mod):
     gv = rt.Volume(v, (1, 1, 1), storage=rt.U16)
     torch_mod.cuda.synchronize()
     nb = [(n + 1 + 7) // 8 for n in dims]
+    ns = [(b + 3) // 4 for b in nb]
+    r256 = lambda x: (x + 255) // 256 * 256
     total = gv.nbytes
-    skip_bytes = (nb[0] * nb[1] * nb[2] * 8 + 255) // 256 * 256
-    raw = gv.buf.cpu().numpy()[total - skip_bytes: total - skip_bytes + nb[0] * nb[1] * nb[2] * 8]
-    rng_ = raw.view(np.float32).reshape(nb[2], nb[1], nb[0], 2)
+    start = total - r256(ns[0] * ns[1] * ns[2] * 8) - r256(nb[0] * nb[1] * nb[2] * 8)
+    raw = gv.buf.cpu().numpy()[start: total]
+    rng_ = raw[: nb[0] * nb[1] * nb[2] * 8].view(np.float32).reshape(nb[2], nb[1], nb[0], 2)
+    sup = raw[r256(nb[0] * nb[1] * nb[2] * 8):][: ns[0] * ns[1] * ns[2] * 8].view(np.float32).reshape(
+        ns[2], ns[1], ns[0], 2)
     g = np.pad(v.astype(np.float64), 1, mode="edge")            # padded nodes 0..n+1
     for bz in range(nb[2]):
         for by in range(nb[1]):
             for bx in range(nb[0]):
                 blk = g[8 * bz: 8 * bz + 9, 8 * by: 8 * by + 9, 8 * bx: 8 * bx + 9]
                 assert rng_[bz, by, bx, 0] == blk.min() and rng_[bz, by, bx, 1] == blk.max()
+    for qz in range(ns[2]):
+        for qy in range(ns[1]):
+            for qx in range(ns[0]):
+                blk = g[32 * qz: 32 * qz + 33, 32 * qy: 32 * qy + 33, 32 * qx: 32 * qx + 33]
+                assert sup[qz, qy, qx, 0] == blk.min() and sup[qz, qy, qx, 1] == blk.max()
 
 
 def test_batches_and_plans_identical(rt, torch_mod, brain):
