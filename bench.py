@@ -51,6 +51,42 @@ def load_traffic(workload: str):
     return rec.get("bytes_per_launch")
 
 
+def _counter_per_dispatch(csv_path, kernel_prefix, counter):
+    """Median per-dispatch value of `counter` over the dispatches of the
+    kernels whose name starts with kernel_prefix (rocprofv3 counter CSV)."""
+    import csv
+    vals = [float(r["Counter_Value"]) for r in csv.DictReader(open(csv_path))
+            if r["Counter_Name"] == counter and r["Kernel_Name"].startswith(kernel_prefix)]
+    if not vals:
+        raise SystemExit(f"no {counter} records for {kernel_prefix} in {csv_path}")
+    vals.sort()
+    return vals[len(vals) // 2]
+
+
+def ingest_traffic(d, key, copy_bytes=1 << 30):
+    """FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of the marcher, each
+    scaled by what the counter reads for a plain copy of copy_bytes (the
+    --probe-copy kernel), recorded with the kernel source hash."""
+    import glob
+    one = lambda sub: glob.glob(os.path.join(d, sub, "*counter_collection.csv"))[0]
+    copy_k = "__amd_rocclr_copyBuffer"
+    march_k = "void rtv::(anonymous namespace)::march_batch_kernel<"
+    fetch_scale = copy_bytes / (_counter_per_dispatch(one("copy_fetch"), copy_k, "FETCH_SIZE") * 1024.0)
+    write_scale = copy_bytes / (_counter_per_dispatch(one("copy_write"), copy_k, "WRITE_SIZE") * 1024.0)
+    fetch = _counter_per_dispatch(one("fetch"), march_k, "FETCH_SIZE") * 1024.0 * fetch_scale
+    write = _counter_per_dispatch(one("write"), march_k, "WRITE_SIZE") * 1024.0 * write_scale
+    try:
+        data = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        data = {}
+    data[key] = {"kernel_hash": kernel_hash(), "bytes_per_launch": int(round(fetch + write)),
+                 "fetch_bytes": int(round(fetch)), "write_bytes": int(round(write)),
+                 "fetch_scale": fetch_scale, "write_scale": write_scale}
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    print(json.dumps({key: data[key]}))
+
+
 def percentile(xs, p):
     xs = sorted(xs)
     if not xs:
@@ -429,8 +465,16 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--probe-copy", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="orbit: keep the default 8x8 tiles, 16 waves")
-    ap.add_argument("--only", choices=["batch", "plain", "graph"], default=None,
-                    help="time one launch form only (for profiling)")
+    ap.add_argument("--only", choices=["batch", "plain", "graph", "skip"], default=None,
+                    help="time one launch form only (for profiling); skip = the graph form with empty-space "
+                         "skipping")
+    ap.add_argument("--shape", default=None, help="orbit: fixed launch shape TWxTHxWAVES (e.g. 4x16x16) "
+                                                  "instead of the autotuner's")
+    ap.add_argument("--ingest-traffic", default=None, metavar="DIR",
+                    help="read rocprofv3 FETCH_SIZE/WRITE_SIZE CSVs from DIR/{fetch,write,copy_fetch,copy_write} "
+                         "and record the orbit kernel's HBM bytes per launch in profiles/traffic.json")
+    ap.add_argument("--traffic-key", default="brain-orbit-36x512x512-u16:cells:graph",
+                    help="workload:layout:form the ingested counters belong to")
     ap.add_argument("--requests", type=int, default=4000, help="serve workload: number of requests")
     ap.add_argument("--workload", choices=["orbit", "precision", "batch", "serve", "projection"], default="orbit",
                     help="orbit: 36 views of the 256x256x160 u16 phantom at 512^2 (default); precision: "
@@ -455,6 +499,8 @@ def main():
     if args.probe_copy:
         probe_copy()
         return
+    if args.ingest_traffic:
+        return ingest_traffic(args.ingest_traffic, args.traffic_key)
     if args.workload == "precision":
         return bench_precision(args)
     if args.workload == "batch":
@@ -479,7 +525,10 @@ def main():
     outs = [torch.empty((height, width, 4), dtype=torch.float32, device="cuda") for _ in range(n_views)]
     jobs = [rt.Job(vol, tf, cam, width, height, step, cutoff, out=o) for cam, o in zip(cams, outs)]
     tuned = None
-    if not args.no_autotune:
+    if args.shape:
+        tw, th, wv = (int(x) for x in args.shape.split("x"))
+        shape = dict(tile=(tw, th), waves_per_block=wv)
+    elif not args.no_autotune:
         from paper_1211_5595_amd import autotune
         tuned = autotune.tune_launch(vol, tf, cams, width, height, step, cutoff, reps=3)
         shape = dict(tile=tuple(tuned["tile"]), waves_per_block=tuned["waves_per_block"])
@@ -514,7 +563,12 @@ def main():
         return e0.elapsed_time(e1) / steps
 
     forms = {"batch": step_batch, "graph": step_graph, "plain": step_plain}
-    if args.only:
+    if args.only == "skip":
+        plan_s = rt.BatchPlan(n_views, rt.U16, layout=layout, skip_empty=True, **shape)
+        jobs_s = [rt.Job(vol, tf, cam, width, height, step, cutoff, out=o, skip_empty=True)
+                  for cam, o in zip(cams, outs)]
+        forms = {"skip": lambda: plan_s.launch(jobs_s)}
+    elif args.only:
         forms = {args.only: forms[args.only]}
     ms = {k: timed(fn, args.steps, args.warmup) for k, fn in forms.items()}
     best = min(ms, key=ms.get)
@@ -544,12 +598,14 @@ def main():
     # roofline of the dominant kernel: algorithmic bytes = 8 trilinear corners
     # x 2 B per sample + 16 B per output pixel, per launch
     algo_bytes = samples_per_step * 16 + n_views * width * height * 16
-    launches_per_step = 1 if best in ("batch", "graph") else n_views
+    launches_per_step = 1 if best in ("batch", "graph", "skip") else n_views
     bytes_per_launch = algo_bytes / launches_per_step
     ms_per_launch = ms_step / launches_per_step
     achieved = bytes_per_launch / (ms_per_launch * 1e-3) / 1e9
     workload = "brain-orbit-36x512x512-u16"
     traffic = load_traffic(workload + ":" + args.layout + ":" + best)
+    if best == "skip":  # skipped samples are never gathered: no algorithmic-byte roofline for this form
+        achieved, traffic = None, None
 
     line = {
         "metric": "ray samples/sec (G/s) + fps at 512x512 over 256x256x160; p50/p99 render latency",
@@ -575,9 +631,10 @@ def main():
         "gsamples_per_s_by_form": {k: round(samples_per_step / (v * 1e-3) / 1e9, 3) for k, v in ms.items()},
         "latency_ms": {"single_view_p50": percentile(lat, 50), "single_view_p99": percentile(lat, 99),
                        "orbit_step": round(ms_step, 4)} if lat else None,
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+        "roofline": None if achieved is None else {
+                     "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
-                     "kernel": "march_batch_kernel<u16>" if best in ("batch", "graph") else "march_plain_kernel<u16>",
+                     "kernel": "march_batch_kernel<u16>" if best in ("batch", "graph", "skip") else "march_plain_kernel<u16>",
                      "algorithmic_bytes_per_launch": int(bytes_per_launch)},
     }
     # exact empty-space skipping over the same views: same images, same
