@@ -40,7 +40,12 @@
  *   R13 projections reduce every lattice sample (no early termination): the
  *       maximum, dt times the weighted sum, or the weighted mean of the
  *       values; the scalar is classified once and laid over the background
- *       with the table's opacity.
+ *       with the table's opacity;
+ *   R14 thresholding composites as R9 with the samples outside the value
+ *       window [iso_value, iso_high] transparent;
+ *   R15 the iso-surface is hit at the first sample reaching the iso-value,
+ *       refined linearly from the sample before, shaded by a headlight on
+ *       the central-difference normal (ambient 0.2, diffuse 0.8), opaque.
  */
 #include "oracle.h"
 
@@ -234,6 +239,41 @@ double orc_trilinear(const orc_volume* vol, const double q_in[3]) {
     return val;
 }
 
+/* Largest magnitude among the 8 corner values that orc_trilinear blends at
+ * q.  The binary32 interpolation on a device errs by a few units in the last
+ * place of this magnitude; decisions taken on an interpolated value (a value
+ * window, an iso-value) are flagged as rounding-decided within
+ * 2^-20 of it (R21, R22). */
+static double cell_corner_max(const orc_volume* vol, const double q_in[3]) {
+    int64_t c0[3];
+    for (int a = 0; a < 3; ++a) {
+        double hi = (double)(vol->dims[a] - 1);
+        double q = q_in[a] < 0.0 ? 0.0 : (q_in[a] > hi ? hi : q_in[a]);
+        c0[a] = clampi((int64_t)floor(q), 0, vol->dims[a] - 2);
+    }
+    double mx = 0.0;
+    int64_t nb[3] = {0, 0, 0};
+    if (!vol->field) orc_u8_brick_count(vol->dims, vol->brick, nb);
+    const int64_t B = vol->brick > 0 ? vol->brick : 1;
+    for (int dz = 0; dz < 2; ++dz)
+        for (int dy = 0; dy < 2; ++dy)
+            for (int dx = 0; dx < 2; ++dx) {
+                double v;
+                if (vol->field) {
+                    v = field_at(vol, c0[0] + dx, c0[1] + dy, c0[2] + dz);
+                } else {
+                    int64_t bx = c0[0] / B, by = c0[1] / B, bz = c0[2] / B;
+                    v = brick_node(vol, nb, bx, by, bz, c0[0] - bx * B + dx, c0[1] - by * B + dy, c0[2] - bz * B + dz);
+                }
+                if (fabs(v) > mx) mx = fabs(v);
+            }
+    return mx;
+}
+
+static double decision_slack(const orc_volume* vol, const double q[3]) {
+    return ldexp(cell_corner_max(vol, q), -20) + ldexp(1.0, -40);
+}
+
 /* Classification (Sections 2.6 and 6; post-classification, R6, R7): the value
  * is mapped to x = clamp((value-vmin)/(vmax-vmin), 0, 1) * (K-1) and the
  * colour and opacity are linearly interpolated between entries j0 and j0+1,
@@ -372,6 +412,109 @@ static void ray_project(const orc_volume* vol, const orc_tf* tf, const orc_param
     memcpy(res->hi, res->out, sizeof(res->out));
 }
 
+/* Iso-surface (Section 4.1 list; R22).  The surface is hit at the first
+ * lattice sample whose value reaches the iso-value; the hit point is refined
+ * by linear interpolation between that sample and the one before it (none
+ * when it is the first sample).  The normal is the direction of steepest
+ * descent of the trilinear field, from central differences over +-1/2 voxel
+ * per axis in index space scaled to millimetres; with a headlight the shade
+ * is c * (0.2 + 0.8 |n.d|), c the table colour at the iso-value, and the
+ * surface is opaque.  A miss shows the background. */
+static void iso_shade(const orc_volume* vol, const orc_tf* tf, const orc_params* prm, const ray_path* rp, double s_hit,
+                      const double dg[6], const double* pert, double out[4]) {
+    /* dg (nullable): perturbations of the 6 central-difference samples */
+    double p[3], q[3], g[3];
+    for (int a = 0; a < 3; ++a) p[a] = rp->o[a] + s_hit * rp->d[a];
+    double gg = 0.0, gd = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        double fp, fm;
+        for (int b = 0; b < 3; ++b) q[b] = p[b] / vol->spacing[b];
+        q[a] += 0.5;
+        fp = orc_trilinear(vol, q);
+        q[a] -= 1.0;
+        fm = orc_trilinear(vol, q);
+        if (dg) {
+            fp += pert[2 * a] * dg[2 * a];
+            fm += pert[2 * a + 1] * dg[2 * a + 1];
+        }
+        g[a] = (fp - fm) / vol->spacing[a];
+        gg += g[a] * g[a];
+        gd += g[a] * rp->d[a];
+    }
+    const double cosang = gg > 0.0 ? fabs(gd) / sqrt(gg) : 1.0;
+    double rgba[4];
+    orc_classify(tf, prm->iso_value, rgba);
+    const double shade = 0.2 + 0.8 * cosang;
+    for (int c = 0; c < 3; ++c) out[c] = rgba[c] * shade;
+    out[3] = 1.0;
+}
+
+static void ray_iso(const orc_volume* vol, const orc_tf* tf, const orc_params* prm, const ray_path* rp,
+                    ray_result* res) {
+    const int64_t n = rp->m + (rp->r > 0.0 ? 1 : 0);
+    double s_prev = 0.0, v_prev = 0.0, e_prev = 0.0;
+    for (int64_t k = 0; k < n; ++k) {
+        double s, weight, q[3];
+        sample_at(rp, k, &s, &weight);
+        const double val = value_at(vol, rp, s, q);
+        const double e = decision_slack(vol, q);
+        if (fabs(val - prm->iso_value) <= e) res->tie |= 8;
+        if (val >= prm->iso_value) {
+            double s_hit = s, lam = 1.0, dl = 0.0;
+            if (k > 0) {
+                lam = (prm->iso_value - v_prev) / (val - v_prev);
+                s_hit = s_prev + lam * (s - s_prev);
+                /* how far the refinement may move under the values' rounding */
+                dl = (e_prev * (1.0 - lam) + e * lam) / (val - v_prev);
+            }
+            res->count = k + 1;
+            iso_shade(vol, tf, prm, rp, s_hit, NULL, NULL, res->out);
+            /* band: the shade over the hit point moved by +-dl of a step and over
+             * each central-difference value moved by its own rounding slack */
+            double dg[6], pq[3];
+            double spread[4] = {0, 0, 0, 0};
+            for (int a = 0; a < 3; ++a) {
+                for (int b = 0; b < 3; ++b) pq[b] = (rp->o[b] + s_hit * rp->d[b]) / vol->spacing[b];
+                pq[a] += 0.5;
+                dg[2 * a] = decision_slack(vol, pq);
+                pq[a] -= 1.0;
+                dg[2 * a + 1] = decision_slack(vol, pq);
+            }
+            for (int j = 0; j < 8; ++j) {
+                double worst[4] = {0, 0, 0, 0};
+                for (int sg = -1; sg <= 1; sg += 2) {
+                    double o2[4];
+                    if (j < 6) {
+                        double pert[6] = {0, 0, 0, 0, 0, 0};
+                        pert[j] = (double)sg;
+                        iso_shade(vol, tf, prm, rp, s_hit, dg, pert, o2);
+                    } else if (k > 0) {
+                        const double s2 = s_prev + (lam + sg * dl) * (s - s_prev);
+                        iso_shade(vol, tf, prm, rp, s2, NULL, NULL, o2);
+                    } else {
+                        continue;
+                    }
+                    for (int c = 0; c < 4; ++c)
+                        if (fabs(o2[c] - res->out[c]) > worst[c]) worst[c] = fabs(o2[c] - res->out[c]);
+                }
+                for (int c = 0; c < 4; ++c) spread[c] += worst[c];
+            }
+            for (int c = 0; c < 4; ++c) {
+                res->lo[c] = res->out[c] - spread[c];
+                res->hi[c] = res->out[c] + spread[c];
+            }
+            return;
+        }
+        s_prev = s;
+        v_prev = val;
+        e_prev = e;
+    }
+    bg_out(prm, res->out);
+    res->count = n;
+    memcpy(res->lo, res->out, sizeof(res->out));
+    memcpy(res->hi, res->out, sizeof(res->out));
+}
+
 static void ray_composite(const orc_volume* vol, const orc_tf* tf, const orc_params* prm, const ray_path* rp,
                           ray_result* res) {
     double C[3] = {0.0, 0.0, 0.0}, T = 1.0;
@@ -379,12 +522,19 @@ static void ray_composite(const orc_volume* vol, const orc_tf* tf, const orc_par
     const double lo_thr = prm->cutoff - prm->tie_delta, hi_thr = prm->cutoff + prm->tie_delta;
     int stopped = 0, in_band = 0;
     double state[4];
+    const int window = prm->ray_function == ORC_THRESHOLD;
     for (int64_t k = 0; k < n; ++k) {
         double s, weight, q[3], rgba[4];
         sample_at(rp, k, &s, &weight);
         double val = value_at(vol, rp, s, q);
         orc_classify(tf, val, rgba);
         double alpha = rgba[3];
+        if (window) {
+            /* thresholding (R21): samples outside [iso_value, iso_high] are transparent */
+            const double e = decision_slack(vol, q);
+            if (alpha > 0.0 && (fabs(val - prm->iso_value) <= e || fabs(val - prm->iso_high) <= e)) res->tie |= 8;
+            if (val < prm->iso_value || val > prm->iso_high) alpha = 0.0;
+        }
         if (k == rp->m) alpha = 1.0 - pow(1.0 - alpha, weight);
         for (int c = 0; c < 3; ++c) C[c] += T * alpha * rgba[c];
         T *= (1.0 - alpha);
@@ -438,6 +588,13 @@ static int march_pixel(const orc_volume* vol, const orc_tf* tf, const orc_camera
         case ORC_XRAY:
         case ORC_AVERAGE:
             ray_project(vol, tf, prm, &rp, res);
+            break;
+        case ORC_THRESHOLD:
+            if (!(prm->iso_value <= prm->iso_high)) return ORC_EINVAL;
+            ray_composite(vol, tf, prm, &rp, res);
+            break;
+        case ORC_ISO:
+            ray_iso(vol, tf, prm, &rp, res);
             break;
         default:
             return ORC_EINVAL;

@@ -49,6 +49,14 @@ extern "C" {
  * background: out.rgb = a c + (1-a) bg.rgb, out.a = a + (1-a) bg.a. */
 #define ORC_ISO 4         /* first crossing of an iso-value, shaded */
 #define ORC_THRESHOLD 5   /* compositing restricted to a value window */
+/* Thresholding composites like ORC_COMPOSITE with the samples whose value lies
+ * outside [iso_value, iso_high] transparent.  The iso-surface is hit at the
+ * first sample whose value reaches iso_value, refined linearly from the
+ * previous sample; out.rgb = c * (0.2 + 0.8 |n.d|) with c the table colour at
+ * iso_value, n the central-difference normal (+-1/2 voxel), d the ray
+ * direction; out.a = 1; a miss gives the background.  Tie bit 3 marks a pixel
+ * where a window or iso decision lies within 2^-20 of the interpolated
+ * cell's largest corner magnitude (decided by rounding). */
 
 typedef struct {
     double eye[3], center[3], up[3];
@@ -109,7 +117,9 @@ void orc_classify(const orc_tf* tf, double value, double rgba[4]);
  * output over the early-termination tie band.  tie (nullable): bit 0 = the
  * pixel lies in an early-termination tie band, bit 1 = its last segment is
  * within 1e-6 of empty or full (sample count may differ by one), bit 2 = the
- * ray grazes the box (hit/miss decided by rounding).
+ * ray grazes the box (hit/miss decided by rounding), bit 3 = a value-window or
+ * iso-value decision is decided by rounding.  For the iso-surface the band
+ * spans the shade over the rounding of the hit refinement and the normal.
  * nthreads <= 0 uses all OpenMP threads. */
 int orc_render(const orc_volume* vol, const orc_tf* tf, const orc_camera* cam,
                const orc_params* prm, const int64_t* pixels, int64_t n,
