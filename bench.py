@@ -265,11 +265,12 @@ def bench_precision(args):
 
 
 def bench_projection(args):
-    """Maximum-intensity, X-ray and average-intensity projection of the
-    256x256x160 u16 phantom over the 36 orbit views at 512x512, step 0.5, one
-    graph-captured persistent launch per step; compositing of the same views
-    beside them.  Projections visit every lattice sample (no early
-    termination)."""
+    """Every ray function over the 36 orbit views of the 256x256x160 u16
+    phantom at 512x512, step 0.5, one graph-captured persistent launch per
+    step: compositing, maximum-intensity, X-ray and average-intensity
+    projection (every lattice sample, no early termination), thresholding to
+    the window [1200, 2600] (with and without empty-space skipping) and the
+    iso-surface at 1000 (samples up to the first hit)."""
     import torch
 
     import paper_1211_5595_amd as rt
@@ -285,22 +286,30 @@ def bench_projection(args):
     tf_np = W.random_tf(ts.K, ts.seed, alpha_max=ts.alpha_max)
     results = {}
     plan = rt.BatchPlan(n_views, rt.U16)
-    for name, fn, top in [("composite", rt.COMPOSITE, ts.vmax), ("mip", rt.MIP, ts.vmax),
-                          ("xray", rt.XRAY, ts.vmax * 150.0), ("average", rt.AVERAGE, ts.vmax)]:
+    plan_s = rt.BatchPlan(n_views, rt.U16, skip_empty=True)
+    for name, fn, top, lo, hi, skip in [("composite", rt.COMPOSITE, ts.vmax, 0.0, 0.0, False),
+                                        ("mip", rt.MIP, ts.vmax, 0.0, 0.0, False),
+                                        ("xray", rt.XRAY, ts.vmax * 150.0, 0.0, 0.0, False),
+                                        ("average", rt.AVERAGE, ts.vmax, 0.0, 0.0, False),
+                                        ("threshold", rt.THRESHOLD, ts.vmax, 1200.0, 2600.0, False),
+                                        ("threshold_skip", rt.THRESHOLD, ts.vmax, 1200.0, 2600.0, True),
+                                        ("iso", rt.ISO, ts.vmax, 1000.0, 0.0, False)]:
         tf = rt.TransferFunction(tf_np, ts.vmin, top)
         outs = [torch.empty((height, width, 4), dtype=torch.float32, device="cuda") for _ in range(n_views)]
-        jobs = [rt.Job(vol, tf, cam, width, height, step, cfg["cutoff"], out=o, ray_function=fn)
-                for cam, o in zip(cams, outs)]
+        jobs = [rt.Job(vol, tf, cam, width, height, step, cfg["cutoff"], out=o, ray_function=fn, iso_value=lo,
+                       iso_high=hi, skip_empty=skip) for cam, o in zip(cams, outs)]
         samples = _count(rt, jobs)
-        ms = _timed(lambda: plan.launch(jobs), args.steps, args.warmup)
+        pl = plan_s if skip else plan
+        ms = _timed(lambda: pl.launch(jobs), args.steps, args.warmup)
         results[name] = {"gsamples_per_s": round(samples / (ms * 1e-3) / 1e9, 3),
                          "fps": round(n_views / (ms * 1e-3), 1), "ms_per_launch": round(ms, 4),
                          "samples_per_launch": samples,
-                         "algorithmic_GB_per_s": round((samples * 16 + n_views * width * height * 16)
-                                                       / (ms * 1e-3) / 1e9, 1)}
+                         # skipped samples are counted but never gathered: no byte rate for them
+                         "algorithmic_GB_per_s": None if skip else
+                         round((samples * 16 + n_views * width * height * 16) / (ms * 1e-3) / 1e9, 1)}
     line = _contract("ray samples/sec (G/s) + fps per ray function at 512x512 over 256x256x160",
                      results["mip"]["gsamples_per_s"], "Gsamples/s", args, results["mip"]["ms_per_launch"], "u16",
-                     {"workload": "brain-projection-36x512x512-u16", "volume": list(vs.dims), "views": n_views,
+                     {"workload": "brain-ray-functions-36x512x512-u16", "volume": list(vs.dims), "views": n_views,
                       "image": [width, height], "step_vox": step, "tf_entries": ts.K,
                       "ray_functions": list(results), "launch": "graph"},
                      by_ray_function=results)
@@ -480,7 +489,8 @@ def main():
                     help="orbit: 36 views of the 256x256x160 u16 phantom at 512^2 (default); precision: "
                          "the same phantom as u16/f16/8-bit bricks at 1024^2, step 0.25; batch: 32 uneven "
                          "volumes x 4 views in one launch vs 128 launches; serve: Poisson request stream; "
-                         "projection: the orbit under maximum-intensity, X-ray and average projection")
+                         "projection: the orbit under every ray function (projections, thresholding, "
+                         "iso-surface)")
     ap.add_argument("--layout", choices=["cells", "poly", "linear"], default="cells",
                     help="device layout of the orbit volume")
     args = ap.parse_args()

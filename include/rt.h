@@ -97,9 +97,21 @@ typedef enum {
     RT_MIP = 1,        /* maximum interpolated value along the ray */
     RT_XRAY = 2,       /* dt times the weighted sum of the values (the chord's line integral) */
     RT_AVERAGE = 3,    /* weighted mean of the values */
-    RT_ISO = 4,        /* first crossing of an iso-value, shaded */
-    RT_THRESHOLD = 5   /* compositing of the samples inside a value window */
+    RT_ISO = 4,        /* first crossing of an iso-value, shaded (below) */
+    RT_THRESHOLD = 5   /* compositing of the samples inside a value window (below) */
 } rt_ray_function;
+/* RT_THRESHOLD composites as RT_COMPOSITE with every sample whose
+ * interpolated value lies outside [iso_value, iso_high] transparent (it still
+ * counts as a processed sample); needs finite iso_value <= iso_high.
+ * RT_ISO: the first lattice sample whose value reaches iso_value is the hit;
+ * the hit point is refined by linear interpolation from the sample before it
+ * (unless it is the ray's first sample); the normal n is the descent direction
+ * of the trilinear field from central differences over +-1/2 cell per axis
+ * (scaled by the spacing); the pixel is opaque, rgb = c * (0.2 + 0.8 |n.d|)
+ * with c the table colour at iso_value and d the ray direction (a headlight),
+ * alpha = 1; a ray that never reaches iso_value shows the background.  The
+ * sample count of a hit is the hit sample's index + 1.  Empty-space skipping
+ * applies to compositing and thresholding only. */
 
 /* Look-at camera (Section 6: camera settings).  w = normalize(center-eye),
  * u = normalize(w x up), v = u x w.  Invalid when eye == center or up is
@@ -208,7 +220,8 @@ rt_status rt_destroy_tf(rt_tf* tf);
  * alpha_cutoff in (0, 1] (1 = stop only at full opacity).  bg_rgba may be
  * NULL (transparent black).  One kernel launch on `stream`.
  * Errors: RT_ERR_INVALID_ARG (NULL, size/camera/step/cutoff out of range,
- * dims mismatch), RT_ERR_UNSUPPORTED (ray function or tile shape not built),
+ * dims mismatch, unknown ray function, invalid threshold window or
+ * iso-value), RT_ERR_UNSUPPORTED (tile shape not built),
  * RT_ERR_DEVICE (launch failure). */
 rt_status rt_render(const rt_volume* volume, const int64_t dims[3], const double spacing[3], const rt_tf* tf,
                     const rt_camera* camera, int width, int height, double step_vox, double alpha_cutoff,

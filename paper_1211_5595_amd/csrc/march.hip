@@ -520,7 +520,9 @@ __device__ __forceinline__ int leap(const uint32_t* s_mask, const VOL& vol, long
     return (int)n;
 }
 
-template <int KIND, int LAYOUT, bool SKIP, class VD>
+// WINDOW: thresholding -- samples whose value lies outside [iso_lo, iso_hi]
+// are transparent (their opacity is taken as 0).
+template <int KIND, int LAYOUT, bool SKIP, bool WINDOW, class VD>
 __device__ __forceinline__ void march_pixel(const VD& V, const float4* __restrict__ s_tf,
                                             const uint32_t* __restrict__ s_mask, __amdgpu_buffer_rsrc_t rs,
                                             const Corners& cn, int i, int j, float4& px, int& count) {
@@ -558,7 +560,8 @@ __device__ __forceinline__ void march_pixel(const VD& V, const float4* __restric
                 const long long Qn[3] = {R.Q[0] + R.dQ[0], R.Q[1] + R.dQ[1], R.Q[2] + R.dQ[2]};
                 const typename S::Raw nxt = S::load(rs, V.vol, cn, Qn);
                 const float val = S::value(cur, frac32(R.Q[0]), frac32(R.Q[1]), frac32(R.Q[2]));
-                const float4 c = classify(s_tf, val, ta, tb, Km1);
+                float4 c = classify(s_tf, val, ta, tb, Km1);
+                if (WINDOW && !(val >= V.iso_lo && val <= V.iso_hi)) c.w = 0.0f;
                 const float Ta = T * c.w;
                 Cr = fmaf(Ta, c.x, Cr);
                 Cg = fmaf(Ta, c.y, Cg);
@@ -575,7 +578,8 @@ __device__ __forceinline__ void march_pixel(const VD& V, const float4* __restric
         if (R.wp > 0.0f && T > thr) {
             const typename S::Raw w = S::load(rs, V.vol, cn, R.Qp);
             const float val = S::value(w, frac32(R.Qp[0]), frac32(R.Qp[1]), frac32(R.Qp[2]));
-            const float4 c = classify(s_tf, val, ta, tb, Km1);
+            float4 c = classify(s_tf, val, ta, tb, Km1);
+            if (WINDOW && !(val >= V.iso_lo && val <= V.iso_hi)) c.w = 0.0f;
             const float a = 1.0f - exp2f(R.wp * log2f(1.0f - c.w));
             const float Ta = T * a;
             Cr = fmaf(Ta, c.x, Cr);
@@ -663,6 +667,107 @@ __device__ __forceinline__ void project_pixel(const VD& V, const float4* __restr
                      fmaf(ia, V.bg[3], c.w));
 }
 
+// Step 3 for the iso-surface: the first lattice sample whose value reaches
+// the iso-value is the hit; the hit point is refined linearly from the sample
+// before (unless it is the first); the surface normal is the descent
+// direction of the trilinear field from central differences over +-1/2 cell
+// per axis, and the opaque surface is shaded by a headlight,
+// c * (0.2 + 0.8 |n.d|), c the table colour at the iso-value.
+template <int KIND, int LAYOUT, class VD>
+__device__ __forceinline__ void iso_pixel(const VD& V, const float4* __restrict__ s_tf, __amdgpu_buffer_rsrc_t rs,
+                                          const Corners& cn, int i, int j, float4& px, int& count) {
+    using S = Sampler<KIND, LAYOUT>;
+    Ray R;
+    px = make_float4(V.bg[0], V.bg[1], V.bg[2], V.bg[3]);
+    count = 0;
+    if (!setup_ray(V, i, j, R)) return;
+    const float iso = V.iso_lo;
+    bool hit = false, refine = false;
+    float v_prev = 0.0f, v_hit = 0.0f;
+    int k = 0;
+    long long P1[3] = {R.Q[0], R.Q[1], R.Q[2]};  // hit sample
+    long long P0[3] = {0, 0, 0};                 // the sample before it
+    if (R.m > 0) {
+        typename S::Raw cur = S::load(rs, V.vol, cn, R.Q);
+        for (;;) {
+            const long long Qn[3] = {R.Q[0] + R.dQ[0], R.Q[1] + R.dQ[1], R.Q[2] + R.dQ[2]};
+            const typename S::Raw nxt = S::load(rs, V.vol, cn, Qn);
+            const float val = S::value(cur, frac32(R.Q[0]), frac32(R.Q[1]), frac32(R.Q[2]));
+            if (val >= iso) {
+                hit = true;
+                v_hit = val;
+                break;
+            }
+            v_prev = val;
+            if (++k >= R.m) break;
+            cur = nxt;
+            R.Q[0] = Qn[0];
+            R.Q[1] = Qn[1];
+            R.Q[2] = Qn[2];
+        }
+        // hit: sample k at R.Q; otherwise k == m and R.Q is the last full sample
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            P1[a] = R.Q[a];
+            P0[a] = R.Q[a] - R.dQ[a];
+        }
+        refine = hit && k > 0;
+    }
+    if (!hit && R.wp > 0.0f) {
+        const typename S::Raw w = S::load(rs, V.vol, cn, R.Qp);
+        const float val = S::value(w, frac32(R.Qp[0]), frac32(R.Qp[1]), frac32(R.Qp[2]));
+        if (val >= iso) {
+            hit = true;
+            v_hit = val;
+            refine = R.m > 0;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                P0[a] = R.Q[a];
+                P1[a] = R.Qp[a];
+            }
+        }
+        k = R.m;
+    }
+    if (!hit) {
+        count = R.m + (R.wp > 0.0f ? 1 : 0);
+        return;
+    }
+    count = k + 1;
+    long long P[3] = {P1[0], P1[1], P1[2]};
+    if (refine) {
+        const float lam = (iso - v_prev) / (v_hit - v_prev);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const long long D = P1[a] - P0[a];
+            P[a] = P0[a] + (long long)rintf(lam * (float)D);
+        }
+    }
+    // central differences over +-1/2 cell (2^31 in 32.32 fixed point) per axis
+    float df[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        long long Pp[3] = {P[0], P[1], P[2]}, Pm[3] = {P[0], P[1], P[2]};
+        Pp[a] += 0x80000000LL;
+        Pm[a] -= 0x80000000LL;
+        const float fp = S::value(S::load(rs, V.vol, cn, Pp), frac32(Pp[0]), frac32(Pp[1]), frac32(Pp[2]));
+        const float fm = S::value(S::load(rs, V.vol, cn, Pm), frac32(Pm[0]), frac32(Pm[1]), frac32(Pm[2]));
+        df[a] = fp - fm;
+    }
+    // n.d with g_a = df_a / s_a and d_a proportional to dQ_a * s_a: the spacing cancels in g.d
+    float gd = 0.0f, gg = 0.0f, dd = 0.0f;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float isp = V.inv_sp[a].hi, dq = (float)R.dQ[a];
+        gd = fmaf(df[a], dq, gd);
+        gg = fmaf(df[a] * isp, df[a] * isp, gg);
+        dd = fmaf(dq / isp, dq / isp, dd);
+    }
+    const float cosang = gg > 0.0f ? fabsf(gd) * __frsqrt_rn(gg) * __frsqrt_rn(dd) : 1.0f;
+    const float4 c = classify(s_tf, iso, V.tf_a, V.tf_b, (float)(V.K - 1));
+    const float shade = fmaf(0.8f, cosang, 0.2f);
+    px = make_float4(c.x * shade, c.y * shade, c.z * shade, 1.0f);
+}
+
 template <int KIND, int LAYOUT, bool SKIP, class VD>
 __device__ __forceinline__ void render_block(const VD& V, const float4* __restrict__ s_tf,
                                              const uint32_t* __restrict__ s_mask, int blk, const LaunchShape& ls,
@@ -679,7 +784,11 @@ __device__ __forceinline__ void render_block(const VD& V, const float4* __restri
         float4 px;
         const int fn = V.ray_function;  // uniform over the view
         if (fn == RT_FN_COMPOSITE)
-            march_pixel<KIND, LAYOUT, SKIP, VD>(V, s_tf, s_mask, rs, cn, i, j, px, count);
+            march_pixel<KIND, LAYOUT, SKIP, false, VD>(V, s_tf, s_mask, rs, cn, i, j, px, count);
+        else if (fn == RT_FN_THRESHOLD)
+            march_pixel<KIND, LAYOUT, SKIP, true, VD>(V, s_tf, s_mask, rs, cn, i, j, px, count);
+        else if (fn == RT_FN_ISO)
+            iso_pixel<KIND, LAYOUT, VD>(V, s_tf, rs, cn, i, j, px, count);
         else if (fn == RT_FN_MIP)
             project_pixel<KIND, LAYOUT, RF_MAX, VD>(V, s_tf, rs, cn, i, j, px, count);
         else

@@ -251,8 +251,8 @@ rt_status make_shape(const rt_render_opts* opts, LaunchShape& ls) {
 
 rt_status make_view(const rt_volume* vol, const int64_t dims[3], const double spacing[3], const rt_tf* tf,
                     const rt_camera* cam, int W, int H, double step_vox, double cutoff, const float* bg,
-                    float* out, int32_t* counts, const LaunchShape& ls, int ray_function, int skip_empty,
-                    ViewDesc& v) {
+                    float* out, int32_t* counts, const LaunchShape& ls, int ray_function, float iso_value,
+                    float iso_high, int skip_empty, ViewDesc& v) {
     if (!vol || !tf || !cam || !out) return fail(RT_ERR_INVALID_ARG, "NULL volume, transfer function, camera or output");
     if (dims)
         for (int a = 0; a < 3; ++a)
@@ -268,7 +268,10 @@ rt_status make_view(const rt_volume* vol, const int64_t dims[3], const double sp
     if (((uintptr_t)out & 15) != 0) return fail(RT_ERR_INVALID_ARG, "output must be 16-byte aligned");
     if (ray_function < RT_COMPOSITE || ray_function > RT_THRESHOLD)
         return fail(RT_ERR_INVALID_ARG, "unknown ray function");
-    if (ray_function > RT_AVERAGE) return fail(RT_ERR_UNSUPPORTED, "ray function not built");
+    if (ray_function == RT_ISO && !std::isfinite(iso_value)) return fail(RT_ERR_INVALID_ARG, "iso-value must be finite");
+    if (ray_function == RT_THRESHOLD &&
+        !(std::isfinite(iso_value) && std::isfinite(iso_high) && iso_value <= iso_high))
+        return fail(RT_ERR_INVALID_ARG, "threshold window must be finite with iso_value <= iso_high");
     if (!finite3(cam->eye) || !finite3(cam->center) || !finite3(cam->up))
         return fail(RT_ERR_INVALID_ARG, "camera vectors must be finite");
     double f[3] = {cam->center[0] - cam->eye[0], cam->center[1] - cam->eye[1], cam->center[2] - cam->eye[2]};
@@ -317,10 +320,12 @@ rt_status make_view(const rt_volume* vol, const int64_t dims[3], const double sp
     v.blocks_x = (v.tiles_x + ls.bw - 1) / ls.bw;
     v.nblocks = v.blocks_x * ((v.tiles_y + ls.bh - 1) / ls.bh);
     v.ray_function = ray_function;
+    v.iso_lo = iso_value;
+    v.iso_hi = iso_high;
     v.vol = vol->dev;
     v.tf = tf->dev;
     v.tf_nz = reinterpret_cast<const int32_t*>(reinterpret_cast<const char*>(tf->dev) + tf_nz_offset(tf->K));
-    v.skip_empty = (skip_empty && ray_function == RT_COMPOSITE) ? 1 : 0;
+    v.skip_empty = (skip_empty && (ray_function == RT_COMPOSITE || ray_function == RT_THRESHOLD)) ? 1 : 0;
     v.K = tf->K;
     const double ta = (double)(tf->K - 1) / (tf->vmax - tf->vmin);
     v.tf_a = (float)ta;
@@ -380,7 +385,7 @@ rt_status build_batch(const rt_render_job* jobs, int n, const LaunchShape& ls, i
         if (!J.volume) return fail(RT_ERR_INVALID_ARG, "job without volume");
         rt_status st = make_view(J.volume, nullptr, nullptr, J.tf, &J.camera, J.width, J.height, J.step_vox,
                                  J.alpha_cutoff, J.bg_rgba, J.out_dev, J.pixel_counts, ls, J.ray_function,
-                                 J.skip_empty, descs[i]);
+                                 J.iso_value, J.iso_high, J.skip_empty, descs[i]);
         if (st != RT_OK) return fail(st, "job " + std::to_string(i) + ": " + g_last_error);
         const int k = J.volume->dev.kind * 4 + J.volume->dev.layout;  // storage type and layout
         if (*kind < 0) *kind = k;
@@ -605,7 +610,7 @@ rt_status rt_render(const rt_volume* volume, const int64_t dims[3], const double
     ViewDesc v;
     st = make_view(volume, dims, spacing, tf, camera, width, height, step_vox, alpha_cutoff, bg_rgba, out_dev,
                    opts ? opts->pixel_counts : nullptr, ls, opts ? opts->ray_function : 0,
-                   opts ? opts->skip_empty : 0, v);
+                   opts ? opts->iso_value : 0.0f, opts ? opts->iso_high : 0.0f, opts ? opts->skip_empty : 0, v);
     if (st != RT_OK) return st;
     hipError_t e = launch_march_plain(v, ls, opts ? opts->sample_counter : nullptr, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "render launch");

@@ -15,7 +15,8 @@ struct ff {
 
 enum StorageKind : int { ST_U8 = 0, ST_U16 = 1, ST_F16 = 2, ST_F32 = 3, ST_U8B = 4 };
 // Ray functions as stored in a view descriptor (values of rt_ray_function).
-enum RayFn : int { RT_FN_COMPOSITE = 0, RT_FN_MIP = 1, RT_FN_XRAY = 2, RT_FN_AVERAGE = 3 };
+enum RayFn : int { RT_FN_COMPOSITE = 0, RT_FN_MIP = 1, RT_FN_XRAY = 2, RT_FN_AVERAGE = 3, RT_FN_ISO = 4,
+                   RT_FN_THRESHOLD = 5 };
 
 enum LayoutKind : int { LAYOUT_CELLS = 0, LAYOUT_LINEAR = 1, LAYOUT_BRICKS = 2, LAYOUT_POLY = 3 };
 
@@ -91,7 +92,7 @@ struct ViewDesc {
     int32_t blocks_x;           // workgroup blocks per block-row
     int32_t nblocks;            // workgroup blocks of this view
     int32_t ray_function;
-    float iso_lo, iso_hi;
+    float iso_lo, iso_hi;       // RT_ISO: iso-value in iso_lo; RT_THRESHOLD: value window [iso_lo, iso_hi]
     VolDev vol;
     const float4* tf;           // K entries
     const int32_t* tf_nz;       // K+2 entries: nz[j] = number of table entries i < j (entry K = entry K-1) with alpha > 0
