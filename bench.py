@@ -342,6 +342,12 @@ def bench_batch(args):
     plain = _plain_caller(rt, jobs)
     ms_graph = _timed(lambda: plan.launch(jobs), args.steps, args.warmup)
     ms_plain = _timed(plain, args.steps, args.warmup)
+    # the same batch with exact empty-space skipping (same images, fewer samples gathered)
+    plan_s = rt.BatchPlan(len(jobs), rt.U16, skip_empty=True)
+    jobs_s = [rt.Job(vols[vi], tfs[vi], cam, side, side, 0.5, 0.99, skip_empty=True) for vi, cam, side in views]
+    ms_skip = _timed(lambda: plan_s.launch(jobs_s), args.steps, args.warmup)
+    torch.cuda.synchronize()
+    same = all(torch.equal(a.out, b.out) for a, b in zip(jobs, jobs_s))
     pixels = sum(j.width * j.height for j in jobs)
     algo = samples * 16 + pixels * 16
     g = samples / (ms_graph * 1e-3) / 1e9
@@ -352,7 +358,9 @@ def bench_batch(args):
                                                                               max(j.width for j in jobs)],
                       "step_vox": 0.5, "alpha_cutoff": 0.99, "tf_entries": 4096, "launch": "graph"},
                      samples_per_step=samples, pixels_per_step=pixels,
-                     ms_per_step_by_form={"graph": round(ms_graph, 4), "plain_128_launches": round(ms_plain, 4)},
+                     ms_per_step_by_form={"graph": round(ms_graph, 4), "plain_128_launches": round(ms_plain, 4),
+                                          "graph_skip_empty": round(ms_skip, 4)},
+                     skip_empty_images_bitwise_equal=bool(same),
                      gsamples_per_s_by_form={"graph": round(g, 3),
                                              "plain_128_launches": round(samples / (ms_plain * 1e-3) / 1e9, 3)},
                      speedup_vs_plain=round(ms_plain / ms_graph, 3),
@@ -378,7 +386,7 @@ def bench_serve(args):
     torch.cuda.set_device(0)
     sp = (0.9, 0.9, 1.2)
     dims = [d for d in W.BATCH_SIZES for _ in range(4)]
-    ex = GpuExecutor(n_streams=3, max_batch=64)
+    ex = GpuExecutor(n_streams=3, max_batch=64)          # exact empty-space skipping on
     for i, d in enumerate(dims):
         ex.add_volume(i, W.phantom_brain(200 + i, dims=d, spacing=sp), sp)
         print(f"volume {i} {d} resident", file=sys.stderr, flush=True)
@@ -436,7 +444,8 @@ def bench_serve(args):
             tfs.update(r.tf_rgba)
             if k == warm and speed == 1.0:
                 counter.zero_()
-            rt.render(ex.volumes[r.volume_id], tfs, r.camera, r.width, r.height, 0.5, 0.99, sample_counter=counter)
+            rt.render(ex.volumes[r.volume_id], tfs, r.camera, r.width, r.height, 0.5, 0.99, sample_counter=counter,
+                      skip_empty=True)
             torch.cuda.synchronize()
             t = time.perf_counter()
             lat.append(t - target)
@@ -458,7 +467,8 @@ def bench_serve(args):
                      "batching", loose["p99_ms"], "ms", args, loose["mean_ms"], "u16",
                      {"workload": "serve-poisson200-16vol-u16", "volumes": len(dims), "sizes": W.BATCH_SIZES,
                       "requests": n_req, "warmup_requests": warm, "image_sides": [256, 1024], "streams": 3,
-                      "max_batch": 64, "step_vox": 0.5, "alpha_cutoff": 0.99, "tf_entries": 4096},
+                      "max_batch": 64, "step_vox": 0.5, "alpha_cutoff": 0.99, "tf_entries": 4096,
+                      "skip_empty": True},
                      resident_bytes=resident, served_loose_budget=loose, served_tight_budget=tight,
                      serial_plain=ser, saturation=sat)
     line["higher_is_better"] = False

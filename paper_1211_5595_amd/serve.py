@@ -247,9 +247,12 @@ class Server:
 
 class GpuExecutor:
     """Runs batches through the C ABI: resident volumes, one batch plan
-    (captured persistent launch) and one table pool per stream."""
+    (captured persistent launch) and one table pool per stream.  Compositing
+    requests use exact empty-space skipping unless skip_empty is False (the
+    images are the same either way)."""
 
-    def __init__(self, n_streams: int = 3, max_batch: int = 64, storage: Optional[int] = None, device="cuda"):
+    def __init__(self, n_streams: int = 3, max_batch: int = 64, storage: Optional[int] = None, device="cuda",
+                 skip_empty: bool = True):
         import torch
 
         from . import BatchPlan, Job, TransferFunction, U16, LAYOUT_CELLS
@@ -260,7 +263,8 @@ class GpuExecutor:
         self.volumes: Dict[Any, Any] = {}
         self._resident = 0
         self.streams = [torch.cuda.Stream(device=device) for _ in range(n_streams)]
-        self.plans = [BatchPlan(max_batch, self.storage, layout=LAYOUT_CELLS, device=device)
+        self.skip_empty = bool(skip_empty)
+        self.plans = [BatchPlan(max_batch, self.storage, layout=LAYOUT_CELLS, device=device, skip_empty=self.skip_empty)
                       for _ in range(n_streams)]
         self.counters = [torch.zeros(1, dtype=torch.int64, device=device) for _ in range(n_streams)]
         self.tf_pools: List[Dict[int, List[Any]]] = [collections.defaultdict(list) for _ in range(n_streams)]
@@ -311,7 +315,7 @@ class GpuExecutor:
                     lst.append(tf)
                 out = torch.empty((r.height, r.width, 4), dtype=torch.float32, device=self.device)
                 jobs.append(self._Job(self.volumes[r.volume_id], tf, r.camera, r.width, r.height, r.step_vox,
-                                      r.alpha_cutoff, r.bg, out=out))
+                                      r.alpha_cutoff, r.bg, out=out, skip_empty=self.skip_empty))
             self.counters[k].zero_()
             self.plans[k].launch(jobs, sample_counter=self.counters[k], stream=s)
             ev = torch.cuda.Event()
