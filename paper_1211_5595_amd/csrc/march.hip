@@ -7,8 +7,13 @@
 //   2. values along the ray: trilinear resampling of the stored grid
 //      (Section 3.2) and classification by the RGBA transfer function
 //      (Sections 2.6 and 6) held in LDS;
-//   3. ray function: front-to-back compositing of the emission-absorption
-//      sum (Section 4.2, eqs. (4)-(5)) with early ray termination.
+//   3. ray function (the Section 4.1 list): front-to-back compositing of the
+//      emission-absorption sum (Section 4.2, eqs. (4)-(5)) with early ray
+//      termination; thresholding (compositing of a value window); maximum-,
+//      X-ray and average-intensity projection (Section 2.4); iso-surface.
+// Compositing can step over empty space: bricks whose samples all have zero
+// opacity for the table are skipped a whole brick at a time, which leaves
+// the result unchanged bit for bit.
 //
 // Precision: the ray set-up (direction, box entry/exit, sample lattice) runs
 // in float-float; sample positions then advance as exact 32.32 fixed-point
@@ -17,8 +22,9 @@
 // compositing run in binary32.  No binary64 on the device.
 //
 // Memory: the volume is read through buffer resources (out-of-range reads
-// return zero, never fault); the 8 corners of a cell are one vector offset
-// plus 8 wave-uniform scalar offsets.
+// return zero, never fault).  In the cell-packed layouts a sample's 8 corners
+// are one vector load; in the linear layout they are one vector offset plus
+// 8 wave-uniform scalar offsets.
 #include "ff_math.h"
 #include "rt_internal.h"
 
