@@ -596,16 +596,16 @@ def main():
     gsps = samples_per_step / (ms_step * 1e-3) / 1e9
     fps = n_views / (ms_step * 1e-3)
 
-    # single-view latency of the plain per-frame renderer (enqueue -> done, device clock)
-    lat = []
-    if not args.only:
+    # single-view latency of the plain per-frame renderer (enqueue -> done, device
+    # clock), arguments marshalled before the timed calls
+    def single_view_latency(opts, images):
         import ctypes as C
         L = rt.lib()
         calls = []
-        for cam, o in zip(cams, outs):
+        for cam, o in zip(cams, images):
             calls.append((C.c_void_p(vol.handle), (C.c_int64 * 3)(*vol.dims), None, C.c_void_p(tf.handle),
                           C.byref(rt.make_camera(cam)), width, height, C.c_double(step), C.c_double(cutoff), None,
-                          C.c_void_p(o.data_ptr()), None, rt._stream_ptr()))
+                          C.c_void_p(o.data_ptr()), C.byref(opts), rt._stream_ptr()))
         evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(3 * n_views)]
         torch.cuda.synchronize()
         for k, (a, b) in enumerate(evs):
@@ -613,7 +613,11 @@ def main():
             L.rt_render(*calls[k % n_views])
             b.record(stream)
         torch.cuda.synchronize()
-        lat = [a.elapsed_time(b) for a, b in evs]
+        return [a.elapsed_time(b) for a, b in evs]
+
+    lat = []
+    if not args.only:
+        lat = single_view_latency(rt.make_opts(**shape), outs)
 
     # roofline of the dominant kernel: algorithmic bytes = 8 trilinear corners
     # x 2 B per sample + 16 B per output pixel, per launch
@@ -661,7 +665,12 @@ def main():
     # composited-sample count, fewer samples gathered; reported beside the
     # fixed-step figure, never as it
     if not args.only:
-        plan_s = rt.BatchPlan(n_views, rt.U16, layout=layout, skip_empty=True, **shape)
+        shape_s = shape
+        if tuned is not None:
+            from paper_1211_5595_amd import autotune
+            t_s = autotune.tune_launch(vol, tf, cams, width, height, step, cutoff, reps=3, skip_empty=True)
+            shape_s = dict(tile=tuple(t_s["tile"]), waves_per_block=t_s["waves_per_block"])
+        plan_s = rt.BatchPlan(n_views, rt.U16, layout=layout, skip_empty=True, **shape_s)
         outs_s = [torch.empty_like(o) for o in outs]
         jobs_s = [rt.Job(vol, tf, cam, width, height, step, cutoff, out=o, skip_empty=True)
                   for cam, o in zip(cams, outs_s)]
@@ -669,10 +678,13 @@ def main():
         plan.launch(jobs)
         torch.cuda.synchronize()
         same = all(torch.equal(a, b) for a, b in zip(outs, outs_s))
+        lat_s = single_view_latency(rt.make_opts(skip_empty=True, **shape_s), outs_s)
         line["skip_empty"] = {"ms_per_step": round(ms_s, 4), "fps": round(n_views / (ms_s * 1e-3), 1),
                               "speedup_vs_fixed_step": round(ms_step / ms_s, 3),
                               "composited_gsamples_per_s": round(samples_per_step / (ms_s * 1e-3) / 1e9, 3),
-                              "images_bitwise_equal": bool(same)}
+                              "images_bitwise_equal": bool(same), "tile": list(shape_s["tile"]),
+                              "waves_per_block": shape_s["waves_per_block"],
+                              "single_view_p50_ms": percentile(lat_s, 50), "single_view_p99_ms": percentile(lat_s, 99)}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(vol_np, tf_np, cams, vs.spacing, width, height, step, cutoff, ts.vmax,
                                             args.cpu_budget)

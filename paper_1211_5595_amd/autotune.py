@@ -31,8 +31,10 @@ def size_class(n: int) -> int:
     return int(math.floor(math.log2(max(int(n), 1))))
 
 
-def launch_key(arch: str, storage: int, layout: int, dims: Sequence[int], width: int, height: int) -> str:
-    return f"{arch}|s{storage}|l{layout}|v{size_class(dims[0] * dims[1] * dims[2])}|i{size_class(width * height)}"
+def launch_key(arch: str, storage: int, layout: int, dims: Sequence[int], width: int, height: int,
+               skip_empty: bool = False) -> str:
+    key = f"{arch}|s{storage}|l{layout}|v{size_class(dims[0] * dims[1] * dims[2])}|i{size_class(width * height)}"
+    return key + ("|skip" if skip_empty else "")
 
 
 class Cache:
@@ -99,18 +101,20 @@ def _time_ms(fn, reps: int) -> float:
 
 def tune_launch(volume, tf, cameras, width: int, height: int, step_vox: float = 0.5, alpha_cutoff: float = 0.99,
                 reps: int = 3, tiles: Sequence[Tuple[int, int]] = TILES, waves: Sequence[int] = WAVES,
-                cache: Optional[Cache] = None, force: bool = False) -> dict:
+                cache: Optional[Cache] = None, force: bool = False, skip_empty: bool = False) -> dict:
     """Choose tile shape and wavefronts per workgroup for batched renders of
-    `cameras` (representative views) of this volume at width x height."""
+    `cameras` (representative views) of this volume at width x height (with
+    empty-space skipping when skip_empty: that kernel has its own best shape)."""
     from . import Job, render_batch
     import torch
-    key = launch_key(_gpu_arch(), volume.storage, volume.layout, volume.dims, width, height)
+    key = launch_key(_gpu_arch(), volume.storage, volume.layout, volume.dims, width, height, skip_empty)
     if cache is not None and not force:
         hit = cache.get(key)
         if hit is not None:
             return hit
     outs = [torch.empty((height, width, 4), dtype=torch.float32, device=volume.buf.device) for _ in cameras]
-    jobs = [Job(volume, tf, c, width, height, step_vox, alpha_cutoff, out=o) for c, o in zip(cameras, outs)]
+    jobs = [Job(volume, tf, c, width, height, step_vox, alpha_cutoff, out=o, skip_empty=skip_empty)
+            for c, o in zip(cameras, outs)]
     cands = [(t, w) for t in tiles for w in waves]
     best, table = pick_best(cands, lambda c: _time_ms(lambda: render_batch(jobs, tile=c[0], waves_per_block=c[1]),
                                                       reps))
