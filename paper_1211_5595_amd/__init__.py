@@ -268,8 +268,11 @@ class Volume:
 
     ``values``: numpy array or CUDA tensor, C-order [z][y][x] of uint8,
     uint16, float16 or float32.  ``storage``: one of U8, U16, F16, F32
-    (``layout`` LAYOUT_CELLS or LAYOUT_LINEAR) or U8_BRICKSCALED (``brick``
-    8/16/32, ``layout`` LAYOUT_CELLS or LAYOUT_BRICKS)."""
+    (``layout`` LAYOUT_CELLS or LAYOUT_LINEAR; LAYOUT_POLY for U8/U16) or
+    U8_BRICKSCALED (``brick`` 8/16/32, ``layout`` LAYOUT_CELLS or
+    LAYOUT_BRICKS).  With ``stream`` given, the conversion runs there after
+    the work already queued on the current stream (which produced the
+    source)."""
 
     def __init__(self, values, spacing: Sequence[float], storage: Optional[int] = None, brick: int = 0,
                  stream=None, device="cuda", layout: int = LAYOUT_CELLS):
@@ -297,6 +300,10 @@ class Volume:
         self.layout = int(layout)
         self.nbytes = rt_volume_bytes(self.dims, self.storage, self.layout, self.brick)
         self.buf = torch.empty(self.nbytes, dtype=torch.uint8, device=src.device)
+        if stream is not None:
+            stream.wait_stream(torch.cuda.current_stream(src.device))   # the source copy / producer
+            self.buf.record_stream(stream)
+            src.record_stream(stream)
         self.handle = rt_create_volume(src.data_ptr(), src_dtype, self.dims, self.spacing, self.storage, self.layout,
                                        self.brick, self.buf.data_ptr(), self.nbytes, stream)
         self._src = src  # kept until the relayout on the stream has consumed it
@@ -326,6 +333,8 @@ class TransferFunction:
         self.vmin, self.vmax = float(vmin), float(vmax)
         self.nbytes = rt_tf_bytes(self.K)
         self.buf = torch.empty(self.nbytes, dtype=torch.uint8, device=device)
+        if stream is not None:
+            self.buf.record_stream(stream)
         self.handle = rt_set_transfer_function(None, t, vmin, vmax, self.buf.data_ptr(), self.nbytes, stream)
         self.table = t
 

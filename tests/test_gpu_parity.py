@@ -470,3 +470,18 @@ def test_abi_errors_with_handles(rt, torch_mod, small):
     with pytest.raises(rt.Unsupported):
         rt.rt_render(gv.handle, gv.dims, None, gtf.handle, good, 8, 8, 0.5, 0.99, None, out.data_ptr(),
                      rt.make_opts(tile=(5, 13)))
+
+
+def test_volume_and_table_created_on_a_side_stream(rt, torch_mod, small):
+    """Creation on a caller stream waits for the source copy made on the
+    current stream; the result renders exactly like the default-stream one."""
+    torch = torch_mod
+    s = torch.cuda.Stream()
+    gv = rt.Volume(small["np"], (1, 1, 2), storage=rt.U8, stream=s)
+    gtf = rt.TransferFunction(small["tf_np"], 0, 255, stream=s)
+    torch.cuda.current_stream().wait_stream(s)
+    cam = W.ortho_camera_small()
+    a = rt.render(gv, gtf, cam, 96, 80, 0.5, 0.99)
+    b = rt.render(small["gv"], small["gtf"], cam, 96, 80, 0.5, 0.99)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
