@@ -984,12 +984,11 @@ hipError_t plain_launch_k(const ViewDesc& v, const LaunchShape& ls, unsigned lon
     const int nblk = v.nblocks;
     if (nblk <= 0) return hipSuccess;
     const size_t lds = (size_t)(v.K + 1) * sizeof(float4) + (v.skip_empty ? (size_t)kSkipMaskBytes : 0);
-    static bool attr = false;
-    if (!attr) {
-        (void)hipFuncSetAttribute((const void*)march_plain_kernel<KIND, LAYOUT, SKIP>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)((kMaxK + 1) * sizeof(float4) + kSkipMaskBytes));
-        attr = true;
-    }
+    // once per kernel, thread-safe (function-local static initialisation)
+    static const hipError_t attr = hipFuncSetAttribute((const void*)march_plain_kernel<KIND, LAYOUT, SKIP>,
+                                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                       (int)((kMaxK + 1) * sizeof(float4) + kSkipMaskBytes));
+    (void)attr;
     hipLaunchKernelGGL((march_plain_kernel<KIND, LAYOUT, SKIP>), dim3(nblk), dim3(64 * ls.waves), lds, s, v, ls,
                        log2i(ls.tile_w), counter);
     return hipGetLastError();
@@ -1005,12 +1004,10 @@ template <int KIND, int LAYOUT, bool SKIP>
 hipError_t batch_launch_k(void* ws, int grid, const LaunchShape& ls, int max_k, hipStream_t s) {
     const int tf_entries = max_k + 1;
     const size_t lds = (size_t)tf_entries * sizeof(float4) + kSkipMaskBytes + 16;
-    static bool attr = false;
-    if (!attr) {
-        (void)hipFuncSetAttribute((const void*)march_batch_kernel<KIND, LAYOUT, SKIP>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)((kMaxK + 1) * sizeof(float4) + kSkipMaskBytes + 16));
-        attr = true;
-    }
+    static const hipError_t attr = hipFuncSetAttribute((const void*)march_batch_kernel<KIND, LAYOUT, SKIP>,
+                                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                       (int)((kMaxK + 1) * sizeof(float4) + kSkipMaskBytes + 16));
+    (void)attr;
     hipLaunchKernelGGL((march_batch_kernel<KIND, LAYOUT, SKIP>), dim3(grid), dim3(64 * ls.waves), lds, s,
                        static_cast<char*>(ws), ls, log2i(ls.tile_w), tf_entries);
     return hipGetLastError();
