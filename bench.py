@@ -256,7 +256,7 @@ def bench_precision(args):
         del plan, vol
     line = _contract("ray samples/sec (G/s) per storage type at 1024x1024 over 256x256x160, step 0.25; "
                      "max/mean RGBA error vs FP64 oracle", results["u16"]["gsamples_per_s"], "Gsamples/s", args,
-                     results["u16"]["ms_per_launch"], "u16/f16/u8",
+                     results["u16"]["ms_per_launch"], "f32",
                      {"workload": "brain-precision-8x1024x1024-step0.25", "volume": list(vs.dims),
                       "views": n_views, "image": [size, size], "step_vox": step, "alpha_cutoff": cutoff,
                       "tf_entries": ts.K, "storage": ["u16", "f16", "u8_brick16"], "launch": "graph"},
@@ -308,7 +308,7 @@ def bench_projection(args):
                          "algorithmic_GB_per_s": None if skip else
                          round((samples * 16 + n_views * width * height * 16) / (ms * 1e-3) / 1e9, 1)}
     line = _contract("ray samples/sec (G/s) + fps per ray function at 512x512 over 256x256x160",
-                     results["mip"]["gsamples_per_s"], "Gsamples/s", args, results["mip"]["ms_per_launch"], "u16",
+                     results["mip"]["gsamples_per_s"], "Gsamples/s", args, results["mip"]["ms_per_launch"], "f32",
                      {"workload": "brain-ray-functions-36x512x512-u16", "volume": list(vs.dims), "views": n_views,
                       "image": [width, height], "step_vox": step, "tf_entries": ts.K,
                       "ray_functions": list(results), "launch": "graph"},
@@ -352,7 +352,7 @@ def bench_batch(args):
     algo = samples * 16 + pixels * 16
     g = samples / (ms_graph * 1e-3) / 1e9
     line = _contract("ray samples/sec (G/s): 128 views of 32 uneven u16 volumes, one persistent graph launch vs "
-                     "128 plain launches", round(g, 3), "Gsamples/s", args, ms_graph, "u16",
+                     "128 plain launches", round(g, 3), "Gsamples/s", args, ms_graph, "f32",
                      {"workload": "uneven-batch-32vol-128views-u16", "volumes": len(specs), "views": len(jobs),
                       "sizes": sorted({s.dims for s in specs}), "image_sides": [min(j.width for j in jobs),
                                                                               max(j.width for j in jobs)],
@@ -464,7 +464,7 @@ def bench_serve(args):
     sat = {"speedup_of_arrivals": 20, "served": served(resident + (4 << 30), 20.0, fast_n),
            "serial": serial(20.0, fast_n)}
     line = _contract("p50/p99 render latency (ms), Poisson 200 req/s over 16 resident u16 volumes, continuous "
-                     "batching", loose["p99_ms"], "ms", args, loose["mean_ms"], "u16",
+                     "batching", loose["p99_ms"], "ms", args, loose["mean_ms"], "f32",
                      {"workload": "serve-poisson200-16vol-u16", "volumes": len(dims), "sizes": W.BATCH_SIZES,
                       "requests": n_req, "warmup_requests": warm, "image_sides": [256, 1024], "streams": 3,
                       "max_batch": 64, "step_vox": 0.5, "alpha_cutoff": 0.99, "tf_entries": 4096,
@@ -503,6 +503,9 @@ def main():
                          "iso-surface)")
     ap.add_argument("--layout", choices=["cells", "poly", "linear"], default="cells",
                     help="device layout of the orbit volume")
+    ap.add_argument("--storage", choices=["u16", "u15"], default="u15",
+                    help="orbit: device storage of the 12-bit uint16 phantom (u15 keeps x-pairs as differences, "
+                         "lossless below 32768: images are checked bit for bit against u16 storage)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -540,7 +543,10 @@ def main():
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
     layout = {"cells": rt.LAYOUT_CELLS, "poly": rt.LAYOUT_POLY, "linear": rt.LAYOUT_LINEAR}[args.layout]
-    vol = rt.Volume(vol_np, vs.spacing, storage=rt.U16, layout=layout)
+    storage = {"u16": rt.U16, "u15": rt.U15}[args.storage]
+    if storage == rt.U15 and layout != rt.LAYOUT_CELLS:
+        raise SystemExit("u15 storage exists in the cell layout only")
+    vol = rt.Volume(vol_np, vs.spacing, storage=storage, layout=layout)
     tf = rt.TransferFunction(tf_np, ts.vmin, ts.vmax)
     outs = [torch.empty((height, width, 4), dtype=torch.float32, device="cuda") for _ in range(n_views)]
     jobs = [rt.Job(vol, tf, cam, width, height, step, cutoff, out=o) for cam, o in zip(cams, outs)]
@@ -554,13 +560,20 @@ def main():
         shape = dict(tile=tuple(tuned["tile"]), waves_per_block=tuned["waves_per_block"])
     else:
         shape = dict(tile=(8, 8), waves_per_block=16)
-    plan = rt.BatchPlan(n_views, rt.U16, layout=layout, **shape)
+    plan = rt.BatchPlan(n_views, storage, layout=layout, **shape)
 
     # untimed counting pass
     counter = torch.zeros(1, dtype=torch.int64, device="cuda")
     rt.render_batch(jobs, sample_counter=counter)
     torch.cuda.synchronize()
     samples_per_step = int(counter.item())
+    equal_u16 = None
+    if storage == rt.U15:  # the difference encoding must not change a bit of the 16-bit images
+        vol16 = rt.Volume(vol_np, vs.spacing, storage=rt.U16, layout=layout)
+        outs16 = rt.render_batch([rt.Job(vol16, tf, cam, width, height, step, cutoff) for cam in cams])
+        torch.cuda.synchronize()
+        equal_u16 = all(torch.equal(a, b) for a, b in zip(outs, outs16))
+        del vol16, outs16
 
     def step_batch():
         rt.render_batch(jobs, **shape)
@@ -584,7 +597,7 @@ def main():
 
     forms = {"batch": step_batch, "graph": step_graph, "plain": step_plain}
     if args.only == "skip":
-        plan_s = rt.BatchPlan(n_views, rt.U16, layout=layout, skip_empty=True, **shape)
+        plan_s = rt.BatchPlan(n_views, storage, layout=layout, skip_empty=True, **shape)
         jobs_s = [rt.Job(vol, tf, cam, width, height, step, cutoff, out=o, skip_empty=True)
                   for cam, o in zip(cams, outs)]
         forms = {"skip": lambda: plan_s.launch(jobs_s)}
@@ -627,7 +640,8 @@ def main():
     ms_per_launch = ms_step / launches_per_step
     achieved = bytes_per_launch / (ms_per_launch * 1e-3) / 1e9
     workload = "brain-orbit-36x512x512-u16"
-    traffic = load_traffic(workload + ":" + args.layout + ":" + best)
+    traffic = load_traffic(workload + ":" + args.layout + ("" if args.storage == "u16" else "-" + args.storage)
+                           + ":" + best)
     if best == "skip":  # skipped samples are never gathered: no algorithmic-byte roofline for this form
         achieved, traffic = None, None
 
@@ -642,13 +656,14 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "u16",
+        "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": workload, "volume": list(vs.dims), "spacing": list(vs.spacing), "storage": "u16",
+        "config": {"workload": workload, "volume": list(vs.dims), "spacing": list(vs.spacing), "storage": args.storage,
                    "image": [width, height], "views": n_views, "step_vox": step, "alpha_cutoff": cutoff,
                    "tf_entries": ts.K, "launch": best, "layout": args.layout, "tile": list(shape["tile"]),
                    "waves_per_block": shape["waves_per_block"]},
         "autotune": tuned,
+        "images_bitwise_equal_u16_storage": equal_u16,
         "fps": round(fps, 1),
         "samples_per_step": samples_per_step,
         "ms_per_step_by_form": {k: round(v, 4) for k, v in ms.items()},
@@ -658,7 +673,8 @@ def main():
         "roofline": None if achieved is None else {
                      "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
-                     "kernel": "march_batch_kernel<u16>" if best in ("batch", "graph", "skip") else "march_plain_kernel<u16>",
+                     "kernel": ("march_batch_kernel<" if best in ("batch", "graph", "skip") else "march_plain_kernel<")
+                               + args.storage + ">",
                      "algorithmic_bytes_per_launch": int(bytes_per_launch)},
     }
     # exact empty-space skipping over the same views: same images, same
@@ -670,7 +686,7 @@ def main():
             from paper_1211_5595_amd import autotune
             t_s = autotune.tune_launch(vol, tf, cams, width, height, step, cutoff, reps=3, skip_empty=True)
             shape_s = dict(tile=tuple(t_s["tile"]), waves_per_block=t_s["waves_per_block"])
-        plan_s = rt.BatchPlan(n_views, rt.U16, layout=layout, skip_empty=True, **shape_s)
+        plan_s = rt.BatchPlan(n_views, storage, layout=layout, skip_empty=True, **shape_s)
         outs_s = [torch.empty_like(o) for o in outs]
         jobs_s = [rt.Job(vol, tf, cam, width, height, step, cutoff, out=o, skip_empty=True)
                   for cam, o in zip(cams, outs_s)]

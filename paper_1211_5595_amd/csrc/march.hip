@@ -139,6 +139,28 @@ __device__ __forceinline__ bool setup_ray(const VD& V, int i, int j, Ray& R) {
 
 __device__ __forceinline__ float lerp(float a, float b, float t) { return fmaf(t, b - a, a); }
 
+// a * b + c on 24-bit unsigned operands in one instruction (the compiler
+// otherwise splits the multiply-adds of a cell address into multiplies and
+// three-way adds, two instructions more per sample).  b is wave-uniform.
+__device__ __forceinline__ uint32_t mad24_s(uint32_t a, uint32_t b, uint32_t c) {
+    uint32_t d;
+    asm("v_mad_u32_u24 %0, %1, %2, %3" : "=v"(d) : "v"(a), "s"(b), "v"(c));
+    return d;
+}
+__device__ __forceinline__ uint32_t mad24_imm6(uint32_t a, uint32_t c) {
+    uint32_t d;
+    asm("v_mad_u32_u24 %0, %1, 6, %2" : "=v"(d) : "v"(a), "v"(c));
+    return d;
+}
+// (a << S) + c in one instruction
+template <int S>
+__device__ __forceinline__ uint32_t lshl_add_(uint32_t a, uint32_t c) {
+    uint32_t d;
+    asm("v_lshl_add_u32 %0, %1, %2, %3" : "=v"(d) : "v"(a), "n"(S), "v"(c));
+    return d;
+}
+#define lshl_add(a, s, c) lshl_add_<s>((a), (c))
+
 __device__ __forceinline__ uint32_t hiword(long long Q) { return (uint32_t)((unsigned long long)Q >> 32); }
 __device__ __forceinline__ float frac32(long long Q) { return (float)(uint32_t)Q * 0x1p-32f; }
 
@@ -161,6 +183,10 @@ struct Elem<ST_U8> {
 };
 template <>
 struct Elem<ST_U8B> : Elem<ST_U8> {};
+template <>
+struct Elem<ST_U15> {
+    static constexpr uint32_t bytes = 2;  // only the cell-packed layout exists for this type
+};
 template <>
 struct Elem<ST_U16> {
     static constexpr uint32_t bytes = 2;
@@ -310,11 +336,32 @@ struct CellBits<ST_F32> {
 template <class VOL>
 __device__ __forceinline__ uint32_t cell_index(const VOL& vol, const long long Q[3]) {
     const uint32_t ix = hiword(Q[0]), iy = hiword(Q[1]), iz = hiword(Q[2]);
-    uint32_t c = __umul24(ix >> 1, 6u) + ix;
-    c = __umul24(iy >> 1, vol.sy) + c;
-    c = __umul24(iz >> 1, vol.sz) + c;
-    return c + 2u * iy + 4u * iz;
+    uint32_t c = lshl_add(iz, 2, lshl_add(iy, 1, ix));
+    c = mad24_imm6(ix >> 1, c);
+    c = mad24_s(iy >> 1, vol.sy, c);
+    return mad24_s(iz >> 1, vol.sz, c);
 }
+
+// 15-bit difference cells: the x-lerp of a pair (c0, d = c1 - c0) is
+// fma(fx, d, c0) -- exactly what trilinear8 computes from (c0, c1), so the
+// images equal those of 16-bit cells bit for bit, with one conversion less
+// per pair.
+template <>
+struct Sampler<ST_U15, LAYOUT_CELLS> {
+    using Raw = u32x4;
+    template <class VOL>
+    static __device__ __forceinline__ Raw load(__amdgpu_buffer_rsrc_t r, const VOL& vol, const Corners&,
+                                               const long long Q[3]) {
+        return __builtin_amdgcn_raw_buffer_load_b128(r, cell_index(vol, Q) << 4, 0, 0);
+    }
+    static __device__ __forceinline__ float value(const Raw& w, float fx, float fy, float fz) {
+        float x[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            x[k] = fmaf(fx, (float)(int)(short)(w[k] >> 16), (float)(w[k] & 0xffffu));
+        return lerp(lerp(x[0], x[1], fy), lerp(x[2], x[3], fy), fz);
+    }
+};
 
 template <int KIND>
 struct Sampler<KIND, LAYOUT_CELLS> {
@@ -527,8 +574,9 @@ __device__ __forceinline__ int leap(const uint32_t* s_mask, const VOL& vol, long
 }
 
 // WINDOW: thresholding -- samples whose value lies outside [iso_lo, iso_hi]
-// are transparent (their opacity is taken as 0).
-template <int KIND, int LAYOUT, bool SKIP, bool WINDOW, class VD>
+// are transparent (their opacity is taken as 0).  COUNT: report the number of
+// samples taken (without it the loop keeps no per-ray copy of its counter).
+template <int KIND, int LAYOUT, bool SKIP, bool WINDOW, bool COUNT, class VD>
 __device__ __forceinline__ void march_pixel(const VD& V, const float4* __restrict__ s_tf,
                                             const uint32_t* __restrict__ s_mask, __amdgpu_buffer_rsrc_t rs,
                                             const Corners& cn, int i, int j, float4& px, int& count) {
@@ -538,7 +586,9 @@ __device__ __forceinline__ void march_pixel(const VD& V, const float4* __restric
     int k = 0;
     if (setup_ray(V, i, j, R)) {
         const float Km1 = (float)(V.K - 1);
-        const float ta = V.tf_a, tb = V.tf_b, thr = V.thr;
+        const float ta = V.tf_a, thr = V.thr;
+        float tb = V.tf_b;
+        asm("" : "+v"(tb));  // held in a vector register: fma(val, ta, tb) may read one scalar only
         if (R.m > 0) {
             typename S::Raw cur = S::load(rs, V.vol, cn, R.Q);
             // wavefront-uniform: the bricks are looked at every 4th sample and
@@ -563,22 +613,21 @@ __device__ __forceinline__ void march_pixel(const VD& V, const float4* __restric
                         stale = false;
                     }
                 }
-                const long long Qn[3] = {R.Q[0] + R.dQ[0], R.Q[1] + R.dQ[1], R.Q[2] + R.dQ[2]};
-                const typename S::Raw nxt = S::load(rs, V.vol, cn, Qn);
                 const float val = S::value(cur, frac32(R.Q[0]), frac32(R.Q[1]), frac32(R.Q[2]));
                 float4 c = classify(s_tf, val, ta, tb, Km1);
                 if (WINDOW && !(val >= V.iso_lo && val <= V.iso_hi)) c.w = 0.0f;
                 const float Ta = T * c.w;
+                asm volatile("" ::"v"(Ta));  // formed before T is overwritten: no copy of T
                 Cr = fmaf(Ta, c.x, Cr);
                 Cg = fmaf(Ta, c.y, Cg);
                 Cb = fmaf(Ta, c.z, Cb);
                 T = fmaf(-T, c.w, T);
                 ++k;
                 if (k >= R.m || T <= thr) break;
-                cur = nxt;
-                R.Q[0] = Qn[0];
-                R.Q[1] = Qn[1];
-                R.Q[2] = Qn[2];
+                R.Q[0] += R.dQ[0];
+                R.Q[1] += R.dQ[1];
+                R.Q[2] += R.dQ[2];
+                cur = S::load(rs, V.vol, cn, R.Q);
             }
         }
         if (R.wp > 0.0f && T > thr) {
@@ -592,11 +641,11 @@ __device__ __forceinline__ void march_pixel(const VD& V, const float4* __restric
             Cg = fmaf(Ta, c.y, Cg);
             Cb = fmaf(Ta, c.z, Cb);
             T = fmaf(-T, a, T);
-            ++k;
+            if constexpr (COUNT) ++k;
         }
     }
     px = make_float4(fmaf(T, V.bg[0], Cr), fmaf(T, V.bg[1], Cg), fmaf(T, V.bg[2], Cb), fmaf(T, V.bg[3], 1.0f - T));
-    count = k;
+    count = COUNT ? k : 0;
 }
 
 __device__ __forceinline__ int wave_sum(int v) {
@@ -789,10 +838,16 @@ __device__ __forceinline__ void render_block(const VD& V, const float4* __restri
     if (i < V.W && j < V.H) {
         float4 px;
         const int fn = V.ray_function;  // uniform over the view
-        if (fn == RT_FN_COMPOSITE)
-            march_pixel<KIND, LAYOUT, SKIP, false, VD>(V, s_tf, s_mask, rs, cn, i, j, px, count);
-        else if (fn == RT_FN_THRESHOLD)
-            march_pixel<KIND, LAYOUT, SKIP, true, VD>(V, s_tf, s_mask, rs, cn, i, j, px, count);
+        // the skipping loop keeps a per-ray counter anyway (leaps differ per ray)
+        const bool want_count = SKIP || V.counts != nullptr || counter != nullptr;
+        if (fn == RT_FN_COMPOSITE) {
+            if (want_count)
+                march_pixel<KIND, LAYOUT, SKIP, false, true, VD>(V, s_tf, s_mask, rs, cn, i, j, px, count);
+            else
+                march_pixel<KIND, LAYOUT, SKIP, false, SKIP, VD>(V, s_tf, s_mask, rs, cn, i, j, px, count);
+        } else if (fn == RT_FN_THRESHOLD) {
+            march_pixel<KIND, LAYOUT, SKIP, true, true, VD>(V, s_tf, s_mask, rs, cn, i, j, px, count);
+        }
         else if (fn == RT_FN_ISO)
             iso_pixel<KIND, LAYOUT, VD>(V, s_tf, rs, cn, i, j, px, count);
         else if (fn == RT_FN_MIP)
@@ -1042,6 +1097,8 @@ hipError_t launch_march_plain(const ViewDesc& v, const LaunchShape& ls, unsigned
         case ST_U8B:
             return L == LAYOUT_CELLS ? plain_launch<ST_U8B, LAYOUT_CELLS>(v, ls, counter, s)
                                      : plain_launch<ST_U8B, LAYOUT_BRICKS>(v, ls, counter, s);
+        case ST_U15:
+            return L == LAYOUT_CELLS ? plain_launch<ST_U15, LAYOUT_CELLS>(v, ls, counter, s) : hipErrorInvalidValue;
         default: return hipErrorInvalidValue;
     }
 }
@@ -1066,6 +1123,8 @@ hipError_t launch_skip_ranges(const VolDev& v, hipStream_t s) {
         case ST_U8B:
             return L == LAYOUT_CELLS ? skip_range_launch<ST_U8B, LAYOUT_CELLS>(v, s)
                                      : skip_range_launch<ST_U8B, LAYOUT_BRICKS>(v, s);
+        case ST_U15:
+            return L == LAYOUT_CELLS ? skip_range_launch<ST_U15, LAYOUT_CELLS>(v, s) : hipErrorInvalidValue;
         default: return hipErrorInvalidValue;
     }
 }
@@ -1091,6 +1150,8 @@ hipError_t launch_march_batch(int kind, int layout, void* workspace, int grid, c
         case ST_U8B:
             return C ? batch_launch<ST_U8B, LAYOUT_CELLS>(workspace, grid, ls, max_k, skip, s)
                      : batch_launch<ST_U8B, LAYOUT_BRICKS>(workspace, grid, ls, max_k, skip, s);
+        case ST_U15:
+            return C ? batch_launch<ST_U15, LAYOUT_CELLS>(workspace, grid, ls, max_k, skip, s) : hipErrorInvalidValue;
         default: return hipErrorInvalidValue;
     }
 }

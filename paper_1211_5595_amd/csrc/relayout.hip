@@ -102,6 +102,35 @@ __global__ void __launch_bounds__(256) relayout_cells_kernel(const typename Src<
     }
 }
 
+// 15-bit difference cells: as relayout_cells_kernel (same block order), with
+// each x-pair of corners stored as (c0, c1 - c0) in 16-bit words, the values
+// clamped to 0..32767 first so that the difference fits a signed word.
+template <int SRC>
+__global__ void __launch_bounds__(256) relayout_cells_dx_kernel(const typename Src<SRC>::T* __restrict__ src,
+                                                                 unsigned short* __restrict__ dst, int nx, int ny,
+                                                                 int nz, int nbx, int nby, int nbz) {
+    const int cxn = 2 * nbx, cyn = 2 * nby, czn = 2 * nbz;
+    const size_t total = (size_t)cxn * cyn * czn;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+        const int within = (int)(e & 7);
+        const size_t blk = e >> 3;
+        const int bx = (int)(blk % nbx);
+        const size_t t = blk / nbx;
+        const int by = (int)(t % nby), bz = (int)(t / nby);
+        const int cx = 2 * bx + (within & 1), cy = 2 * by + ((within >> 1) & 1), cz = 2 * bz + (within >> 2);
+#pragma unroll
+        for (int c = 0; c < 8; c += 2) {
+            const int j = min(max(cy + ((c >> 1) & 1) - 1, 0), ny - 1);
+            const int k = min(max(cz + (c >> 2) - 1, 0), nz - 1);
+            const int i0 = min(max(cx - 1, 0), nx - 1), i1 = min(max(cx, 0), nx - 1);
+            const int v0 = min((int)src[((size_t)k * ny + j) * nx + i0], 32767);
+            const int v1 = min((int)src[((size_t)k * ny + j) * nx + i1], 32767);
+            dst[e * 8 + c] = (unsigned short)v0;
+            dst[e * 8 + c + 1] = (unsigned short)(short)(v1 - v0);
+        }
+    }
+}
+
 // Polynomial cells: as relayout_cells_kernel, but the 8 stored values are the
 // coefficients of the cell's trilinear polynomial, formed in integer
 // arithmetic from integer corners and stored as exact binary32 values.
@@ -297,6 +326,13 @@ hipError_t cells_dispatch(const void* src, int dst_kind, const int32_t n[3], con
         case ST_F16:
             hipLaunchKernelGGL((relayout_cells_kernel<SRC, ST_F16>), dim3(g), dim3(256), 0, s, p, dst, n[0], n[1],
                                n[2], nb[0], nb[1], nb[2]);
+            break;
+        case ST_U15:
+            if constexpr (SRC == ST_U8 || SRC == ST_U16)
+                hipLaunchKernelGGL((relayout_cells_dx_kernel<SRC>), dim3(g), dim3(256), 0, s, p,
+                                   static_cast<unsigned short*>(dst), n[0], n[1], n[2], nb[0], nb[1], nb[2]);
+            else
+                return hipErrorInvalidValue;
             break;
         case ST_F32:
             hipLaunchKernelGGL((relayout_cells_kernel<SRC, ST_F32>), dim3(g), dim3(256), 0, s, p, dst, n[0], n[1],

@@ -13,7 +13,7 @@ struct ff {
     float hi, lo;
 };
 
-enum StorageKind : int { ST_U8 = 0, ST_U16 = 1, ST_F16 = 2, ST_F32 = 3, ST_U8B = 4 };
+enum StorageKind : int { ST_U8 = 0, ST_U16 = 1, ST_F16 = 2, ST_F32 = 3, ST_U8B = 4, ST_U15 = 5 };
 // Ray functions as stored in a view descriptor (values of rt_ray_function).
 enum RayFn : int { RT_FN_COMPOSITE = 0, RT_FN_MIP = 1, RT_FN_XRAY = 2, RT_FN_AVERAGE = 3, RT_FN_ISO = 4,
                    RT_FN_THRESHOLD = 5 };
@@ -30,6 +30,9 @@ enum LayoutKind : int { LAYOUT_CELLS = 0, LAYOUT_LINEAR = 1, LAYOUT_BRICKS = 2, 
 //    line for 16-bit storage), blocks in x-fastest order.  One vector load
 //    per sample, and the cache lines a ray tile touches do not depend on
 //    the viewing direction.
+//    For U15 the 8 16-bit words of a cell are the x-pairs (c000, c100-c000),
+//    (c010, c110-c010), (c001, c101-c001), (c011, c111-c011): the first of
+//    each pair unsigned, the difference a signed 16-bit integer.
 //  LAYOUT_POLY (U8/U16): like LAYOUT_CELLS, but a cell holds the binary32
 //    coefficients p0, px, py, pz, pxy, pxz, pyz, pxyz of its trilinear
 //    polynomial v = p0 + px fx + py fy + pz fz + pxy fx fy + pxz fx fz

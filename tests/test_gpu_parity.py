@@ -485,3 +485,66 @@ def test_volume_and_table_created_on_a_side_stream(rt, torch_mod, small):
     b = rt.render(small["gv"], small["gtf"], cam, 96, 80, 0.5, 0.99)
     torch.cuda.synchronize()
     assert torch.equal(a, b)
+
+
+def test_u15_cells_bitwise_equal_u16_on_12bit_data(rt, torch_mod, brain):
+    """Pairs stored as (c0, c1 - c0) interpolate with exactly the operations of
+    16-bit cells: plain, batched, planned and skipping renders are bit for
+    bit those of the u16 volume, sample counts included."""
+    torch = torch_mod
+    gv = rt.Volume(brain["np"], brain["sp"], storage=rt.U15)
+    for view in (0, 11, 26):
+        cam = brain["cams"][view]
+        a, ca = gpu_render(rt, torch, brain["gv"], brain["gtf"], cam, 300, 220, 0.5, 0.99)
+        b, cb = gpu_render(rt, torch, gv, brain["gtf"], cam, 300, 220, 0.5, 0.99)
+        assert np.array_equal(a, b) and np.array_equal(ca, cb), view
+    jobs16 = [rt.Job(brain["gv"], brain["gtf"], c, 160, 128, 0.5, 0.99) for c in brain["cams"][::9]]
+    jobs15 = [rt.Job(gv, brain["gtf"], c, 160, 128, 0.5, 0.99, skip_empty=True) for c in brain["cams"][::9]]
+    outs16 = rt.render_batch(jobs16)
+    rt.BatchPlan(len(jobs15), rt.U15, skip_empty=True).launch(jobs15)
+    torch.cuda.synchronize()
+    for x, j in zip(outs16, jobs15):
+        assert torch.equal(x, j.out)
+    with pytest.raises(rt.InvalidArgument):      # a u16 plan does not take u15 volumes
+        rt.BatchPlan(4, rt.U16).launch(jobs15[:1])
+
+
+def test_u15_every_ray_function_bitwise_equal_u16(rt, torch_mod, brain, small):
+    """Projections, thresholding (with and without skipping) and the iso-surface
+    (whose shading reads six more samples per hit) give the u16 images exactly;
+    an 8-bit source stored as u15 gives the images of the same values as u16."""
+    torch = torch_mod
+    gv = rt.Volume(brain["np"], brain["sp"], storage=rt.U15)
+    cam = brain["cams"][7]
+    for fn, lo, hi, sk in ((rt.MIP, 0.0, 0.0, False), (rt.XRAY, 0.0, 0.0, False),
+                           (rt.AVERAGE, 0.0, 0.0, False), (rt.THRESHOLD, 1200.0, 2600.0, True),
+                           (rt.ISO, 1000.0, 0.0, False)):
+        a = rt.render(brain["gv"], brain["gtf"], cam, 180, 150, 0.5, 0.99, ray_function=fn, iso_value=lo,
+                      iso_high=hi)
+        b = rt.render(gv, brain["gtf"], cam, 180, 150, 0.5, 0.99, ray_function=fn, iso_value=lo, iso_high=hi,
+                      skip_empty=sk)
+        torch.cuda.synchronize()
+        assert torch.equal(a, b), fn
+    v8 = small["np"]
+    a = rt.render(rt.Volume(v8.astype(np.uint16), (1, 1, 2), storage=rt.U16), small["gtf"], W.ortho_camera_small(),
+                  96, 80, 0.5, 0.99)
+    b = rt.render(rt.Volume(v8, (1, 1, 2), storage=rt.U15), small["gtf"], W.ortho_camera_small(), 96, 80, 0.5, 0.99)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
+def test_u15_clamps_above_32767(rt, torch_mod, orc):
+    """Values above 32767 are stored as 32767; the render equals the oracle on
+    the clamped field."""
+    rng = np.random.default_rng(15)
+    dims, sp = (29, 23, 17), (0.8, 1.0, 1.3)
+    v = rng.integers(0, 65536, size=dims[::-1], dtype=np.uint16)
+    v = ((v.astype(np.int64) + np.roll(v, 1, 0) + np.roll(v, 1, 2)) // 3).astype(np.uint16)
+    t = W.random_tf(1024, 61, alpha_max=0.3)
+    cam = W.random_camera(rng, dims, sp)
+    gv = rt.Volume(v, sp, storage=rt.U15)
+    got, c = gpu_render(rt, torch_mod, gv, rt.TransferFunction(t, 0, 40000), cam, 70, 50, 0.5, 0.99)
+    ref = orc.render(orc.Volume(np.minimum(v, 32767), sp), orc.TF(t, 0, 40000), cam, 70, 50, 0.5, 0.99,
+                     tie_delta=DELTA, want_band=True)
+    check(got, ref, c, "u15 clamped")
+    assert (v > 32767).any()
