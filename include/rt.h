@@ -70,18 +70,25 @@ typedef enum {
     RT_F16 = 2,             /* IEEE half; conversion from other types rounds to nearest even */
     RT_F32 = 3,             /* IEEE single */
     RT_U8_BRICKSCALED = 4,  /* storage only: 8-bit codes with a (lo, scale) per brick of B^3 cells */
-    RT_U15 = 5              /* storage only, RT_LAYOUT_CELLS only, from RT_U8/RT_U16 sources: integers
+    RT_U15 = 5,             /* storage only, RT_LAYOUT_CELLS only, from RT_U8/RT_U16 sources: integers
                              * 0..32767 (larger values are clamped to 32767, so 15-bit data such as
                              * 12-bit MRI is converted exactly); each cell keeps its x-neighbour corner
                              * pairs as (c0, c1 - c0), which saves one conversion per pair in the marcher.
                              * Images are bit-identical to RT_U16 for the same (unclamped) data. */
+    RT_U12 = 6              /* storage only, RT_LAYOUT_CELLS only, from RT_U8/RT_U16 sources: integers
+                             * 0..4096 (larger values are clamped to 4096, so 12-bit data is converted
+                             * exactly), each stored as the IEEE half of (value - 2048), which is exact
+                             * on that range.  The marcher interpolates the halves with mixed-precision
+                             * fused multiply-adds and no conversions; all arithmetic is binary32.
+                             * Images match RT_U16 to within binary32 rounding (not bit for bit: the
+                             * interpolation runs on values shifted by 2048). */
 } rt_dtype;
 
 /* Device layouts of a volume.  All of them add a one-node replicated border
  * on every face so that clamp-to-edge holds without per-sample clamping. */
 typedef enum {
     RT_LAYOUT_CELLS = 0,  /* every cell's 8 corners contiguous, cells in 2x2x2 blocks; any storage type
-                           * (the only layout of RT_U15).
+                           * (the only layout of RT_U15 and RT_U12).
                            * 8 values per cell (8x the grid); for RT_U8_BRICKSCALED the codes of a
                            * cell use its owning brick's (lo, scale), kept once per 2x2x2 block */
     RT_LAYOUT_LINEAR = 1, /* RT_U8/RT_U16/RT_F16/RT_F32: the bordered grid in C order (1x the grid) */

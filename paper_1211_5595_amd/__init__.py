@@ -20,7 +20,7 @@ import numpy as np
 
 __all__ = [
     "RTError", "InvalidArgument", "OutOfMemory", "DeviceError", "Unsupported",
-    "U8", "U16", "F16", "F32", "U8_BRICKSCALED", "U15", "COMPOSITE", "MIP", "XRAY", "AVERAGE", "ISO", "THRESHOLD",
+    "U8", "U16", "F16", "F32", "U8_BRICKSCALED", "U15", "U12", "COMPOSITE", "MIP", "XRAY", "AVERAGE", "ISO", "THRESHOLD",
     "lib", "rt_volume_bytes", "rt_create_volume", "rt_destroy_volume", "rt_tf_bytes",
     "rt_set_transfer_function", "rt_destroy_tf", "rt_render", "rt_batch_workspace_bytes",
     "rt_render_batch", "rt_batch_plan_create", "rt_batch_plan_launch", "rt_batch_plan_destroy",
@@ -30,7 +30,7 @@ __all__ = [
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "librtvol.so")
 
-U8, U16, F16, F32, U8_BRICKSCALED, U15 = 0, 1, 2, 3, 4, 5
+U8, U16, F16, F32, U8_BRICKSCALED, U15, U12 = 0, 1, 2, 3, 4, 5, 6
 LAYOUT_CELLS, LAYOUT_LINEAR, LAYOUT_BRICKS, LAYOUT_POLY = 0, 1, 2, 3
 COMPOSITE, MIP, XRAY, AVERAGE, ISO, THRESHOLD = range(6)
 _DTYPE_CODE = {np.dtype(np.uint8): U8, np.dtype(np.uint16): U16, np.dtype(np.float16): F16,

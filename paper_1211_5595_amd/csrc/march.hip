@@ -188,6 +188,10 @@ struct Elem<ST_U15> {
     static constexpr uint32_t bytes = 2;  // only the cell-packed layout exists for this type
 };
 template <>
+struct Elem<ST_U12> {
+    static constexpr uint32_t bytes = 2;  // only the cell-packed layout exists for this type
+};
+template <>
 struct Elem<ST_U16> {
     static constexpr uint32_t bytes = 2;
     static __device__ __forceinline__ float load(__amdgpu_buffer_rsrc_t r, uint32_t off, int soff) {
@@ -362,6 +366,61 @@ struct Sampler<ST_U15, LAYOUT_CELLS> {
         return lerp(lerp(x[0], x[1], fy), lerp(x[2], x[3], fy), fz);
     }
 };
+
+// 12-bit half cells: each corner is the binary16 of (value - 2048), exact for
+// values 0..4096.  A mixed-precision fused multiply-add reads binary16 halves
+// of a register directly: one forms c1 - c0 exactly, one the x-lerp
+// fma(fx, c1 - c0, c0) -- the operations of 16-bit cells on values shifted by
+// 2048, with no conversions.  stored() is the interpolated value in the
+// shifted units; value() adds the 2048 back.
+__device__ __forceinline__ float half_pair_diff(uint32_t w) {  // hi half - lo half, exact
+    float d;
+    asm("v_fma_mix_f32 %0, %1, 1.0, -%1 op_sel:[1,0,0] op_sel_hi:[1,0,1]" : "=v"(d) : "v"(w));
+    return d;
+}
+__device__ __forceinline__ float lo_half(uint32_t w) {
+    return (float)__builtin_bit_cast(_Float16, (unsigned short)(w & 0xffffu));
+}
+
+template <>
+struct Sampler<ST_U12, LAYOUT_CELLS> {
+    using Raw = u32x4;
+    static constexpr float bias = 2048.0f;
+    template <class VOL>
+    static __device__ __forceinline__ Raw load(__amdgpu_buffer_rsrc_t r, const VOL& vol, const Corners&,
+                                               const long long Q[3]) {
+        return __builtin_amdgcn_raw_buffer_load_b128(r, cell_index(vol, Q) << 4, 0, 0);
+    }
+    static __device__ __forceinline__ float stored(const Raw& w, float fx, float fy, float fz) {
+        float x[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) x[k] = fmaf(fx, half_pair_diff(w[k]), lo_half(w[k]));
+        return lerp(lerp(x[0], x[1], fy), lerp(x[2], x[3], fy), fz);
+    }
+    static __device__ __forceinline__ float value(const Raw& w, float fx, float fy, float fz) {
+        return stored(w, fx, fy, fz) + bias;
+    }
+};
+
+// Samplers whose stored values are shifted (bias != 0) give the compositing
+// loop the shifted value, with the shift folded into the table mapping.
+template <class...>
+using void_t_ = void;
+template <class S, class = void>
+struct StoredBias {
+    static constexpr float v = 0.0f;
+};
+template <class S>
+struct StoredBias<S, void_t_<decltype(S::bias)>> {
+    static constexpr float v = S::bias;
+};
+template <class S>
+__device__ __forceinline__ float stored_value(const typename S::Raw& w, float fx, float fy, float fz) {
+    if constexpr (StoredBias<S>::v != 0.0f)
+        return S::stored(w, fx, fy, fz);
+    else
+        return S::value(w, fx, fy, fz);
+}
 
 template <int KIND>
 struct Sampler<KIND, LAYOUT_CELLS> {
@@ -573,6 +632,11 @@ __device__ __forceinline__ int leap(const uint32_t* s_mask, const VOL& vol, long
     return (int)n;
 }
 
+template <class VD>
+__device__ __forceinline__ bool in_window(float val, const VD& V) {
+    return val >= V.iso_lo && val <= V.iso_hi;
+}
+
 // WINDOW: thresholding -- samples whose value lies outside [iso_lo, iso_hi]
 // are transparent (their opacity is taken as 0).  COUNT: report the number of
 // samples taken (without it the loop keeps no per-ray copy of its counter).
@@ -586,8 +650,9 @@ __device__ __forceinline__ void march_pixel(const VD& V, const float4* __restric
     int k = 0;
     if (setup_ray(V, i, j, R)) {
         const float Km1 = (float)(V.K - 1);
+        constexpr float bias = StoredBias<S>::v;
         const float ta = V.tf_a, thr = V.thr;
-        float tb = V.tf_b;
+        float tb = bias != 0.0f ? fmaf(bias, ta, V.tf_b) : V.tf_b;
         asm("" : "+v"(tb));  // held in a vector register: fma(val, ta, tb) may read one scalar only
         if (R.m > 0) {
             typename S::Raw cur = S::load(rs, V.vol, cn, R.Q);
@@ -613,9 +678,9 @@ __device__ __forceinline__ void march_pixel(const VD& V, const float4* __restric
                         stale = false;
                     }
                 }
-                const float val = S::value(cur, frac32(R.Q[0]), frac32(R.Q[1]), frac32(R.Q[2]));
+                const float val = stored_value<S>(cur, frac32(R.Q[0]), frac32(R.Q[1]), frac32(R.Q[2]));
                 float4 c = classify(s_tf, val, ta, tb, Km1);
-                if (WINDOW && !(val >= V.iso_lo && val <= V.iso_hi)) c.w = 0.0f;
+                if (WINDOW && !in_window(val + bias, V)) c.w = 0.0f;
                 const float Ta = T * c.w;
                 asm volatile("" ::"v"(Ta));  // formed before T is overwritten: no copy of T
                 Cr = fmaf(Ta, c.x, Cr);
@@ -632,9 +697,9 @@ __device__ __forceinline__ void march_pixel(const VD& V, const float4* __restric
         }
         if (R.wp > 0.0f && T > thr) {
             const typename S::Raw w = S::load(rs, V.vol, cn, R.Qp);
-            const float val = S::value(w, frac32(R.Qp[0]), frac32(R.Qp[1]), frac32(R.Qp[2]));
+            const float val = stored_value<S>(w, frac32(R.Qp[0]), frac32(R.Qp[1]), frac32(R.Qp[2]));
             float4 c = classify(s_tf, val, ta, tb, Km1);
-            if (WINDOW && !(val >= V.iso_lo && val <= V.iso_hi)) c.w = 0.0f;
+            if (WINDOW && !in_window(val + bias, V)) c.w = 0.0f;
             const float a = 1.0f - exp2f(R.wp * log2f(1.0f - c.w));
             const float Ta = T * a;
             Cr = fmaf(Ta, c.x, Cr);
@@ -1099,6 +1164,8 @@ hipError_t launch_march_plain(const ViewDesc& v, const LaunchShape& ls, unsigned
                                      : plain_launch<ST_U8B, LAYOUT_BRICKS>(v, ls, counter, s);
         case ST_U15:
             return L == LAYOUT_CELLS ? plain_launch<ST_U15, LAYOUT_CELLS>(v, ls, counter, s) : hipErrorInvalidValue;
+        case ST_U12:
+            return L == LAYOUT_CELLS ? plain_launch<ST_U12, LAYOUT_CELLS>(v, ls, counter, s) : hipErrorInvalidValue;
         default: return hipErrorInvalidValue;
     }
 }
@@ -1125,6 +1192,8 @@ hipError_t launch_skip_ranges(const VolDev& v, hipStream_t s) {
                                      : skip_range_launch<ST_U8B, LAYOUT_BRICKS>(v, s);
         case ST_U15:
             return L == LAYOUT_CELLS ? skip_range_launch<ST_U15, LAYOUT_CELLS>(v, s) : hipErrorInvalidValue;
+        case ST_U12:
+            return L == LAYOUT_CELLS ? skip_range_launch<ST_U12, LAYOUT_CELLS>(v, s) : hipErrorInvalidValue;
         default: return hipErrorInvalidValue;
     }
 }
@@ -1152,6 +1221,8 @@ hipError_t launch_march_batch(int kind, int layout, void* workspace, int grid, c
                      : batch_launch<ST_U8B, LAYOUT_BRICKS>(workspace, grid, ls, max_k, skip, s);
         case ST_U15:
             return C ? batch_launch<ST_U15, LAYOUT_CELLS>(workspace, grid, ls, max_k, skip, s) : hipErrorInvalidValue;
+        case ST_U12:
+            return C ? batch_launch<ST_U12, LAYOUT_CELLS>(workspace, grid, ls, max_k, skip, s) : hipErrorInvalidValue;
         default: return hipErrorInvalidValue;
     }
 }

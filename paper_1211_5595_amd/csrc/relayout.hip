@@ -131,6 +131,32 @@ __global__ void __launch_bounds__(256) relayout_cells_dx_kernel(const typename S
     }
 }
 
+// 12-bit half cells: as relayout_cells_kernel, each value clamped to 0..4096
+// and stored as the binary16 of (value - 2048), which is exact on that range
+// (every integer of magnitude up to 2048 is a binary16 value).
+template <int SRC>
+__global__ void __launch_bounds__(256) relayout_cells_h12_kernel(const typename Src<SRC>::T* __restrict__ src,
+                                                                  _Float16* __restrict__ dst, int nx, int ny, int nz,
+                                                                  int nbx, int nby, int nbz) {
+    const size_t total = (size_t)8 * nbx * nby * nbz;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+        const int within = (int)(e & 7);
+        const size_t blk = e >> 3;
+        const int bx = (int)(blk % nbx);
+        const size_t t = blk / nbx;
+        const int by = (int)(t % nby), bz = (int)(t / nby);
+        const int cx = 2 * bx + (within & 1), cy = 2 * by + ((within >> 1) & 1), cz = 2 * bz + (within >> 2);
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const int i = min(max(cx + (c & 1) - 1, 0), nx - 1);
+            const int j = min(max(cy + ((c >> 1) & 1) - 1, 0), ny - 1);
+            const int k = min(max(cz + (c >> 2) - 1, 0), nz - 1);
+            const int v = min((int)src[((size_t)k * ny + j) * nx + i], 4096);
+            dst[e * 8 + c] = (_Float16)(v - 2048);
+        }
+    }
+}
+
 // Polynomial cells: as relayout_cells_kernel, but the 8 stored values are the
 // coefficients of the cell's trilinear polynomial, formed in integer
 // arithmetic from integer corners and stored as exact binary32 values.
@@ -331,6 +357,13 @@ hipError_t cells_dispatch(const void* src, int dst_kind, const int32_t n[3], con
             if constexpr (SRC == ST_U8 || SRC == ST_U16)
                 hipLaunchKernelGGL((relayout_cells_dx_kernel<SRC>), dim3(g), dim3(256), 0, s, p,
                                    static_cast<unsigned short*>(dst), n[0], n[1], n[2], nb[0], nb[1], nb[2]);
+            else
+                return hipErrorInvalidValue;
+            break;
+        case ST_U12:
+            if constexpr (SRC == ST_U8 || SRC == ST_U16)
+                hipLaunchKernelGGL((relayout_cells_h12_kernel<SRC>), dim3(g), dim3(256), 0, s, p,
+                                   static_cast<_Float16*>(dst), n[0], n[1], n[2], nb[0], nb[1], nb[2]);
             else
                 return hipErrorInvalidValue;
             break;

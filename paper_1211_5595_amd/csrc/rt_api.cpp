@@ -72,6 +72,7 @@ int elem_bytes(int kind) {
         case ST_F16: return 2;
         case ST_F32: return 4;
         case ST_U15: return 2;
+        case ST_U12: return 2;
         default: return 0;
     }
 }
@@ -84,7 +85,8 @@ bool layout_allowed(int storage, int layout) {
         case RT_F16:
         case RT_F32: return layout == RT_LAYOUT_CELLS || layout == RT_LAYOUT_LINEAR;
         case RT_U8_BRICKSCALED: return layout == RT_LAYOUT_CELLS || layout == RT_LAYOUT_BRICKS;
-        case RT_U15: return layout == RT_LAYOUT_CELLS;
+        case RT_U15:
+        case RT_U12: return layout == RT_LAYOUT_CELLS;
         default: return false;
     }
 }
@@ -147,7 +149,7 @@ rt_status compute_data_layout(const int64_t dims[3], int storage, int layout, in
     for (int a = 0; a < 3; ++a)
         if (dims[a] < 2 || dims[a] > (1 << 20)) return fail(RT_ERR_INVALID_ARG, "each dimension must be in [2, 2^20]");
     std::memset(&L, 0, sizeof(L));
-    if (storage < RT_U8 || storage > RT_U15) return fail(RT_ERR_INVALID_ARG, "unknown storage type");
+    if (storage < RT_U8 || storage > RT_U12) return fail(RT_ERR_INVALID_ARG, "unknown storage type");
     const bool u8b = storage == RT_U8_BRICKSCALED;
     if (!layout_allowed(storage, layout)) return fail(RT_ERR_INVALID_ARG, "layout not available for this storage type");
     if (u8b) {
@@ -471,7 +473,7 @@ rt_status rt_create_volume(const void* src_dev, int src_dtype, const int64_t dim
     if (((uintptr_t)dev_buf & 255) != 0) return fail(RT_ERR_INVALID_ARG, "volume buffer must be 256-byte aligned");
     if (storage != RT_U8_BRICKSCALED) {
         const bool ok = storage == RT_F16 || storage == RT_F32 || (storage == RT_U16 && src_dtype <= RT_U16) ||
-                        (storage == RT_U8 && src_dtype == RT_U8) || (storage == RT_U15 && src_dtype <= RT_U16);
+                        (storage == RT_U8 && src_dtype == RT_U8) || ((storage == RT_U15 || storage == RT_U12) && src_dtype <= RT_U16);
         if (!ok) return fail(RT_ERR_INVALID_ARG, "conversion to this storage type would lose information");
         if (layout == RT_LAYOUT_POLY && src_dtype > RT_U16)
             return fail(RT_ERR_INVALID_ARG, "the polynomial layout needs integer source data");
@@ -675,7 +677,7 @@ rt_status rt_batch_plan_create(int max_jobs, int storage, int layout, void* work
     if (((uintptr_t)workspace & 255) != 0) return fail(RT_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
     if (max_jobs < 1 || max_jobs > kMaxBatchJobs) return fail(RT_ERR_INVALID_ARG, "max_jobs must be in [1, 4096]");
     if (ws_bytes < batch_ws_bytes(max_jobs)) return fail(RT_ERR_OUT_OF_MEMORY, "workspace smaller than rt_batch_workspace_bytes");
-    if (storage < RT_U8 || storage > RT_U15) return fail(RT_ERR_INVALID_ARG, "unknown storage type");
+    if (storage < RT_U8 || storage > RT_U12) return fail(RT_ERR_INVALID_ARG, "unknown storage type");
     if (!layout_allowed(storage, layout)) return fail(RT_ERR_INVALID_ARG, "layout not available for this storage type");
     LaunchShape ls;
     rt_status st = make_shape(opts, ls);

@@ -13,7 +13,7 @@ struct ff {
     float hi, lo;
 };
 
-enum StorageKind : int { ST_U8 = 0, ST_U16 = 1, ST_F16 = 2, ST_F32 = 3, ST_U8B = 4, ST_U15 = 5 };
+enum StorageKind : int { ST_U8 = 0, ST_U16 = 1, ST_F16 = 2, ST_F32 = 3, ST_U8B = 4, ST_U15 = 5, ST_U12 = 6 };
 // Ray functions as stored in a view descriptor (values of rt_ray_function).
 enum RayFn : int { RT_FN_COMPOSITE = 0, RT_FN_MIP = 1, RT_FN_XRAY = 2, RT_FN_AVERAGE = 3, RT_FN_ISO = 4,
                    RT_FN_THRESHOLD = 5 };

@@ -81,6 +81,8 @@ def test_volume_bytes(rt):
     assert vb((2, 2, 2), rt.F32) == r256(2 * 2 * 2 * 8 * 8 * 4)
     # 15-bit difference cells: the same size as 16-bit cells
     assert vb((256, 256, 160), rt.U15) == r256(129 * 129 * 81 * 8 * 8 * 2)
+    # 12-bit half cells: likewise
+    assert vb((256, 256, 160), rt.U12) == r256(129 * 129 * 81 * 8 * 8 * 2)
     # polynomial cells (integer data): as cells, 8 binary32 coefficients each
     assert vb((256, 256, 160), rt.U16, rt.LAYOUT_POLY) == r256(129 * 129 * 81 * 8 * 8 * 4)
     assert vb((64, 64, 32), rt.U8, rt.LAYOUT_POLY) == r256(33 * 33 * 17 * 8 * 8 * 4)
@@ -109,7 +111,9 @@ def test_volume_bytes(rt):
     ((4, 4, 4), 4, 3, 8, "InvalidArgument"),
     ((4, 4, 4), 5, 1, 0, "InvalidArgument"),    # 15-bit difference cells: cell layout only
     ((4, 4, 4), 5, 3, 0, "InvalidArgument"),
-    ((4, 4, 4), 6, 0, 0, "InvalidArgument"),
+    ((4, 4, 4), 6, 1, 0, "InvalidArgument"),    # 12-bit half cells: cell layout only
+    ((4, 4, 4), 6, 3, 0, "InvalidArgument"),
+    ((4, 4, 4), 7, 0, 0, "InvalidArgument"),
 ])
 def test_volume_bytes_errors(rt, dims, storage, layout, brick, exc):
     with pytest.raises(getattr(rt, exc)):

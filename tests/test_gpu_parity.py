@@ -533,6 +533,52 @@ def test_u15_every_ray_function_bitwise_equal_u16(rt, torch_mod, brain, small):
     assert torch.equal(a, b)
 
 
+def test_u12_brain_views_match_oracle(rt, torch_mod, orc, brain):
+    """12-bit half cells hold the phantom exactly; full views against the
+    oracle on the same grid, and against 16-bit storage to binary32 rounding."""
+    gv = rt.Volume(brain["np"], brain["sp"], storage=rt.U12)
+    for view in (2, 19):
+        cam = brain["cams"][view]
+        got, c = gpu_render(rt, torch_mod, gv, brain["gtf"], cam, 512, 512, 0.5, 0.99)
+        ref = orc.render(brain["ov"], brain["otf"], cam, 512, 512, 0.5, 0.99, tie_delta=DELTA, want_band=True)
+        check(got, ref, c, f"u12 brain view {view}")
+        u16, _ = gpu_render(rt, torch_mod, brain["gv"], brain["gtf"], cam, 512, 512, 0.5, 0.99)
+        assert np.abs(got - u16)[(ref.tie & 1) == 0].max() <= TOL
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_u12_random_small_cases(rt, torch_mod, orc, seed):
+    """Random grids (some values above 4096, stored as 4096), tables, cameras,
+    steps and cutoffs, with a plain and a batched launch."""
+    rng = np.random.default_rng(1200 + seed)
+    dims = tuple(int(x) for x in rng.integers(2, 60, 3))
+    sp = tuple(float(x) for x in rng.uniform(0.4, 2.5, 3))
+    v = rng.integers(0, 4600 if seed % 2 else 4097, size=dims[::-1], dtype=np.uint16)
+    v = ((v.astype(np.int64) + np.roll(v, 1, 0) + np.roll(v, 1, 1)) // 3).astype(np.uint16)
+    t = W.random_tf(int(rng.integers(64, 4097)), seed + 120, alpha_max=float(rng.uniform(0.05, 0.9)))
+    cam = W.random_camera(rng, dims, sp)
+    Wd, Hd = int(rng.integers(1, 120)), int(rng.integers(1, 100))
+    step, cutoff = float(rng.uniform(0.2, 1.2)), float(rng.uniform(0.6, 1.0))
+    gv, gtf = rt.Volume(v, sp, storage=rt.U12), rt.TransferFunction(t, 0, 4600)
+    got, c = gpu_render(rt, torch_mod, gv, gtf, cam, Wd, Hd, step, cutoff)
+    ref = orc.render(orc.Volume(np.minimum(v, 4096), sp), orc.TF(t, 0, 4600), cam, Wd, Hd, step, cutoff,
+                     tie_delta=DELTA, want_band=True)
+    check(got, ref, c, f"u12 seed {seed} dims {dims}")
+    out = rt.render_batch([rt.Job(gv, gtf, cam, Wd, Hd, step, cutoff)])[0]
+    torch_mod.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy().astype(np.float64), got)
+
+
+def test_u12_from_u8_source(rt, torch_mod, orc, small):
+    gv = rt.Volume(small["np"], (1, 1, 2), storage=rt.U12)
+    got, c = gpu_render(rt, torch_mod, gv, small["gtf"], W.ortho_camera_small(), 128, 128, 0.5, 0.99)
+    ref = orc.render(small["ov"], small["otf"], W.ortho_camera_small(), 128, 128, 0.5, 0.99, tie_delta=DELTA,
+                     want_band=True)
+    check(got, ref, c, "u12 from u8")
+    with pytest.raises(rt.InvalidArgument):     # binary32 source: not integer data
+        rt.Volume(small["np"].astype(np.float32), (1, 1, 2), storage=rt.U12)
+
+
 def test_u15_clamps_above_32767(rt, torch_mod, orc):
     """Values above 32767 are stored as 32767; the render equals the oracle on
     the clamped field."""

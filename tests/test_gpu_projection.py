@@ -118,7 +118,7 @@ def test_random_small_cases(rt, torch_mod, orc, seed):
     check(got, c, ref, f"random {seed} {rf} dims {dims}")
 
 
-@pytest.mark.parametrize("storage", ["F32", "F16", "U8_BRICKSCALED"])
+@pytest.mark.parametrize("storage", ["F32", "F16", "U8_BRICKSCALED", "U15", "U12"])
 def test_storage_types(rt, torch_mod, orc, brain, storage):
     """Every sampler variant under the summing projection (the maximum shares
     the sampling code)."""
@@ -128,6 +128,8 @@ def test_storage_types(rt, torch_mod, orc, brain, storage):
         gv, field = rt.Volume(v, sp, storage=rt.F32), orc.Volume(v.astype(np.float64), sp)
     elif storage == "F16":
         gv, field = rt.Volume(v, sp, storage=rt.F16), orc.Volume(v.astype(np.float16).astype(np.float64), sp)
+    elif storage in ("U15", "U12"):  # exact for the 12-bit phantom
+        gv, field = rt.Volume(v, sp, storage=getattr(rt, storage)), orc.Volume(v, sp)
     else:
         gv, field = rt.Volume(v, sp, storage=rt.U8_BRICKSCALED, brick=16), orc.Volume.from_u8_bricks(v, sp, 16)
     for rf in ("AVERAGE", "MIP"):

@@ -77,6 +77,7 @@ def test_brain_view_matches_oracle(rt, torch_mod, orc, brain):
     ("F16", "LAYOUT_CELLS", 0), ("F16", "LAYOUT_LINEAR", 0),
     ("F32", "LAYOUT_CELLS", 0), ("F32", "LAYOUT_LINEAR", 0),
     ("U8_BRICKSCALED", "LAYOUT_CELLS", 16), ("U8_BRICKSCALED", "LAYOUT_BRICKS", 8),
+    ("U15", "LAYOUT_CELLS", 0), ("U12", "LAYOUT_CELLS", 0),
 ])
 def test_storage_and_layouts_identical(rt, torch_mod, brain, storage, layout, brick):
     v = brain["np"]
