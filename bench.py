@@ -181,6 +181,11 @@ def _plain_caller(rt, jobs):
     return run
 
 
+def _storage(rt, args):
+    """Device storage of the 12-bit uint16 phantoms (every choice holds them exactly)."""
+    return {"u16": rt.U16, "u15": rt.U15, "u12": rt.U12}[args.storage]
+
+
 def _contract(metric, value, unit, args, ms_step, dtype, config, **extra):
     line = {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak",
@@ -215,7 +220,7 @@ def bench_precision(args):
     err_views = [0, 3]
     ref_u16 = {}
     results = {}
-    for name, storage, brick, elem_bytes in [("u16", rt.U16, 0, 2), ("f16", rt.F16, 0, 2),
+    for name, storage, brick, elem_bytes in [("u16", rt.U16, 0, 2), ("u12", rt.U12, 0, 2), ("f16", rt.F16, 0, 2),
                                              ("u8_brick16", rt.U8_BRICKSCALED, 16, 1)]:
         vol = rt.Volume(vol_np, vs.spacing, storage=storage, brick=brick)
         outs = [torch.empty((size, size, 4), dtype=torch.float32, device="cuda") for _ in range(n_views)]
@@ -224,7 +229,7 @@ def bench_precision(args):
         samples = _count(rt, jobs)
         ms = _timed(lambda: plan.launch(jobs), args.steps, args.warmup)
         algo = samples * 8 * elem_bytes + n_views * size * size * 16
-        if name == "u16":
+        if name in ("u16", "u12"):  # both hold the 12-bit grid exactly
             ofield = oracle.Volume(vol_np, vs.spacing)
         elif name == "f16":
             ofield = oracle.Volume(vol_np.astype(np.float16).astype(np.float64), vs.spacing)
@@ -259,7 +264,7 @@ def bench_precision(args):
                      results["u16"]["ms_per_launch"], "f32",
                      {"workload": "brain-precision-8x1024x1024-step0.25", "volume": list(vs.dims),
                       "views": n_views, "image": [size, size], "step_vox": step, "alpha_cutoff": cutoff,
-                      "tf_entries": ts.K, "storage": ["u16", "f16", "u8_brick16"], "launch": "graph"},
+                      "tf_entries": ts.K, "storage": ["u16", "u12", "f16", "u8_brick16"], "launch": "graph"},
                      by_storage=results)
     print(json.dumps(line), flush=True)
 
@@ -282,11 +287,12 @@ def bench_projection(args):
     vol_np = W.phantom_brain(vs.seed, dims=vs.dims, spacing=vs.spacing)
     cams = W.orbit_cameras(vs.dims, vs.spacing, n_views)
     torch.cuda.set_device(0)
-    vol = rt.Volume(vol_np, vs.spacing, storage=rt.U16)
+    st = _storage(rt, args)
+    vol = rt.Volume(vol_np, vs.spacing, storage=st)
     tf_np = W.random_tf(ts.K, ts.seed, alpha_max=ts.alpha_max)
     results = {}
-    plan = rt.BatchPlan(n_views, rt.U16)
-    plan_s = rt.BatchPlan(n_views, rt.U16, skip_empty=True)
+    plan = rt.BatchPlan(n_views, st)
+    plan_s = rt.BatchPlan(n_views, st, skip_empty=True)
     for name, fn, top, lo, hi, skip in [("composite", rt.COMPOSITE, ts.vmax, 0.0, 0.0, False),
                                         ("mip", rt.MIP, ts.vmax, 0.0, 0.0, False),
                                         ("xray", rt.XRAY, ts.vmax * 150.0, 0.0, 0.0, False),
@@ -310,6 +316,7 @@ def bench_projection(args):
     line = _contract("ray samples/sec (G/s) + fps per ray function at 512x512 over 256x256x160",
                      results["mip"]["gsamples_per_s"], "Gsamples/s", args, results["mip"]["ms_per_launch"], "f32",
                      {"workload": "brain-ray-functions-36x512x512-u16", "volume": list(vs.dims), "views": n_views,
+                      "storage": args.storage,
                       "image": [width, height], "step_vox": step, "tf_entries": ts.K,
                       "ray_functions": list(results), "launch": "graph"},
                      by_ray_function=results)
@@ -331,19 +338,19 @@ def bench_batch(args):
     vols, tfs = [], []
     for i, sp in enumerate(specs):
         v = W.phantom_brain(sp.seed, dims=sp.dims, spacing=sp.spacing)
-        vols.append(rt.Volume(v, sp.spacing, storage=rt.U16))
+        vols.append(rt.Volume(v, sp.spacing, storage=_storage(rt, args)))
         tfs.append(rt.TransferFunction(W.random_tf(4096, 1000 + i, alpha_max=0.05), 0.0, 4095.0))
         print(f"volume {i} {sp.dims} ready", file=sys.stderr, flush=True)
     gen_s = time.perf_counter() - t0
     jobs = [rt.Job(vols[vi], tfs[vi], cam, side, side, 0.5, 0.99) for vi, cam, side in views]
-    plan = rt.BatchPlan(len(jobs), rt.U16)
+    plan = rt.BatchPlan(len(jobs), _storage(rt, args))
     samples = _count(rt, jobs)
 
     plain = _plain_caller(rt, jobs)
     ms_graph = _timed(lambda: plan.launch(jobs), args.steps, args.warmup)
     ms_plain = _timed(plain, args.steps, args.warmup)
     # the same batch with exact empty-space skipping (same images, fewer samples gathered)
-    plan_s = rt.BatchPlan(len(jobs), rt.U16, skip_empty=True)
+    plan_s = rt.BatchPlan(len(jobs), _storage(rt, args), skip_empty=True)
     jobs_s = [rt.Job(vols[vi], tfs[vi], cam, side, side, 0.5, 0.99, skip_empty=True) for vi, cam, side in views]
     ms_skip = _timed(lambda: plan_s.launch(jobs_s), args.steps, args.warmup)
     torch.cuda.synchronize()
@@ -354,6 +361,7 @@ def bench_batch(args):
     line = _contract("ray samples/sec (G/s): 128 views of 32 uneven u16 volumes, one persistent graph launch vs "
                      "128 plain launches", round(g, 3), "Gsamples/s", args, ms_graph, "f32",
                      {"workload": "uneven-batch-32vol-128views-u16", "volumes": len(specs), "views": len(jobs),
+                      "storage": args.storage,
                       "sizes": sorted({s.dims for s in specs}), "image_sides": [min(j.width for j in jobs),
                                                                               max(j.width for j in jobs)],
                       "step_vox": 0.5, "alpha_cutoff": 0.99, "tf_entries": 4096, "launch": "graph"},
@@ -386,7 +394,7 @@ def bench_serve(args):
     torch.cuda.set_device(0)
     sp = (0.9, 0.9, 1.2)
     dims = [d for d in W.BATCH_SIZES for _ in range(4)]
-    ex = GpuExecutor(n_streams=3, max_batch=64)          # exact empty-space skipping on
+    ex = GpuExecutor(n_streams=3, max_batch=64, storage=_storage(rt, args))  # exact empty-space skipping on
     for i, d in enumerate(dims):
         ex.add_volume(i, W.phantom_brain(200 + i, dims=d, spacing=sp), sp)
         print(f"volume {i} {d} resident", file=sys.stderr, flush=True)
@@ -466,6 +474,7 @@ def bench_serve(args):
     line = _contract("p50/p99 render latency (ms), Poisson 200 req/s over 16 resident u16 volumes, continuous "
                      "batching", loose["p99_ms"], "ms", args, loose["mean_ms"], "f32",
                      {"workload": "serve-poisson200-16vol-u16", "volumes": len(dims), "sizes": W.BATCH_SIZES,
+                      "storage": args.storage,
                       "requests": n_req, "warmup_requests": warm, "image_sides": [256, 1024], "streams": 3,
                       "max_batch": 64, "step_vox": 0.5, "alpha_cutoff": 0.99, "tf_entries": 4096,
                       "skip_empty": True},
@@ -504,9 +513,10 @@ def main():
     ap.add_argument("--layout", choices=["cells", "poly", "linear"], default="cells",
                     help="device layout of the orbit volume")
     ap.add_argument("--storage", choices=["u16", "u15", "u12"], default="u12",
-                    help="orbit: device storage of the 12-bit uint16 phantom, all exact for it (u15: x-pairs as "
+                    help="device storage of the 12-bit uint16 phantoms, all exact for them (u15: x-pairs as "
                          "differences, images bit-identical to u16; u12: halves of value-2048, images equal to "
-                         "u16 within binary32 rounding); the images are compared with u16 storage in the run")
+                         "u16 within binary32 rounding); the orbit compares its images with u16 storage in the "
+                         "run; the precision workload always measures its own list")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -544,7 +554,7 @@ def main():
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
     layout = {"cells": rt.LAYOUT_CELLS, "poly": rt.LAYOUT_POLY, "linear": rt.LAYOUT_LINEAR}[args.layout]
-    storage = {"u16": rt.U16, "u15": rt.U15, "u12": rt.U12}[args.storage]
+    storage = _storage(rt, args)
     if storage != rt.U16 and layout != rt.LAYOUT_CELLS:
         raise SystemExit(args.storage + " storage exists in the cell layout only")
     vol = rt.Volume(vol_np, vs.spacing, storage=storage, layout=layout)
