@@ -394,7 +394,8 @@ def bench_serve(args):
     torch.cuda.set_device(0)
     sp = (0.9, 0.9, 1.2)
     dims = [d for d in W.BATCH_SIZES for _ in range(4)]
-    ex = GpuExecutor(n_streams=3, max_batch=64, storage=_storage(rt, args))  # exact empty-space skipping on
+    ex = GpuExecutor(n_streams=3, max_batch=64, storage=_storage(rt, args),  # exact empty-space skipping on
+                     tile_order=args.tile_order or 2)
     for i, d in enumerate(dims):
         ex.add_volume(i, W.phantom_brain(200 + i, dims=d, spacing=sp), sp)
         print(f"volume {i} {d} resident", file=sys.stderr, flush=True)
@@ -474,7 +475,7 @@ def bench_serve(args):
     line = _contract("p50/p99 render latency (ms), Poisson 200 req/s over 16 resident u16 volumes, continuous "
                      "batching", loose["p99_ms"], "ms", args, loose["mean_ms"], "f32",
                      {"workload": "serve-poisson200-16vol-u16", "volumes": len(dims), "sizes": W.BATCH_SIZES,
-                      "storage": args.storage,
+                      "storage": args.storage, "tile_order": args.tile_order or 2,
                       "requests": n_req, "warmup_requests": warm, "image_sides": [256, 1024], "streams": 3,
                       "max_batch": 64, "step_vox": 0.5, "alpha_cutoff": 0.99, "tf_entries": 4096,
                       "skip_empty": True},
@@ -510,6 +511,8 @@ def main():
                          "volumes x 4 views in one launch vs 128 launches; serve: Poisson request stream; "
                          "projection: the orbit under every ray function (projections, thresholding, "
                          "iso-surface)")
+    ap.add_argument("--tile-order", type=int, choices=[0, 1, 2], default=0,
+                    help="serve: tile order of the executor's plans (0 = its default, spread; 1 compact; 2 spread)")
     ap.add_argument("--layout", choices=["cells", "poly", "linear"], default="cells",
                     help="device layout of the orbit volume")
     ap.add_argument("--storage", choices=["u16", "u15", "u12"], default="u12",

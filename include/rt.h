@@ -153,6 +153,14 @@ typedef struct {
     int tile_w, tile_h;                 /* ray tile of one wavefront, tile_w*tile_h == 64; 0 = 8x8 */
     int waves_per_block;                /* wavefronts per workgroup, 1..16; 0 = default */
     int skip_empty;                     /* compositing: nonzero leaps over empty space (see below) */
+    int tile_order;                     /* 1: a workgroup renders a compact block of tiles (cache
+                                         * locality across the rays of a block: the better order when
+                                         * many views share the GPU); 2: its wavefronts take tiles
+                                         * spread over the view (tile = block + blocks * wavefront), so
+                                         * the long rays of the middle of an image share a SIMD with
+                                         * short ones (lower latency when one view has the GPU to
+                                         * itself); 0: 2 for rt_render, 1 for batches and plans.
+                                         * Images are identical in every order. */
 } rt_render_opts;
 
 /* Empty-space skipping (compositing only).  Each volume keeps, per skip brick

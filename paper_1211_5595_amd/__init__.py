@@ -68,7 +68,7 @@ class rt_camera(C.Structure):
 class rt_render_opts(C.Structure):
     _fields_ = [("sample_counter", C.c_void_p), ("pixel_counts", C.c_void_p), ("ray_function", C.c_int),
                 ("iso_value", C.c_float), ("iso_high", C.c_float), ("tile_w", C.c_int), ("tile_h", C.c_int),
-                ("waves_per_block", C.c_int), ("skip_empty", C.c_int)]
+                ("waves_per_block", C.c_int), ("skip_empty", C.c_int), ("tile_order", C.c_int)]
 
 
 class rt_render_job(C.Structure):
@@ -163,8 +163,9 @@ def make_camera(cam) -> rt_camera:
 
 
 def make_opts(sample_counter=None, pixel_counts=None, ray_function=COMPOSITE, iso_value=0.0, iso_high=0.0,
-              tile=(0, 0), waves_per_block=0, skip_empty=False) -> rt_render_opts:
+              tile=(0, 0), waves_per_block=0, skip_empty=False, tile_order=0) -> rt_render_opts:
     o = rt_render_opts()
+    o.tile_order = int(tile_order)
     o.skip_empty = 1 if skip_empty else 0
     o.sample_counter = sample_counter.data_ptr() if sample_counter is not None else None
     o.pixel_counts = pixel_counts.data_ptr() if pixel_counts is not None else None
@@ -360,13 +361,13 @@ class TransferFunction:
 def render(volume: Volume, tf: TransferFunction, camera, width: int, height: int, step_vox: float = 0.5,
            alpha_cutoff: float = 0.99, bg=(0.0, 0.0, 0.0, 0.0), out=None, pixel_counts=None, sample_counter=None,
            spacing=None, tile=(0, 0), waves_per_block=0, stream=None, ray_function=COMPOSITE, iso_value=0.0,
-           iso_high=0.0, skip_empty=False):
+           iso_high=0.0, skip_empty=False, tile_order=0):
     """Render one view; returns the float32 [H][W][4] device image."""
     torch = _torch()
     if out is None:
         out = torch.empty((height, width, 4), dtype=torch.float32, device=volume.buf.device)
     opts = make_opts(sample_counter, pixel_counts, ray_function, iso_value, iso_high, tile=tile,
-                     waves_per_block=waves_per_block, skip_empty=skip_empty)
+                     waves_per_block=waves_per_block, skip_empty=skip_empty, tile_order=tile_order)
     rt_render(volume.handle, volume.dims, spacing, tf.handle, camera, width, height, step_vox, alpha_cutoff, bg,
               out.data_ptr(), opts, stream)
     return out
@@ -415,7 +416,7 @@ _ws_cache = {}
 
 
 def render_batch(jobs: Sequence[Job], sample_counter=None, workspace=None, tile=(0, 0), waves_per_block=0,
-                 stream=None):
+                 stream=None, tile_order=0):
     """Render all jobs in one persistent launch (job table copied per call)."""
     n = len(jobs)
     dev = jobs[0].out.device
@@ -424,7 +425,7 @@ def render_batch(jobs: Sequence[Job], sample_counter=None, workspace=None, tile=
         workspace = _ws_cache.get(key)
         if workspace is None:
             workspace = _ws_cache[key] = _Workspace(n, dev)
-    opts = make_opts(None, None, COMPOSITE, tile=tile, waves_per_block=waves_per_block)
+    opts = make_opts(None, None, COMPOSITE, tile=tile, waves_per_block=waves_per_block, tile_order=tile_order)
     rt_render_batch([j.struct() for j in jobs], workspace.buf.data_ptr(), workspace.nbytes,
                     sample_counter.data_ptr() if sample_counter is not None else None, opts, stream)
     return [j.out for j in jobs]
@@ -434,11 +435,11 @@ class BatchPlan:
     """The persistent batched launch captured once in a HIP graph."""
 
     def __init__(self, max_jobs: int, storage: int, tile=(0, 0), waves_per_block=0, device="cuda",
-                 layout: int = LAYOUT_CELLS, skip_empty: bool = False):
+                 layout: int = LAYOUT_CELLS, skip_empty: bool = False, tile_order: int = 0):
         self.ws = _Workspace(max_jobs, device)
         self.handle = rt_batch_plan_create(max_jobs, storage, layout, self.ws.buf.data_ptr(), self.ws.nbytes,
                                            make_opts(tile=tile, waves_per_block=waves_per_block,
-                                                     skip_empty=skip_empty))
+                                                     skip_empty=skip_empty, tile_order=tile_order))
 
     def launch(self, jobs: Sequence[Job], sample_counter=None, stream=None):
         rt_batch_plan_launch(self.handle, [j.struct() for j in jobs],

@@ -893,9 +893,18 @@ __device__ __forceinline__ void render_block(const VD& V, const float4* __restri
                                              const uint32_t* __restrict__ s_mask, int blk, const LaunchShape& ls,
                                              int tw_shift, unsigned long long* __restrict__ counter) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int by = blk / V.blocks_x, bx = blk - by * V.blocks_x;
-    const int tx = bx * ls.bw + wave % ls.bw, ty = by * ls.bh + wave / ls.bw;
-    if (tx >= V.tiles_x || ty >= V.tiles_y) return;
+    int tx, ty;
+    if (ls.order == 0) {  // compact: the workgroup's tiles form a bw x bh block
+        const int by = blk / V.blocks_x, bx = blk - by * V.blocks_x;
+        tx = bx * ls.bw + wave % ls.bw;
+        ty = by * ls.bh + wave / ls.bw;
+        if (tx >= V.tiles_x || ty >= V.tiles_y) return;
+    } else {  // spread: tile blk + nblocks * wave in row-major tile order
+        const int t = blk + V.nblocks * wave;
+        if (t >= V.tiles_x * V.tiles_y) return;
+        ty = t / V.tiles_x;
+        tx = t - ty * V.tiles_x;
+    }
     const int i = tx * ls.tile_w + (lane & (ls.tile_w - 1)), j = ty * ls.tile_h + (lane >> tw_shift);
     const __amdgpu_buffer_rsrc_t rs = make_rsrc(V.vol.data, V.vol.data_bytes);
     const Corners cn = corners_of(LAYOUT == LAYOUT_BRICKS ? 1u : Elem<KIND>::bytes, V.vol.sy, V.vol.sz);

@@ -241,7 +241,9 @@ void cross(const double a[3], const double b[3], double c[3]) {
 }
 double norm(const double a[3]) { return std::sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]); }
 
-rt_status make_shape(const rt_render_opts* opts, LaunchShape& ls) {
+// single_view: the launch renders one view alone (rt_render), which decides
+// the default tile order.
+rt_status make_shape(const rt_render_opts* opts, bool single_view, LaunchShape& ls) {
     int tw = 8, th = 8, waves = 16;
     if (opts) {
         if (opts->tile_w || opts->tile_h) {
@@ -249,7 +251,11 @@ rt_status make_shape(const rt_render_opts* opts, LaunchShape& ls) {
             th = opts->tile_h;
         }
         if (opts->waves_per_block) waves = opts->waves_per_block;
+        if (opts->tile_order < 0 || opts->tile_order > 2)
+            return fail(RT_ERR_INVALID_ARG, "tile_order must be 0, 1 or 2");
     }
+    const int order = opts ? opts->tile_order : 0;
+    ls.order = order == 2 || (order == 0 && single_view) ? 1 : 0;  // 1 = spread
     if (tw <= 0 || th <= 0 || tw * th != 64 || (tw & (tw - 1)))
         return fail(RT_ERR_UNSUPPORTED, "tile must be tile_w x tile_h = 64 with tile_w a power of two");
     if (waves != 1 && waves != 2 && waves != 4 && waves != 8 && waves != 16)
@@ -618,7 +624,7 @@ rt_status rt_render(const rt_volume* volume, const int64_t dims[3], const double
                     const float bg_rgba[4], float* out_dev, const rt_render_opts* opts, void* stream) {
     if (!dims) return fail(RT_ERR_INVALID_ARG, "dims is NULL");
     LaunchShape ls;
-    rt_status st = make_shape(opts, ls);
+    rt_status st = make_shape(opts, true, ls);
     if (st != RT_OK) return st;
     ViewDesc v;
     st = make_view(volume, dims, spacing, tf, camera, width, height, step_vox, alpha_cutoff, bg_rgba, out_dev,
@@ -642,7 +648,7 @@ rt_status rt_render_batch(const rt_render_job* jobs, int n, void* workspace, siz
     if (!workspace) return fail(RT_ERR_INVALID_ARG, "workspace is NULL");
     if (((uintptr_t)workspace & 255) != 0) return fail(RT_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
     LaunchShape ls;
-    rt_status st = make_shape(opts, ls);
+    rt_status st = make_shape(opts, false, ls);
     if (st != RT_OK) return st;
     std::vector<ViewDesc> descs;
     std::vector<int> prefix;
@@ -680,7 +686,7 @@ rt_status rt_batch_plan_create(int max_jobs, int storage, int layout, void* work
     if (storage < RT_U8 || storage > RT_U12) return fail(RT_ERR_INVALID_ARG, "unknown storage type");
     if (!layout_allowed(storage, layout)) return fail(RT_ERR_INVALID_ARG, "layout not available for this storage type");
     LaunchShape ls;
-    rt_status st = make_shape(opts, ls);
+    rt_status st = make_shape(opts, false, ls);
     if (st != RT_OK) return st;
     rt_batch_plan* p = new (std::nothrow) rt_batch_plan;
     if (!p) return fail(RT_ERR_OUT_OF_MEMORY, "host allocation failed");

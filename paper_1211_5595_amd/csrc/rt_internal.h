@@ -111,6 +111,7 @@ struct LaunchShape {
     int tile_w, tile_h;   // tile_w * tile_h == 64
     int waves;            // waves per workgroup
     int bw, bh;           // workgroup block in tiles: bw * bh == waves
+    int order;            // 0: compact blocks; 1: tiles spread over the view (resolved from the options)
 };
 
 // Workspace layout of a batched launch (device memory owned by the caller).

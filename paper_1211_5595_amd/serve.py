@@ -114,6 +114,7 @@ class Server:
         self.batches = 0
         self._thread: Optional[threading.Thread] = None
         self._stop = threading.Event()
+        self._wake = threading.Condition(self._lock)  # signalled by submit() and stop()
 
     # ---- requests -------------------------------------------------------
     def submit(self, req: RenderRequest) -> RenderFuture:
@@ -129,6 +130,7 @@ class Server:
             return fut
         with self._lock:
             self._queue.append(fut)
+            self._wake.notify()
         return fut
 
     def pending(self) -> int:
@@ -206,14 +208,29 @@ class Server:
         return bool(done)
 
     # ---- background loop ------------------------------------------------
-    def start(self, idle_sleep: float = 20e-6):
+    def _idle(self, max_wait: float):
+        """Nothing to do this tick.  With batches on the GPU, only yield (their
+        completion is polled, and a timed sleep would add its granularity,
+        tens of microseconds, to every request); otherwise block until a
+        submission or stop() wakes the loop (or max_wait passes)."""
+        with self._lock:
+            if self._inflight:
+                busy = True
+            else:
+                busy = False
+                if not self._queue and not self._stop.is_set():
+                    self._wake.wait(max_wait)
+        if busy:
+            time.sleep(0)
+
+    def start(self, idle_wait: float = 1e-3):
         def loop():
             while not self._stop.is_set():
                 if not self.run_once():
-                    time.sleep(idle_sleep)
+                    self._idle(idle_wait)
             while self.pending():
                 if not self.run_once():
-                    time.sleep(idle_sleep)
+                    self._idle(idle_wait)
         self._stop.clear()
         self._thread = threading.Thread(target=loop, daemon=True)
         self._thread.start()
@@ -226,7 +243,9 @@ class Server:
                 for f in self._queue:
                     f._finish(None, self.clock(), RuntimeError("server stopped"))
                 self._queue.clear()
-        self._stop.set()
+        with self._lock:
+            self._stop.set()
+            self._wake.notify()
         self._thread.join()
         self._thread = None
 
@@ -249,10 +268,11 @@ class GpuExecutor:
     """Runs batches through the C ABI: resident volumes, one batch plan
     (captured persistent launch) and one table pool per stream.  Compositing
     requests use exact empty-space skipping unless skip_empty is False (the
-    images are the same either way)."""
+    images are the same either way).  tile_order is the plans' tile order
+    (2, spread, by default: batches here are small and latency-bound)."""
 
     def __init__(self, n_streams: int = 3, max_batch: int = 64, storage: Optional[int] = None, device="cuda",
-                 skip_empty: bool = True):
+                 skip_empty: bool = True, tile_order: int = 2):
         import torch
 
         from . import BatchPlan, Job, TransferFunction, U16, LAYOUT_CELLS
@@ -264,9 +284,13 @@ class GpuExecutor:
         self._resident = 0
         self.streams = [torch.cuda.Stream(device=device) for _ in range(n_streams)]
         self.skip_empty = bool(skip_empty)
-        self.plans = [BatchPlan(max_batch, self.storage, layout=LAYOUT_CELLS, device=device, skip_empty=self.skip_empty)
-                      for _ in range(n_streams)]
+        self.plans = [BatchPlan(max_batch, self.storage, layout=LAYOUT_CELLS, device=device, skip_empty=self.skip_empty,
+                                tile_order=tile_order) for _ in range(n_streams)]
+        # cumulative sample counters, copied to pinned host memory behind each
+        # batch, so retiring a batch reads its count without a device round trip
         self.counters = [torch.zeros(1, dtype=torch.int64, device=device) for _ in range(n_streams)]
+        self.host_counts = torch.zeros(n_streams, dtype=torch.int64, pin_memory=True)
+        self._last_count = [0] * n_streams
         self.tf_pools: List[Dict[int, List[Any]]] = [collections.defaultdict(list) for _ in range(n_streams)]
         self.busy = [None] * n_streams
         self.max_batch = max_batch
@@ -316,8 +340,8 @@ class GpuExecutor:
                 out = torch.empty((r.height, r.width, 4), dtype=torch.float32, device=self.device)
                 jobs.append(self._Job(self.volumes[r.volume_id], tf, r.camera, r.width, r.height, r.step_vox,
                                       r.alpha_cutoff, r.bg, out=out, skip_empty=self.skip_empty))
-            self.counters[k].zero_()
             self.plans[k].launch(jobs, sample_counter=self.counters[k], stream=s)
+            self.host_counts[k:k + 1].copy_(self.counters[k], non_blocking=True)
             ev = torch.cuda.Event()
             ev.record(s)
         self.busy[k] = (ev, jobs)
@@ -330,8 +354,8 @@ class GpuExecutor:
         ev, jobs = self.busy[token]
         ev.synchronize()
         self.busy[token] = None
-        with self.torch.cuda.stream(self.streams[token]):
-            n = int(self.counters[token].item())
+        total = int(self.host_counts[token])
+        n, self._last_count[token] = total - self._last_count[token], total
         # per-request counts are not tracked; the batch total is attributed evenly for statistics
         per = [n // len(jobs)] * len(jobs)
         return [j.out for j in jobs], per

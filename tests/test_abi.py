@@ -146,6 +146,16 @@ def test_null_arguments_are_reported_not_fatal(rt):
     assert L.rt_version().startswith(b"rtvol")
 
 
+def test_launch_options_are_checked_before_any_device_work(rt):
+    """Tile shape, wavefronts per block and tile order are validated first."""
+    L = rt.lib()
+    dims = (C.c_int64 * 3)(4, 4, 4)
+    for kw, code in ((dict(tile_order=3), 1), (dict(tile_order=-1), 1), (dict(tile=(3, 21)), 4),
+                     (dict(tile=(16, 8)), 4), (dict(waves_per_block=3), 4)):
+        o = rt.make_opts(**kw)
+        assert L.rt_render(None, dims, None, None, None, 8, 8, 0.5, 0.99, None, None, C.byref(o), None) == code, kw
+
+
 def test_product_path_does_not_import_oracle():
     """The product package never imports the oracle nor the generators."""
     pkg = os.path.join(ROOT, "paper_1211_5595_amd")

@@ -533,6 +533,33 @@ def test_u15_every_ray_function_bitwise_equal_u16(rt, torch_mod, brain, small):
     assert torch.equal(a, b)
 
 
+def test_tile_orders_give_identical_images(rt, torch_mod, brain):
+    """Compact and spread tile orders (and the default of each entry point)
+    only change which workgroup renders a tile: images and counts are equal."""
+    torch = torch_mod
+    cams = brain["cams"][::7]
+    for tile, wv in (((4, 16), 16), ((8, 8), 4), ((2, 32), 8)):
+        for skip in (False, True):
+            base = [gpu_render(rt, torch, brain["gv"], brain["gtf"], c, 200, 150, 0.5, 0.99, tile=tile,
+                               waves_per_block=wv, tile_order=1, skip_empty=skip) for c in cams]
+            for order in (0, 2):
+                for c, (img, cnt) in zip(cams, base):
+                    got = gpu_render(rt, torch, brain["gv"], brain["gtf"], c, 200, 150, 0.5, 0.99, tile=tile,
+                                     waves_per_block=wv, tile_order=order, skip_empty=skip)
+                    assert np.array_equal(got[0], img) and np.array_equal(got[1], cnt)
+            for order in (0, 1, 2):
+                outs = rt.render_batch([rt.Job(brain["gv"], brain["gtf"], c, 200, 150, 0.5, 0.99, skip_empty=skip)
+                                        for c in cams], tile=tile, waves_per_block=wv, tile_order=order)
+                plan = rt.BatchPlan(len(cams), rt.U16, tile=tile, waves_per_block=wv, tile_order=order,
+                                    skip_empty=skip)
+                pj = [rt.Job(brain["gv"], brain["gtf"], c, 200, 150, 0.5, 0.99, skip_empty=skip) for c in cams]
+                plan.launch(pj)
+                torch.cuda.synchronize()
+                for o, j, (img, _) in zip(outs, pj, base):
+                    assert np.array_equal(o.cpu().numpy().astype(np.float64), img)
+                    assert np.array_equal(j.out.cpu().numpy().astype(np.float64), img)
+
+
 def test_u12_brain_views_match_oracle(rt, torch_mod, orc, brain):
     """12-bit half cells hold the phantom exactly; full views against the
     oracle on the same grid, and against 16-bit storage to binary32 rounding."""
