@@ -24,6 +24,8 @@ __all__ = [
     "lib", "rt_volume_bytes", "rt_create_volume", "rt_destroy_volume", "rt_tf_bytes",
     "rt_set_transfer_function", "rt_destroy_tf", "rt_render", "rt_batch_workspace_bytes",
     "rt_render_batch", "rt_batch_plan_create", "rt_batch_plan_launch", "rt_batch_plan_destroy",
+    "rt_server_arena_bytes", "rt_server_create", "rt_server_submit", "rt_server_wait", "rt_server_release",
+    "rt_server_get_stats", "rt_server_destroy", "REQ_QUEUED", "REQ_RUNNING", "REQ_DONE", "REQ_FAILED",
     "Volume", "TransferFunction", "BatchPlan", "render", "render_batch", "Job",
 ]
 
@@ -79,6 +81,28 @@ class rt_render_job(C.Structure):
                 ("skip_empty", C.c_int)]
 
 
+class rt_request(C.Structure):
+    _fields_ = [("volume", C.c_void_p), ("tf_rgba", C.POINTER(C.c_float)), ("tf_entries", C.c_int),
+                ("tf_vmin", C.c_double), ("tf_vmax", C.c_double), ("camera", rt_camera), ("width", C.c_int),
+                ("height", C.c_int), ("step_vox", C.c_double), ("alpha_cutoff", C.c_double),
+                ("bg_rgba", C.c_float * 4), ("ray_function", C.c_int), ("iso_value", C.c_float),
+                ("iso_high", C.c_float)]
+
+
+class rt_request_info(C.Structure):
+    _fields_ = [("state", C.c_int), ("status", C.c_int), ("image_dev", C.c_void_p), ("t_submit", C.c_double),
+                ("t_launch", C.c_double), ("t_done", C.c_double), ("batch_size", C.c_int),
+                ("batch_samples", C.c_ulonglong)]
+
+
+class rt_server_stats(C.Structure):
+    _fields_ = [("submitted", C.c_ulonglong), ("completed", C.c_ulonglong), ("failed", C.c_ulonglong),
+                ("batches", C.c_ulonglong), ("pool_bytes", C.c_size_t), ("pool_in_use", C.c_size_t),
+                ("pool_peak", C.c_size_t), ("queued", C.c_int), ("running", C.c_int)]
+
+
+REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_FAILED = range(4)
+
 _lib = None
 
 
@@ -111,6 +135,14 @@ def lib():
                                      C.POINTER(vp)],
             "rt_batch_plan_launch": [vp, C.POINTER(rt_render_job), C.c_int, vp, vp],
             "rt_batch_plan_destroy": [vp],
+            "rt_server_arena_bytes": [C.c_int, C.c_int, C.c_size_t, szp],
+            "rt_server_create": [C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(rt_render_opts), vp, C.c_size_t,
+                                 C.c_size_t, C.POINTER(vp)],
+            "rt_server_submit": [vp, C.POINTER(rt_request), C.POINTER(C.c_uint64)],
+            "rt_server_wait": [vp, C.c_uint64, C.c_double, C.POINTER(rt_request_info)],
+            "rt_server_release": [vp, C.c_uint64],
+            "rt_server_get_stats": [vp, C.POINTER(rt_server_stats)],
+            "rt_server_destroy": [vp],
         }
         for name, argt in sigs.items():
             f = getattr(L, name)
@@ -259,6 +291,47 @@ def rt_batch_plan_launch(plan_h: int, jobs, counter_ptr: Optional[int] = None, s
 
 def rt_batch_plan_destroy(plan_h: int):
     _check(lib().rt_batch_plan_destroy(C.c_void_p(plan_h)), "rt_batch_plan_destroy")
+
+
+def rt_server_arena_bytes(n_streams: int, max_batch: int, image_pool_bytes: int) -> int:
+    b = C.c_size_t()
+    _check(lib().rt_server_arena_bytes(n_streams, max_batch, image_pool_bytes, C.byref(b)), "rt_server_arena_bytes")
+    return b.value
+
+
+def rt_server_create(n_streams: int, max_batch: int, storage: int, layout: int, opts, arena_ptr: int,
+                     arena_bytes: int, image_pool_bytes: int) -> int:
+    h = C.c_void_p()
+    _check(lib().rt_server_create(n_streams, max_batch, storage, layout, C.byref(opts) if opts is not None else None,
+                                  C.c_void_p(arena_ptr), arena_bytes, image_pool_bytes, C.byref(h)),
+           "rt_server_create")
+    return h.value
+
+
+def rt_server_submit(server_h: int, req: rt_request) -> int:
+    t = C.c_uint64()
+    _check(lib().rt_server_submit(C.c_void_p(server_h), C.byref(req), C.byref(t)), "rt_server_submit")
+    return t.value
+
+
+def rt_server_wait(server_h: int, ticket: int, timeout_s: float = -1.0) -> rt_request_info:
+    info = rt_request_info()
+    _check(lib().rt_server_wait(C.c_void_p(server_h), ticket, timeout_s, C.byref(info)), "rt_server_wait")
+    return info
+
+
+def rt_server_release(server_h: int, ticket: int):
+    _check(lib().rt_server_release(C.c_void_p(server_h), ticket), "rt_server_release")
+
+
+def rt_server_get_stats(server_h: int) -> rt_server_stats:
+    st = rt_server_stats()
+    _check(lib().rt_server_get_stats(C.c_void_p(server_h), C.byref(st)), "rt_server_get_stats")
+    return st
+
+
+def rt_server_destroy(server_h: int):
+    _check(lib().rt_server_destroy(C.c_void_p(server_h)), "rt_server_destroy")
 
 
 # ---------------------------------------------------------------------------

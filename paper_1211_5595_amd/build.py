@@ -17,7 +17,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD_DIR = os.path.join(ROOT, "_build")
 LIB_PATH = os.path.join(PKG, "librtvol.so")
-SOURCES = ["march.hip", "relayout.hip", "rt_api.cpp"]
+SOURCES = ["march.hip", "relayout.hip", "rt_api.cpp", "rt_serve.cpp"]
 ARCH = "gfx950"
 
 FLAGS = [

@@ -435,7 +435,49 @@ void write_batch_host(void* h, const std::vector<ViewDesc>& descs, const std::ve
 
 size_t batch_copy_bytes(int n) { return kBatchHeaderBytes + prefix_bytes() + (size_t)n * sizeof(ViewDesc); }
 
+int layout_code(int layout) {
+    return layout == RT_LAYOUT_LINEAR   ? LAYOUT_LINEAR
+           : layout == RT_LAYOUT_BRICKS ? LAYOUT_BRICKS
+           : layout == RT_LAYOUT_POLY   ? LAYOUT_POLY
+                                        : LAYOUT_CELLS;
+}
+
 }  // namespace
+
+namespace rtv {
+
+int storage_layout_kind(int storage, int layout) {
+    if (storage < RT_U8 || storage > RT_U12 || !layout_allowed(storage, layout)) return -1;
+    return (storage == RT_U8_BRICKSCALED ? ST_U8B : storage) * 4 + layout_code(layout);
+}
+
+int volume_kind(const rt_volume* vol) { return vol ? vol->dev.kind * 4 + vol->dev.layout : -1; }
+
+int set_last_error(int status, const char* msg) { return fail(static_cast<rt_status>(status), msg); }
+
+int check_request(const rt_volume* vol, int K, double vmin, double vmax, const void* camera, int W, int H,
+                  double step_vox, double cutoff, const float* bg, const float* out, int ray_function,
+                  float iso_value, float iso_high, int* kind) {
+    if (K < 2 || K > kMaxK) return fail(RT_ERR_INVALID_ARG, "K must be in [2, 4096]");
+    if (!std::isfinite(vmin) || !std::isfinite(vmax) || !(vmax > vmin)) return fail(RT_ERR_INVALID_ARG, "need vmin < vmax");
+    rt_tf probe;  // geometry and table size only: never read on the device
+    std::memset(&probe, 0, sizeof(probe));
+    probe.dev = reinterpret_cast<const float4*>((uintptr_t)256);
+    probe.K = K;
+    probe.vmin = vmin;
+    probe.vmax = vmax;
+    LaunchShape ls;
+    rt_status st = make_shape(nullptr, false, ls);
+    if (st != RT_OK) return st;
+    ViewDesc v;
+    st = make_view(vol, nullptr, nullptr, &probe, static_cast<const rt_camera*>(camera), W, H, step_vox, cutoff, bg,
+                   const_cast<float*>(out), nullptr, ls, ray_function, iso_value, iso_high, 0, v);
+    if (st != RT_OK) return st;
+    if (kind) *kind = volume_kind(vol);
+    return RT_OK;
+}
+
+}  // namespace rtv
 
 extern "C" {
 
@@ -692,11 +734,7 @@ rt_status rt_batch_plan_create(int max_jobs, int storage, int layout, void* work
     if (!p) return fail(RT_ERR_OUT_OF_MEMORY, "host allocation failed");
     std::memset(p, 0, sizeof(*p));
     p->max_jobs = max_jobs;
-    p->kind = (storage == RT_U8_BRICKSCALED ? ST_U8B : storage) * 4 +
-              (layout == RT_LAYOUT_LINEAR   ? LAYOUT_LINEAR
-               : layout == RT_LAYOUT_BRICKS ? LAYOUT_BRICKS
-               : layout == RT_LAYOUT_POLY   ? LAYOUT_POLY
-                                            : LAYOUT_CELLS);
+    p->kind = storage_layout_kind(storage, layout);
     p->ls = ls;
     p->grid = batch_persistent_grid(ls, kMaxK);
     p->ws = workspace;

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+struct rt_volume;
+
 namespace rtv {
 
 // A float-float number: value = hi + lo with |lo| <= ulp(hi)/2.  Used for the
@@ -156,5 +158,18 @@ hipError_t launch_relayout_u8b(const void* src, int src_kind, const int32_t n[3]
 hipError_t launch_relayout_u8b_cells(const void* src, int src_kind, const int32_t n[3], int B, const int32_t nb[3],
                                      float2* brick_par, const int32_t ncb[3], float2* block_par,
                                      unsigned char* codes, hipStream_t s);
+
+// Host-side helpers of rt_api.cpp used by the serving runtime (rt_serve.cpp).
+// storage_layout_kind: the storage-type-and-layout code of a batch plan, -1
+// when the pair does not exist.  check_request: the validation rt_render and
+// the batch calls apply to one view, run without any device work (the table is
+// given by its size and value window only); *kind receives the volume's code.
+int storage_layout_kind(int storage, int layout);
+int volume_kind(const rt_volume* vol);
+// Record msg as the calling thread's rt_last_error(); returns status.
+int set_last_error(int status, const char* msg);
+int check_request(const rt_volume* vol, int K, double vmin, double vmax, const void* camera, int W, int H,
+                  double step_vox, double cutoff, const float* bg, const float* out, int ray_function,
+                  float iso_value, float iso_high, int* kind);
 
 }  // namespace rtv

@@ -21,6 +21,7 @@ with a scripted executor and a fake clock).
 from __future__ import annotations
 
 import collections
+import ctypes
 import dataclasses
 import threading
 import time
@@ -52,6 +53,9 @@ class RenderRequest:
     alpha_cutoff: float = 0.99
     bg: Sequence[float] = (0.0, 0.0, 0.0, 0.0)
     deadline: Optional[float] = None   # absolute time on the server clock; None = wait forever
+    ray_function: int = 0              # rt_ray_function (compositing by default)
+    iso_value: float = 0.0             # iso-value, or the low end of a threshold window
+    iso_high: float = 0.0              # high end of a threshold window
 
 
 class RenderFuture:
@@ -339,7 +343,8 @@ class GpuExecutor:
                     lst.append(tf)
                 out = torch.empty((r.height, r.width, 4), dtype=torch.float32, device=self.device)
                 jobs.append(self._Job(self.volumes[r.volume_id], tf, r.camera, r.width, r.height, r.step_vox,
-                                      r.alpha_cutoff, r.bg, out=out, skip_empty=self.skip_empty))
+                                      r.alpha_cutoff, r.bg, out=out, skip_empty=self.skip_empty,
+                                      ray_function=r.ray_function, iso_value=r.iso_value, iso_high=r.iso_high))
             self.plans[k].launch(jobs, sample_counter=self.counters[k], stream=s)
             self.host_counts[k:k + 1].copy_(self.counters[k], non_blocking=True)
             ev = torch.cuda.Event()
@@ -359,3 +364,115 @@ class GpuExecutor:
         # per-request counts are not tracked; the batch total is attributed evenly for statistics
         per = [n // len(jobs)] * len(jobs)
         return [j.out for j in jobs], per
+
+
+class NativeServer:
+    """The library's own serving runtime (rt_serve.h): admission against an
+    image pool, continuous batching onto n_streams streams and the request
+    loop all run in a native server thread; Python only marshals requests.
+
+    image_pool_bytes is the admission budget: a request holds its image
+    (W*H*16 bytes) in the pool from admission until it is released (result()
+    copies the image out and releases it).  The arena (workspaces, table slots
+    and the pool) is one device allocation made here and owned by this object.
+    """
+
+    def __init__(self, image_pool_bytes: int, n_streams: int = 3, max_batch: int = 64, storage: Optional[int] = None,
+                 skip_empty: bool = True, tile_order: int = 2, device="cuda"):
+        import torch
+
+        from . import (LAYOUT_CELLS, U16, make_opts, rt_server_arena_bytes, rt_server_create)
+        self.torch = torch
+        self.device = device
+        self.storage = U16 if storage is None else storage
+        nbytes = rt_server_arena_bytes(n_streams, max_batch, image_pool_bytes)
+        self.arena = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        self._base = (self.arena.data_ptr() + 255) // 256 * 256
+        self._shift = self._base - self.arena.data_ptr()
+        torch.cuda.synchronize(device)
+        self.handle = rt_server_create(n_streams, max_batch, self.storage, LAYOUT_CELLS,
+                                       make_opts(skip_empty=skip_empty, tile_order=tile_order), self._base, nbytes,
+                                       image_pool_bytes)
+        self.volumes: Dict[Any, Any] = {}
+        self._resident = 0
+
+    # volumes
+    def add_volume(self, vid, values, spacing):
+        from . import Volume
+        v = Volume(values, spacing, storage=self.storage, device=self.device)
+        self.torch.cuda.synchronize(self.device)
+        self.volumes[vid] = v
+        self._resident += v.nbytes
+        return v
+
+    def resident_bytes(self) -> int:
+        return self._resident
+
+    # requests
+    def submit(self, req: RenderRequest) -> int:
+        """Queue a request; returns its ticket.  Raises InvalidArgument for an
+        invalid request or unknown volume, OutOfMemory for an image larger
+        than the whole pool."""
+        from . import InvalidArgument, make_camera, rt_request, rt_server_submit
+        v = self.volumes.get(req.volume_id)
+        if v is None:
+            raise InvalidArgument(f"unknown volume {req.volume_id!r}")
+        t = np.ascontiguousarray(req.tf_rgba, dtype=np.float32)
+        r = rt_request()
+        r.volume = v.handle
+        r.tf_rgba = t.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+        r.tf_entries = int(t.shape[0])
+        r.tf_vmin, r.tf_vmax = float(req.vmin), float(req.vmax)
+        r.camera = make_camera(req.camera)
+        r.width, r.height = int(req.width), int(req.height)
+        r.step_vox, r.alpha_cutoff = float(req.step_vox), float(req.alpha_cutoff)
+        r.bg_rgba[:] = [float(c) for c in req.bg]
+        r.ray_function = int(getattr(req, "ray_function", 0))
+        r.iso_value = float(getattr(req, "iso_value", 0.0))
+        r.iso_high = float(getattr(req, "iso_high", 0.0))
+        return rt_server_submit(self.handle, r)
+
+    def wait(self, ticket: int, timeout: float = -1.0):
+        """The request's rt_request_info once it is DONE or FAILED (or when
+        timeout seconds have passed; negative = no limit)."""
+        from . import rt_server_wait
+        return rt_server_wait(self.handle, ticket, timeout)
+
+    def image(self, info, width: int, height: int):
+        """A view of a DONE request's image in the pool (valid until release)."""
+        off = info.image_dev - self._base + self._shift
+        return self.arena[off: off + width * height * 16].view(self.torch.float32).view(height, width, 4)
+
+    def result(self, ticket: int, width: int, height: int, timeout: float = -1.0):
+        """Wait, copy the image out of the pool and release the request."""
+        from . import REQ_DONE, RTError, rt_server_release
+        info = self.wait(ticket, timeout)
+        if info.state != REQ_DONE:
+            if info.state == 3:
+                rt_server_release(self.handle, ticket)
+                raise RTError(f"request failed with status {info.status}")
+            raise TimeoutError("render not finished")
+        img = self.image(info, width, height).clone()
+        self.torch.cuda.current_stream(self.device).synchronize()
+        rt_server_release(self.handle, ticket)
+        return img
+
+    def release(self, ticket: int):
+        from . import rt_server_release
+        rt_server_release(self.handle, ticket)
+
+    def stats(self):
+        from . import rt_server_get_stats
+        return rt_server_get_stats(self.handle)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            from . import rt_server_destroy
+            rt_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -165,3 +165,32 @@ def test_product_path_does_not_import_oracle():
                 src = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in src and "from oracle" not in src and "oracle.h" not in src, f
                 assert "import workloads" not in src and "from workloads" not in src, f
+
+
+def test_server_arena_and_argument_checks(rt):
+    """The serving runtime's sizes, and its argument checks, which run before
+    any device work."""
+    r = lambda x: (x + 255) // 256 * 256
+    lane = r(rt.rt_batch_workspace_bytes(64)) + 256 + 64 * r(rt.rt_tf_bytes(4096))
+    assert rt.rt_server_arena_bytes(3, 64, 1 << 20) == 3 * lane + (1 << 20)
+    assert rt.rt_server_arena_bytes(1, 1, 1000) == r(rt.rt_batch_workspace_bytes(1)) + 256 + r(rt.rt_tf_bytes(4096)) \
+        + 1024
+    for args in ((0, 4, 4096), (9, 4, 4096), (1, 0, 4096), (1, 257, 4096), (1, 4, 255)):
+        with pytest.raises(rt.InvalidArgument):
+            rt.rt_server_arena_bytes(*args)
+    L = rt.lib()
+    h = C.c_void_p()
+    need = rt.rt_server_arena_bytes(2, 8, 1 << 20)
+    cases = [((2, 8, 1, 0, None, None, need, 1 << 20), 1),        # NULL arena
+             ((2, 8, 1, 0, None, 4096 + 16, need, 1 << 20), 1),   # misaligned arena
+             ((2, 8, 1, 0, None, 4096, need - 1, 1 << 20), 2),    # arena too small
+             ((2, 8, 12, 0, None, 4096, need, 1 << 20), 1),       # unknown storage
+             ((2, 8, 6, 1, None, 4096, need, 1 << 20), 1),        # u12 exists in the cell layout only
+             ((0, 8, 1, 0, None, 4096, need, 1 << 20), 1)]        # no stream
+    for (ns, mb, st, lay, opts, arena, nbytes, pool), code in cases:
+        assert L.rt_server_create(ns, mb, st, lay, opts, C.c_void_p(arena), nbytes, pool, C.byref(h)) == code
+        assert h.value is None
+    bad = rt.make_opts(tile_order=5)
+    assert L.rt_server_create(2, 8, 1, 0, C.byref(bad), C.c_void_p(4096), need, 1 << 20, C.byref(h)) == 1
+    assert L.rt_server_submit(None, None, None) == 1 and L.rt_server_release(None, 1) == 1
+    assert L.rt_server_destroy(None) == 0
