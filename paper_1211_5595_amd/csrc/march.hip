@@ -402,6 +402,15 @@ struct Sampler<ST_U12, LAYOUT_CELLS> {
     }
 };
 
+// An empty use of the first word of a loaded cell: pins the load ahead of a
+// branch after which only one side needs it.
+template <class Raw>
+__device__ __forceinline__ void keep_issued(const Raw& w) {
+    uint32_t first;
+    __builtin_memcpy(&first, &w, sizeof(first));
+    asm volatile("" ::"v"(first));
+}
+
 // Samplers whose stored values are shifted (bias != 0) give the compositing
 // loop the shifted value, with the shift folded into the table mapping.
 template <class...>
@@ -640,7 +649,7 @@ __device__ __forceinline__ bool in_window(float val, const VD& V) {
 // WINDOW: thresholding -- samples whose value lies outside [iso_lo, iso_hi]
 // are transparent (their opacity is taken as 0).  COUNT: report the number of
 // samples taken (without it the loop keeps no per-ray copy of its counter).
-template <int KIND, int LAYOUT, bool SKIP, bool WINDOW, bool COUNT, class VD>
+template <int KIND, int LAYOUT, bool SKIP, bool WINDOW, bool COUNT, bool PREFETCH, class VD>
 __device__ __forceinline__ void march_pixel(const VD& V, const float4* __restrict__ s_tf,
                                             const uint32_t* __restrict__ s_mask, __amdgpu_buffer_rsrc_t rs,
                                             const Corners& cn, int i, int j, float4& px, int& count) {
@@ -661,7 +670,38 @@ __device__ __forceinline__ void march_pixel(const VD& V, const float4* __restric
             // sample is taken, so a run of leaps never waits on memory)
             int it = 0;
             bool stale = false;
-            for (;;) {
+            if constexpr (PREFETCH && !SKIP) {
+                // the next sample's cell is requested before this sample is
+                // processed, so a wavefront that has its SIMD to itself (a lone
+                // view leaves most SIMDs with few wavefronts) overlaps the load
+                // with the arithmetic; its use on the exit path keeps the
+                // compiler from moving the request behind the exit test.  It
+                // costs register copies per sample, so the batched kernel, whose
+                // many wavefronts hide the latency anyway, does not use it.
+                for (;;) {
+                    const long long Qn[3] = {R.Q[0] + R.dQ[0], R.Q[1] + R.dQ[1], R.Q[2] + R.dQ[2]};
+                    const typename S::Raw nxt = S::load(rs, V.vol, cn, Qn);
+                    const float val = stored_value<S>(cur, frac32(R.Q[0]), frac32(R.Q[1]), frac32(R.Q[2]));
+                    float4 c = classify(s_tf, val, ta, tb, Km1);
+                    if (WINDOW && !in_window(val + bias, V)) c.w = 0.0f;
+                    const float Ta = T * c.w;
+                    asm volatile("" ::"v"(Ta));  // formed before T is overwritten: no copy of T
+                    Cr = fmaf(Ta, c.x, Cr);
+                    Cg = fmaf(Ta, c.y, Cg);
+                    Cb = fmaf(Ta, c.z, Cb);
+                    T = fmaf(-T, c.w, T);
+                    ++k;
+                    if (k >= R.m || T <= thr) {
+                        keep_issued(nxt);
+                        break;
+                    }
+                    cur = nxt;
+                    R.Q[0] = Qn[0];
+                    R.Q[1] = Qn[1];
+                    R.Q[2] = Qn[2];
+                }
+            }
+            for (; !(PREFETCH && !SKIP);) {
                 if constexpr (SKIP) {
                     // all live rays of the wavefront in empty bricks: each leaps to
                     // its first sample outside its brick (or to the end of its ray)
@@ -888,7 +928,9 @@ __device__ __forceinline__ void iso_pixel(const VD& V, const float4* __restrict_
     px = make_float4(c.x * shade, c.y * shade, c.z * shade, 1.0f);
 }
 
-template <int KIND, int LAYOUT, bool SKIP, class VD>
+// PREFETCH: the compositing loop requests the next cell before processing the
+// current sample (the single-view kernel; see march_pixel).
+template <int KIND, int LAYOUT, bool SKIP, bool PREFETCH, class VD>
 __device__ __forceinline__ void render_block(const VD& V, const float4* __restrict__ s_tf,
                                              const uint32_t* __restrict__ s_mask, int blk, const LaunchShape& ls,
                                              int tw_shift, unsigned long long* __restrict__ counter) {
@@ -916,11 +958,11 @@ __device__ __forceinline__ void render_block(const VD& V, const float4* __restri
         const bool want_count = SKIP || V.counts != nullptr || counter != nullptr;
         if (fn == RT_FN_COMPOSITE) {
             if (want_count)
-                march_pixel<KIND, LAYOUT, SKIP, false, true, VD>(V, s_tf, s_mask, rs, cn, i, j, px, count);
+                march_pixel<KIND, LAYOUT, SKIP, false, true, PREFETCH, VD>(V, s_tf, s_mask, rs, cn, i, j, px, count);
             else
-                march_pixel<KIND, LAYOUT, SKIP, false, SKIP, VD>(V, s_tf, s_mask, rs, cn, i, j, px, count);
+                march_pixel<KIND, LAYOUT, SKIP, false, SKIP, PREFETCH, VD>(V, s_tf, s_mask, rs, cn, i, j, px, count);
         } else if (fn == RT_FN_THRESHOLD) {
-            march_pixel<KIND, LAYOUT, SKIP, true, true, VD>(V, s_tf, s_mask, rs, cn, i, j, px, count);
+            march_pixel<KIND, LAYOUT, SKIP, true, true, PREFETCH, VD>(V, s_tf, s_mask, rs, cn, i, j, px, count);
         }
         else if (fn == RT_FN_ISO)
             iso_pixel<KIND, LAYOUT, VD>(V, s_tf, rs, cn, i, j, px, count);
@@ -960,7 +1002,7 @@ __global__ void RT_MARCH_ATTRS march_plain_kernel(const ViewDesc V, const Launch
     load_tf(s_tf, V.tf, V.K);
     if (SKIP) build_skip_mask(s_mask, V);
     __syncthreads();
-    render_block<KIND, LAYOUT, SKIP, ViewDesc>(V, s_tf, s_mask, xcd_remap(blockIdx.x, gridDim.x), ls, tw_shift,
+    render_block<KIND, LAYOUT, SKIP, true, ViewDesc>(V, s_tf, s_mask, xcd_remap(blockIdx.x, gridDim.x), ls, tw_shift,
                                                counter);
 }
 
@@ -1021,7 +1063,7 @@ __global__ void RT_MARCH_ATTRS march_batch_kernel(char* __restrict__ ws, const L
             }
             __syncthreads();
         }
-        render_block<KIND, LAYOUT, SKIP, CViewDesc>(V, s_tf, s_mask, g - prefix[lo], ls, tw_shift, counter);
+        render_block<KIND, LAYOUT, SKIP, false, CViewDesc>(V, s_tf, s_mask, g - prefix[lo], ls, tw_shift, counter);
         __syncthreads();
     }
 }
