@@ -749,7 +749,11 @@ def main():
                      "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
                      "kernel": ("march_batch_kernel<" if best in ("batch", "graph", "skip") else "march_plain_kernel<")
                                + args.storage + ">",
-                     "algorithmic_bytes_per_launch": int(bytes_per_launch)},
+                     "algorithmic_bytes_per_launch": int(bytes_per_launch),
+                     # the caches serve two thirds of the logical gathers, so the
+                     # fraction can exceed 1; what binds is vector-instruction issue
+                     "limiter": "VALU issue (VALUBusy ~97 %, see profiles/march_batch_" + args.storage
+                                + "_brain_orbit.md)"},
     }
     # exact empty-space skipping over the same views: same images, same
     # composited-sample count, fewer samples gathered; reported beside the
