@@ -112,14 +112,31 @@ def cpu_baseline(vol_np, tf_np, cams, spacing, width, height, step, cutoff, vmax
         if time.perf_counter() - t0 > budget_s:
             break
     dt = time.perf_counter() - t0
+    # one core, on the first view alone
+    t1 = time.perf_counter()
+    r1 = oracle.render(V, T, cams[0], width, height, step, cutoff, nthreads=1)
+    dt1 = time.perf_counter() - t1
     return {"value": samples / dt / 1e9, "unit": "Gsamples/s", "cores": oracle.max_threads(), "kind": "oracle",
             "sample": f"{n_views} of the {len(cams)} orbit views, {width}x{height}, whole images",
-            "fps": n_views / dt, "seconds": dt}
+            "fps": n_views / dt, "seconds": dt, "cpu_model": _cpu_model(),
+            "single_core": {"value": int(r1.counts.sum()) / dt1 / 1e9, "unit": "Gsamples/s", "cores": 1,
+                            "sample": "orbit view 0, whole image", "seconds": dt1}}
 
 
-def probe_copy(gib: float = 1.0, reps: int = 10):
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def probe_copy(gib: float = 1.0, reps: int = 10, quiet: bool = False):
     """Plain device copy of a known size (for counter calibration and the
-    achievable-bandwidth figure)."""
+    achievable-bandwidth figure); returns the copy's read+write GB/s."""
     import torch
     n = int(gib * (1 << 30))
     a = torch.empty(n, dtype=torch.uint8, device="cuda")
@@ -133,8 +150,10 @@ def probe_copy(gib: float = 1.0, reps: int = 10):
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / reps
-    print(json.dumps({"probe": "copy", "bytes_read": n, "bytes_written": n, "ms": ms,
-                      "GB_per_s": 2 * n / ms / 1e6}))
+    if not quiet:
+        print(json.dumps({"probe": "copy", "bytes_read": n, "bytes_written": n, "ms": ms,
+                          "GB_per_s": 2 * n / ms / 1e6}))
+    return 2 * n / ms / 1e6
 
 
 def _timed(fn, steps, warmup):
@@ -634,11 +653,15 @@ def main():
         shape = dict(tile=(8, 8), waves_per_block=16)
     plan = rt.BatchPlan(n_views, storage, layout=layout, **shape)
 
-    # untimed counting pass
+    # untimed counting pass, with per-pixel counts for the samples per hitting ray
     counter = torch.zeros(1, dtype=torch.int64, device="cuda")
-    rt.render_batch(jobs, sample_counter=counter)
+    pix = [torch.zeros((height, width), dtype=torch.int32, device="cuda") for _ in cams]
+    rt.render_batch([rt.Job(vol, tf, cam, width, height, step, cutoff, out=o, pixel_counts=c)
+                     for cam, o, c in zip(cams, outs, pix)], sample_counter=counter)
     torch.cuda.synchronize()
     samples_per_step = int(counter.item())
+    hitting_rays = int(sum(int((c > 0).sum()) for c in pix))
+    del pix
     vs_u16 = None
     if storage != rt.U16:  # the same views from 16-bit storage of the same grid
         vol16 = rt.Volume(vol_np, vs.spacing, storage=rt.U16, layout=layout)
@@ -740,6 +763,8 @@ def main():
         "images_vs_u16_storage": vs_u16,
         "fps": round(fps, 1),
         "samples_per_step": samples_per_step,
+        "hitting_rays_per_step": hitting_rays,
+        "mean_samples_per_hitting_ray": round(samples_per_step / max(hitting_rays, 1), 1),
         "ms_per_step_by_form": {k: round(v, 4) for k, v in ms.items()},
         "gsamples_per_s_by_form": {k: round(samples_per_step / (v * 1e-3) / 1e9, 3) for k, v in ms.items()},
         "latency_ms": {"single_view_p50": percentile(lat, 50), "single_view_p99": percentile(lat, 99),
@@ -755,6 +780,8 @@ def main():
                      "limiter": "VALU issue (VALUBusy ~97 %, see profiles/march_batch_" + args.storage
                                 + "_brain_orbit.md)"},
     }
+    if line["roofline"] is not None and not args.only:  # what a plain device copy achieves on this GPU
+        line["roofline"]["achievable_copy_GBps"] = round(probe_copy(1.0, 10, quiet=True), 1)
     # exact empty-space skipping over the same views: same images, same
     # composited-sample count, fewer samples gathered; reported beside the
     # fixed-step figure, never as it

@@ -1,9 +1,10 @@
-"""Autotuner for the marcher's launch shape and a volume's layout.
+"""Autotuner for the marcher's launch shape and a volume's storage and layout.
 
 Tunables: the ray tile of one wavefront (8x8, 16x4, 4x16, 32x2 pixels), the
 wavefronts per workgroup (4, 8, 16) and, per volume at creation, the storage
 layout (cell-packed, polynomial cells for integer data, or linear; for 8-bit
-brick storage the brick edge 8, 16 or 32).  Tile shape and wavefronts never
+brick storage the brick edge 8, 16 or 32) or, for integer data, the storage
+type among the encodings that hold the grid exactly (tune_storage).  Tile shape and wavefronts never
 change a pixel; the cell-packed and linear layouts render the same image bit
 for bit, and the polynomial layout evaluates the same interpolant in another
 rounding order (within the same tolerance of the exact result), so the choice
@@ -120,6 +121,67 @@ def tune_launch(volume, tf, cameras, width: int, height: int, step_vox: float = 
                                                       reps))
     result = {"tile": list(best[0]), "waves_per_block": best[1], "ms": table[str(best)], "timings_ms": table,
               "key": key}
+    if cache is not None:
+        cache.put(key, result)
+    return result
+
+
+def exact_storages(values) -> List[Tuple[int, int]]:
+    """(storage, layout) pairs that hold an integer grid without loss: 8-bit
+    data as u8 (any integer layout) or u16; 16-bit data as u16, and also as
+    15-bit difference cells when its maximum is at most 32767 and as 12-bit
+    half cells when it is at most 4096 (both in the cell layout).  Float data
+    has no alternative to its own type here (empty list)."""
+    import numpy as np
+    from . import LAYOUT_CELLS, LAYOUT_LINEAR, LAYOUT_POLY, U8, U12, U15, U16
+    dt = np.asarray(values).dtype
+    if dt not in (np.uint8, np.uint16):
+        return []
+    vmax = int(np.asarray(values).max()) if np.asarray(values).size else 0
+    out = [(U16, LAYOUT_CELLS), (U16, LAYOUT_POLY), (U16, LAYOUT_LINEAR)]
+    if dt == np.uint8:
+        out = [(U8, LAYOUT_CELLS), (U8, LAYOUT_POLY), (U8, LAYOUT_LINEAR)] + out
+    if vmax <= 32767:
+        out.append((U15, LAYOUT_CELLS))
+    if vmax <= 4096:
+        out.append((U12, LAYOUT_CELLS))
+    return out
+
+
+def tune_storage(values, spacing, tf, cameras, width: int, height: int, step_vox: float = 0.5,
+                 alpha_cutoff: float = 0.99, reps: int = 3, cache: Optional[Cache] = None,
+                 force: bool = False) -> dict:
+    """Choose the device storage type and layout of an integer volume among the
+    exact encodings (exact_storages) by timing batched renders of
+    representative views.  Every candidate holds the same grid; u15 cells
+    render bit for bit as u16 cells, the polynomial layout and u12 cells
+    evaluate the same interpolant in another rounding order (within the same
+    tolerance of the exact result)."""
+    from . import Job, Volume, render_batch
+    import torch
+    import numpy as np
+    nz, ny, nx = values.shape
+    cands = exact_storages(values)
+    if not cands:
+        raise ValueError("tune_storage needs uint8 or uint16 data")
+    key = (f"{_gpu_arch()}|storage|d{np.asarray(values).dtype}|m{int(np.asarray(values).max()).bit_length()}"
+           f"|v{size_class(nx * ny * nz)}|i{size_class(width * height)}")
+    if cache is not None and not force:
+        hit = cache.get(key)
+        if hit is not None:
+            return hit
+
+    def measure(c):
+        vol = Volume(values, spacing, storage=c[0], layout=c[1])
+        outs = [torch.empty((height, width, 4), dtype=torch.float32, device=vol.buf.device) for _ in cameras]
+        jobs = [Job(vol, tf, cam, width, height, step_vox, alpha_cutoff, out=o) for cam, o in zip(cameras, outs)]
+        ms = _time_ms(lambda: render_batch(jobs), reps)
+        measure.bytes[str(c)] = vol.nbytes
+        return ms
+    measure.bytes = {}
+    best, table = pick_best(cands, measure)
+    result = {"storage": best[0], "layout": best[1], "ms": table[str(best)], "timings_ms": table,
+              "bytes": measure.bytes, "key": key}
     if cache is not None:
         cache.put(key, result)
     return result

@@ -47,3 +47,38 @@ def test_tuned_launch_is_bitwise_equal_and_not_slower(tmp_path):
     lay = at.tune_layout(W.phantom_brain(9, dims=(64, 64, 48), spacing=sp), sp, rt.U16, tf, cams[:2], 128, 128,
                          reps=1)
     assert lay["layout"] in (rt.LAYOUT_CELLS, rt.LAYOUT_POLY, rt.LAYOUT_LINEAR)
+
+
+def test_exact_storage_candidates():
+    """Only encodings that hold the grid exactly are offered."""
+    import paper_1211_5595_amd as rt
+    u12 = np.array([[[0, 4096]]], dtype=np.uint16)
+    u15 = np.array([[[0, 4097]]], dtype=np.uint16)
+    u16 = np.array([[[0, 32768]]], dtype=np.uint16)
+    c12, c15, c16 = at.exact_storages(u12), at.exact_storages(u15), at.exact_storages(u16)
+    assert (rt.U12, rt.LAYOUT_CELLS) in c12 and (rt.U15, rt.LAYOUT_CELLS) in c12
+    assert (rt.U12, rt.LAYOUT_CELLS) not in c15 and (rt.U15, rt.LAYOUT_CELLS) in c15
+    assert all(s == rt.U16 for s, _ in c16)
+    c8 = at.exact_storages(np.array([[[0, 255]]], dtype=np.uint8))
+    assert (rt.U8, rt.LAYOUT_CELLS) in c8 and (rt.U12, rt.LAYOUT_CELLS) in c8
+    assert at.exact_storages(np.zeros((2, 2, 2), np.float32)) == []
+
+
+@pytest.mark.gpu
+def test_tuned_storage_renders_the_same_grid(tmp_path):
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1211_5595_amd as rt
+    import workloads as W
+    dims, sp = (128, 112, 80), (0.9, 0.9, 1.2)
+    v = W.phantom_brain(21, dims=dims, spacing=sp)
+    tf = rt.TransferFunction(W.random_tf(4096, 6, alpha_max=0.05), 0, 4095)
+    cams = W.orbit_cameras(dims, sp, 4)
+    res = at.tune_storage(v, sp, tf, cams, 256, 256, reps=1, cache=at.Cache(str(tmp_path / "s.json")))
+    assert (res["storage"], res["layout"]) in at.exact_storages(v)
+    assert len(res["timings_ms"]) == len(at.exact_storages(v))
+    a = rt.render(rt.Volume(v, sp, storage=rt.U16), tf, cams[1], 256, 256)
+    b = rt.render(rt.Volume(v, sp, storage=res["storage"], layout=res["layout"]), tf, cams[1], 256, 256)
+    torch.cuda.synchronize()
+    assert float((a - b).abs().max()) < 1e-3      # same grid; early-termination ties aside, rounding-level
