@@ -60,7 +60,7 @@ class _TF(C.Structure):
 class _Params(C.Structure):
     _fields_ = [("width", C.c_int), ("height", C.c_int), ("step_vox", C.c_double), ("cutoff", C.c_double),
                 ("bg", C.c_double * 4), ("ray_function", C.c_int), ("iso_value", C.c_double),
-                ("iso_high", C.c_double), ("tie_delta", C.c_double)]
+                ("iso_high", C.c_double), ("tie_delta", C.c_double), ("opacity_unit", C.c_double)]
 
 
 _lib = None
@@ -158,7 +158,7 @@ class TF:
 
 
 def _params(width, height, step_vox, cutoff, bg=(0, 0, 0, 0), ray_function=COMPOSITE, iso_value=0.0,
-            iso_high=0.0, tie_delta=0.0) -> _Params:
+            iso_high=0.0, tie_delta=0.0, opacity_unit=0.0) -> _Params:
     p = _Params()
     p.width, p.height = int(width), int(height)
     p.step_vox, p.cutoff = float(step_vox), float(cutoff)
@@ -166,6 +166,7 @@ def _params(width, height, step_vox, cutoff, bg=(0, 0, 0, 0), ray_function=COMPO
     p.ray_function = int(ray_function)
     p.iso_value, p.iso_high = float(iso_value), float(iso_high)
     p.tie_delta = float(tie_delta)
+    p.opacity_unit = float(opacity_unit)
     return p
 
 
@@ -177,11 +178,12 @@ class RenderResult:
 def render(vol: Volume, tf: TF, cam, width: int, height: int, step_vox: float, cutoff: float,
            bg=(0.0, 0.0, 0.0, 0.0), pixels: Optional[np.ndarray] = None, tie_delta: float = 0.0,
            ray_function: int = COMPOSITE, iso_value: float = 0.0, iso_high: float = 0.0,
-           nthreads: int = 0, want_band: bool = False) -> RenderResult:
+           nthreads: int = 0, want_band: bool = False, opacity_unit: float = 0.0) -> RenderResult:
     """Render the whole image (``pixels`` None -> float64 [H][W][4]) or the
-    listed pixel ids (j*W + i -> float64 [n][4])."""
+    listed pixel ids (j*W + i -> float64 [n][4]).  opacity_unit > 0 applies
+    the opacity correction to that unit distance (compositing, thresholding)."""
     L = lib()
-    prm = _params(width, height, step_vox, cutoff, bg, ray_function, iso_value, iso_high, tie_delta)
+    prm = _params(width, height, step_vox, cutoff, bg, ray_function, iso_value, iso_high, tie_delta, opacity_unit)
     camc = _camera(cam)
     if pixels is None:
         n = width * height

@@ -25,8 +25,10 @@
  *   R3  samples at the midpoints of the dt-segments of [t_near, t_far], plus
  *       one sample at the midpoint of the last, partial segment of length r,
  *       whose opacity is corrected to 1-(1-a)^(r/dt);
- *   R4  no opacity correction for full samples (the table alpha is the
- *       per-sample alpha);
+ *   R4  no opacity correction for full samples by default (the table alpha
+ *       is the per-sample alpha); R24: on request, the table's opacities are
+ *       per unit distance u and are corrected to the sample spacing,
+ *       a' = 1-(1-a)^(dt/u), entry by entry before interpolation;
  *   R5  trilinear interpolation with clamp-to-edge, i0 = min(floor(q), n-2);
  *   R6  post-classification: interpolate the scalar, then look it up;
  *   R7  linear interpolation between the K table entries over [vmin, vmax];
@@ -288,6 +290,23 @@ void orc_classify(const orc_tf* tf, double value, double rgba[4]) {
         rgba[c] = (1.0 - g) * (double)tf->rgba[4 * j0 + c] + g * (double)tf->rgba[4 * (j0 + 1) + c];
 }
 
+/* Opacity correction (R24): the table's opacities are per unit distance u;
+ * a sample that stands for dt of ray gets a' = 1 - (1 - a)^(dt/u), applied to
+ * the two table entries before they are interpolated, so the correction is a
+ * transformation of the table (one table serves every sample of a render). */
+void orc_classify_corrected(const orc_tf* tf, double value, double r, double rgba[4]) {
+    orc_classify(tf, value, rgba);
+    if (!(r > 0.0)) return;
+    double x = (value - tf->vmin) / (tf->vmax - tf->vmin);
+    x = x < 0.0 ? 0.0 : (x > 1.0 ? 1.0 : x);
+    x *= (double)(tf->K - 1);
+    int64_t j0 = clampi((int64_t)floor(x), 0, tf->K - 2);
+    double g = x - (double)j0;
+    const double a0 = 1.0 - pow(1.0 - (double)tf->rgba[4 * j0 + 3], r);
+    const double a1 = 1.0 - pow(1.0 - (double)tf->rgba[4 * (j0 + 1) + 3], r);
+    rgba[3] = (1.0 - g) * a0 + g * a1;
+}
+
 /* ========================================================================= */
 /* step 3: the ray function                                                    */
 /* ========================================================================= */
@@ -523,11 +542,12 @@ static void ray_composite(const orc_volume* vol, const orc_tf* tf, const orc_par
     int stopped = 0, in_band = 0;
     double state[4];
     const int window = prm->ray_function == ORC_THRESHOLD;
+    const double r_corr = prm->opacity_unit > 0.0 ? rp->dt / prm->opacity_unit : 0.0;
     for (int64_t k = 0; k < n; ++k) {
         double s, weight, q[3], rgba[4];
         sample_at(rp, k, &s, &weight);
         double val = value_at(vol, rp, s, q);
-        orc_classify(tf, val, rgba);
+        orc_classify_corrected(tf, val, r_corr, rgba);
         double alpha = rgba[3];
         if (window) {
             /* thresholding (R21): samples outside [iso_value, iso_high] are transparent */
@@ -614,6 +634,7 @@ static int check_inputs(const orc_volume* vol, const orc_tf* tf, const orc_camer
     if (!(prm->step_vox > 0.0) || !isfinite(prm->step_vox)) return ORC_EINVAL;
     if (!(prm->cutoff > 0.0 && prm->cutoff <= 1.0)) return ORC_EINVAL;
     if (!(prm->tie_delta >= 0.0)) return ORC_EINVAL;
+    if (!(prm->opacity_unit >= 0.0) || !isfinite(prm->opacity_unit)) return ORC_EINVAL;
     double w[3], u[3], v[3];
     if (orc_camera_frame(cam, w, u, v) != ORC_OK) return ORC_EINVAL;
     double o[3], d[3];
@@ -666,11 +687,12 @@ int64_t orc_trace_ray(const orc_volume* vol, const orc_tf* tf, const orc_camera*
     if (!rp.hit) return 0;
     int64_t n = rp.m + (rp.r > 0.0 ? 1 : 0), nrec = 0;
     double C[3] = {0.0, 0.0, 0.0}, T = 1.0;
+    const double r_corr = prm->opacity_unit > 0.0 ? rp.dt / prm->opacity_unit : 0.0;
     for (int64_t k = 0; k < n && nrec < max_rec; ++k) {
         double s, weight, q[3], rgba[4];
         sample_at(&rp, k, &s, &weight);
         double val = value_at(vol, &rp, s, q);
-        orc_classify(tf, val, rgba);
+        orc_classify_corrected(tf, val, r_corr, rgba);
         double alpha = rgba[3];
         if (k == rp.m) alpha = 1.0 - pow(1.0 - alpha, weight);
         for (int c = 0; c < 3; ++c) C[c] += T * alpha * rgba[c];

@@ -93,6 +93,7 @@ typedef struct {
     double iso_value;         /* ORC_ISO: iso-value; ORC_THRESHOLD: window low */
     double iso_high;          /* ORC_THRESHOLD: window high */
     double tie_delta;         /* half-width of the early-termination tie band (>= 0) */
+    double opacity_unit;      /* > 0: opacity correction (R24) to this sample distance, mm; 0: none */
 } orc_params;
 
 /* ---- step 1: the ray path ------------------------------------------------ */
@@ -109,6 +110,10 @@ int64_t orc_lattice(double L, double dt, int64_t* m, double* r);
 /* ---- step 2: the values along the ray ------------------------------------ */
 double orc_trilinear(const orc_volume* vol, const double q[3]);
 void orc_classify(const orc_tf* tf, double value, double rgba[4]);
+/* As orc_classify, with the opacity entries corrected to the sample spacing
+ * first (R24): a' = 1 - (1 - a)^r, r = dt / unit distance; r = 0 leaves the
+ * table as it is. */
+void orc_classify_corrected(const orc_tf* tf, double value, double r, double rgba[4]);
 
 /* ---- step 3: the ray function, whole images ------------------------------ */
 /* Render the listed pixels (pixel id = j*W + i; NULL = all W*H in order).
