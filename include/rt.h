@@ -161,6 +161,12 @@ typedef struct {
                                          * short ones (lower latency when one view has the GPU to
                                          * itself); 0: 2 for rt_render, 1 for batches and plans.
                                          * Images are identical in every order. */
+    double opacity_unit_distance;       /* > 0 (mm): the table's opacities are per this distance
+                                         * and are corrected to the sample spacing,
+                                         * a' = 1 - (1 - a)^(dt / unit), entry by entry when the
+                                         * table is staged (compositing and thresholding; the
+                                         * paper's compositing, Section 4.2, uses the table opacity
+                                         * per sample, which is the default 0) */
 } rt_render_opts;
 
 /* Empty-space skipping (compositing only).  Each volume keeps, per skip brick
@@ -261,6 +267,7 @@ typedef struct {
     int ray_function;         /* rt_ray_function of this view; 0 = compositing */
     float iso_value, iso_high;
     int skip_empty;           /* compositing: leap over empty space (as rt_render_opts.skip_empty) */
+    double opacity_unit_distance; /* as rt_render_opts.opacity_unit_distance (0 = none) */
 } rt_render_job;
 
 /* Workspace bytes for batches of up to max_jobs views (max_jobs >= 1). */

@@ -54,6 +54,7 @@ typedef struct {
     float bg_rgba[4];
     int ray_function;          /* rt_ray_function */
     float iso_value, iso_high; /* as in rt_render_opts */
+    double opacity_unit_distance; /* as in rt_render_opts (0 = none) */
 } rt_request;
 
 enum {

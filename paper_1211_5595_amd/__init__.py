@@ -70,7 +70,8 @@ class rt_camera(C.Structure):
 class rt_render_opts(C.Structure):
     _fields_ = [("sample_counter", C.c_void_p), ("pixel_counts", C.c_void_p), ("ray_function", C.c_int),
                 ("iso_value", C.c_float), ("iso_high", C.c_float), ("tile_w", C.c_int), ("tile_h", C.c_int),
-                ("waves_per_block", C.c_int), ("skip_empty", C.c_int), ("tile_order", C.c_int)]
+                ("waves_per_block", C.c_int), ("skip_empty", C.c_int), ("tile_order", C.c_int),
+                ("opacity_unit_distance", C.c_double)]
 
 
 class rt_render_job(C.Structure):
@@ -78,7 +79,7 @@ class rt_render_job(C.Structure):
                 ("height", C.c_int), ("step_vox", C.c_double), ("alpha_cutoff", C.c_double),
                 ("bg_rgba", C.c_float * 4), ("out_dev", C.c_void_p), ("pixel_counts", C.c_void_p),
                 ("ray_function", C.c_int), ("iso_value", C.c_float), ("iso_high", C.c_float),
-                ("skip_empty", C.c_int)]
+                ("skip_empty", C.c_int), ("opacity_unit_distance", C.c_double)]
 
 
 class rt_request(C.Structure):
@@ -86,7 +87,7 @@ class rt_request(C.Structure):
                 ("tf_vmin", C.c_double), ("tf_vmax", C.c_double), ("camera", rt_camera), ("width", C.c_int),
                 ("height", C.c_int), ("step_vox", C.c_double), ("alpha_cutoff", C.c_double),
                 ("bg_rgba", C.c_float * 4), ("ray_function", C.c_int), ("iso_value", C.c_float),
-                ("iso_high", C.c_float)]
+                ("iso_high", C.c_float), ("opacity_unit_distance", C.c_double)]
 
 
 class rt_request_info(C.Structure):
@@ -195,9 +196,11 @@ def make_camera(cam) -> rt_camera:
 
 
 def make_opts(sample_counter=None, pixel_counts=None, ray_function=COMPOSITE, iso_value=0.0, iso_high=0.0,
-              tile=(0, 0), waves_per_block=0, skip_empty=False, tile_order=0) -> rt_render_opts:
+              tile=(0, 0), waves_per_block=0, skip_empty=False, tile_order=0,
+              opacity_unit_distance=0.0) -> rt_render_opts:
     o = rt_render_opts()
     o.tile_order = int(tile_order)
+    o.opacity_unit_distance = float(opacity_unit_distance)
     o.skip_empty = 1 if skip_empty else 0
     o.sample_counter = sample_counter.data_ptr() if sample_counter is not None else None
     o.pixel_counts = pixel_counts.data_ptr() if pixel_counts is not None else None
@@ -434,13 +437,14 @@ class TransferFunction:
 def render(volume: Volume, tf: TransferFunction, camera, width: int, height: int, step_vox: float = 0.5,
            alpha_cutoff: float = 0.99, bg=(0.0, 0.0, 0.0, 0.0), out=None, pixel_counts=None, sample_counter=None,
            spacing=None, tile=(0, 0), waves_per_block=0, stream=None, ray_function=COMPOSITE, iso_value=0.0,
-           iso_high=0.0, skip_empty=False, tile_order=0):
+           iso_high=0.0, skip_empty=False, tile_order=0, opacity_unit_distance=0.0):
     """Render one view; returns the float32 [H][W][4] device image."""
     torch = _torch()
     if out is None:
         out = torch.empty((height, width, 4), dtype=torch.float32, device=volume.buf.device)
     opts = make_opts(sample_counter, pixel_counts, ray_function, iso_value, iso_high, tile=tile,
-                     waves_per_block=waves_per_block, skip_empty=skip_empty, tile_order=tile_order)
+                     waves_per_block=waves_per_block, skip_empty=skip_empty, tile_order=tile_order,
+                     opacity_unit_distance=opacity_unit_distance)
     rt_render(volume.handle, volume.dims, spacing, tf.handle, camera, width, height, step_vox, alpha_cutoff, bg,
               out.data_ptr(), opts, stream)
     return out
@@ -452,11 +456,12 @@ class Job:
     def __init__(self, volume: Volume, tf: TransferFunction, camera, width: int, height: int,
                  step_vox: float = 0.5, alpha_cutoff: float = 0.99, bg=(0.0, 0.0, 0.0, 0.0), out=None,
                  pixel_counts=None, ray_function: int = COMPOSITE, iso_value: float = 0.0, iso_high: float = 0.0,
-                 skip_empty: bool = False):
+                 skip_empty: bool = False, opacity_unit_distance: float = 0.0):
         torch = _torch()
         self.volume, self.tf, self.camera = volume, tf, camera
         self.ray_function, self.iso_value, self.iso_high = int(ray_function), float(iso_value), float(iso_high)
         self.skip_empty = bool(skip_empty)
+        self.opacity_unit_distance = float(opacity_unit_distance)
         self.width, self.height = int(width), int(height)
         self.step_vox, self.alpha_cutoff, self.bg = float(step_vox), float(alpha_cutoff), tuple(bg)
         self.out = out if out is not None else torch.empty((height, width, 4), dtype=torch.float32,
@@ -474,6 +479,7 @@ class Job:
         j.pixel_counts = self.pixel_counts.data_ptr() if self.pixel_counts is not None else None
         j.ray_function, j.iso_value, j.iso_high = self.ray_function, self.iso_value, self.iso_high
         j.skip_empty = 1 if self.skip_empty else 0
+        j.opacity_unit_distance = self.opacity_unit_distance
         return j
 
 

@@ -759,9 +759,15 @@ __device__ __forceinline__ int wave_sum(int v) {
     return v;
 }
 
-__device__ __forceinline__ void load_tf(float4* s_tf, const float4* __restrict__ tf, int K) {
-    for (int e = threadIdx.x; e < K; e += blockDim.x) s_tf[e] = tf[e];
-    if (threadIdx.x == 0) s_tf[K] = tf[K - 1];
+// Stage the table in LDS.  alpha_exp > 0: opacity correction to the sample
+// spacing, a' = 1 - (1 - a)^alpha_exp per entry (a = 0 stays exactly 0 and a = 1
+// stays 1, so empty-space skipping's opacity counts still hold).
+__device__ __forceinline__ void load_tf(float4* s_tf, const float4* __restrict__ tf, int K, float alpha_exp) {
+    for (int e = threadIdx.x; e <= K; e += blockDim.x) {
+        float4 t = tf[min(e, K - 1)];
+        if (alpha_exp > 0.0f) t.w = 1.0f - exp2f(alpha_exp * log2f(1.0f - t.w));
+        s_tf[e] = t;
+    }
 }
 
 // One workgroup block of a view: wave w renders tile (w % bw, w / bw) of the block.
@@ -999,7 +1005,7 @@ __global__ void RT_MARCH_ATTRS march_plain_kernel(const ViewDesc V, const Launch
                                                    unsigned long long* __restrict__ counter) {
     extern __shared__ float4 s_tf[];
     uint32_t* s_mask = reinterpret_cast<uint32_t*>(s_tf + V.K + 1);
-    load_tf(s_tf, V.tf, V.K);
+    load_tf(s_tf, V.tf, V.K, V.alpha_exp);
     if (SKIP) build_skip_mask(s_mask, V);
     __syncthreads();
     render_block<KIND, LAYOUT, SKIP, true, ViewDesc>(V, s_tf, s_mask, xcd_remap(blockIdx.x, gridDim.x), ls, tw_shift,
@@ -1034,7 +1040,11 @@ __global__ void RT_MARCH_ATTRS march_batch_kernel(char* __restrict__ ws, const L
     // the table in LDS and the (volume, table) pair the mask was built for live
     // in LDS, not in scalar registers that would stay live across the marcher
     __shared__ const void* s_have[3];
-    if (threadIdx.x == 0) s_have[0] = s_have[1] = s_have[2] = nullptr;
+    __shared__ float s_have_exp;  // the opacity correction of the staged table
+    if (threadIdx.x == 0) {
+        s_have[0] = s_have[1] = s_have[2] = nullptr;
+        s_have_exp = 0.0f;
+    }
     for (;;) {
         if (threadIdx.x == 0) s_claim[0] = (int)atomicAdd(queue, 1u);
         __syncthreads();
@@ -1047,15 +1057,16 @@ __global__ void RT_MARCH_ATTRS march_batch_kernel(char* __restrict__ ws, const L
             else hi = mid;
         }
         const CViewDesc& V = jobs[lo];
-        const bool new_tf = (const void*)V.tf != s_have[0];
+        const bool new_tf = (const void*)V.tf != s_have[0] || V.alpha_exp != s_have_exp;
         const bool new_mask = SKIP && V.skip_empty && ((const void*)V.vol.ess_range != s_have[1] ||
                                                        (const void*)V.tf != s_have[2]);
         if (new_tf || new_mask) {
             __syncthreads();  // every lane has read s_have
-            if (new_tf) load_tf(s_tf, V.tf, V.K);
+            if (new_tf) load_tf(s_tf, V.tf, V.K, V.alpha_exp);
             if (new_mask) build_skip_mask(s_mask, V);
             if (threadIdx.x == 0) {
                 s_have[0] = V.tf;
+                s_have_exp = V.alpha_exp;
                 if (new_mask) {
                     s_have[1] = V.vol.ess_range;
                     s_have[2] = V.tf;

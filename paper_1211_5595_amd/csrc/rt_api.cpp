@@ -271,7 +271,7 @@ rt_status make_shape(const rt_render_opts* opts, bool single_view, LaunchShape& 
 rt_status make_view(const rt_volume* vol, const int64_t dims[3], const double spacing[3], const rt_tf* tf,
                     const rt_camera* cam, int W, int H, double step_vox, double cutoff, const float* bg,
                     float* out, int32_t* counts, const LaunchShape& ls, int ray_function, float iso_value,
-                    float iso_high, int skip_empty, ViewDesc& v) {
+                    float iso_high, int skip_empty, double opacity_unit, ViewDesc& v) {
     if (!vol || !tf || !cam || !out) return fail(RT_ERR_INVALID_ARG, "NULL volume, transfer function, camera or output");
     if (dims)
         for (int a = 0; a < 3; ++a)
@@ -314,6 +314,8 @@ rt_status make_view(const rt_volume* vol, const int64_t dims[3], const double sp
     if (bg)
         for (int c = 0; c < 4; ++c)
             if (!std::isfinite(bg[c])) return fail(RT_ERR_INVALID_ARG, "background must be finite");
+    if (!(opacity_unit >= 0.0) || !std::isfinite(opacity_unit))
+        return fail(RT_ERR_INVALID_ARG, "opacity unit distance must be finite and >= 0");
     const double dt = step_vox * std::min(sp[0], std::min(sp[1], sp[2]));
     double diag2 = 0.0;
     for (int a = 0; a < 3; ++a) diag2 += std::pow((double)(vol->dims[a] - 1) * sp[a], 2);
@@ -349,6 +351,9 @@ rt_status make_view(const rt_volume* vol, const int64_t dims[3], const double sp
     const double ta = (double)(tf->K - 1) / (tf->vmax - tf->vmin);
     v.tf_a = (float)ta;
     v.tf_b = (float)(-tf->vmin * ta);
+    v.alpha_exp = (opacity_unit > 0.0 && (ray_function == RT_COMPOSITE || ray_function == RT_THRESHOLD))
+                      ? (float)(dt / opacity_unit)
+                      : 0.0f;
     v.out = out;
     v.counts = counts;
     return RT_OK;
@@ -404,7 +409,7 @@ rt_status build_batch(const rt_render_job* jobs, int n, const LaunchShape& ls, i
         if (!J.volume) return fail(RT_ERR_INVALID_ARG, "job without volume");
         rt_status st = make_view(J.volume, nullptr, nullptr, J.tf, &J.camera, J.width, J.height, J.step_vox,
                                  J.alpha_cutoff, J.bg_rgba, J.out_dev, J.pixel_counts, ls, J.ray_function,
-                                 J.iso_value, J.iso_high, J.skip_empty, descs[i]);
+                                 J.iso_value, J.iso_high, J.skip_empty, J.opacity_unit_distance, descs[i]);
         if (st != RT_OK) return fail(st, "job " + std::to_string(i) + ": " + g_last_error);
         const int k = J.volume->dev.kind * 4 + J.volume->dev.layout;  // storage type and layout
         if (*kind < 0) *kind = k;
@@ -457,7 +462,7 @@ int set_last_error(int status, const char* msg) { return fail(static_cast<rt_sta
 
 int check_request(const rt_volume* vol, int K, double vmin, double vmax, const void* camera, int W, int H,
                   double step_vox, double cutoff, const float* bg, const float* out, int ray_function,
-                  float iso_value, float iso_high, int* kind) {
+                  float iso_value, float iso_high, double opacity_unit, int* kind) {
     if (K < 2 || K > kMaxK) return fail(RT_ERR_INVALID_ARG, "K must be in [2, 4096]");
     if (!std::isfinite(vmin) || !std::isfinite(vmax) || !(vmax > vmin)) return fail(RT_ERR_INVALID_ARG, "need vmin < vmax");
     rt_tf probe;  // geometry and table size only: never read on the device
@@ -471,7 +476,7 @@ int check_request(const rt_volume* vol, int K, double vmin, double vmax, const v
     if (st != RT_OK) return st;
     ViewDesc v;
     st = make_view(vol, nullptr, nullptr, &probe, static_cast<const rt_camera*>(camera), W, H, step_vox, cutoff, bg,
-                   const_cast<float*>(out), nullptr, ls, ray_function, iso_value, iso_high, 0, v);
+                   const_cast<float*>(out), nullptr, ls, ray_function, iso_value, iso_high, 0, opacity_unit, v);
     if (st != RT_OK) return st;
     if (kind) *kind = volume_kind(vol);
     return RT_OK;
@@ -671,7 +676,8 @@ rt_status rt_render(const rt_volume* volume, const int64_t dims[3], const double
     ViewDesc v;
     st = make_view(volume, dims, spacing, tf, camera, width, height, step_vox, alpha_cutoff, bg_rgba, out_dev,
                    opts ? opts->pixel_counts : nullptr, ls, opts ? opts->ray_function : 0,
-                   opts ? opts->iso_value : 0.0f, opts ? opts->iso_high : 0.0f, opts ? opts->skip_empty : 0, v);
+                   opts ? opts->iso_value : 0.0f, opts ? opts->iso_high : 0.0f, opts ? opts->skip_empty : 0,
+                   opts ? opts->opacity_unit_distance : 0.0, v);
     if (st != RT_OK) return st;
     hipError_t e = launch_march_plain(v, ls, opts ? opts->sample_counter : nullptr, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "render launch");

@@ -104,6 +104,7 @@ struct ViewDesc {
     int32_t skip_empty;         // nonzero: leap over skip bricks whose samples all have zero opacity
     int32_t K;
     float tf_a, tf_b;           // x = val*tf_a + tf_b, clamped to [0, K-1]
+    float alpha_exp;            // > 0: table opacities corrected to a' = 1-(1-a)^alpha_exp when staged
     float* out;                 // H*W float4
     int32_t* counts;            // nullable
 };
@@ -170,6 +171,6 @@ int volume_kind(const rt_volume* vol);
 int set_last_error(int status, const char* msg);
 int check_request(const rt_volume* vol, int K, double vmin, double vmax, const void* camera, int W, int H,
                   double step_vox, double cutoff, const float* bg, const float* out, int ray_function,
-                  float iso_value, float iso_high, int* kind);
+                  float iso_value, float iso_high, double opacity_unit, int* kind);
 
 }  // namespace rtv

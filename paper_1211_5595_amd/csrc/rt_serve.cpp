@@ -242,6 +242,7 @@ bool rt_server::launch(std::unique_lock<std::mutex>& lk) {
         J.ray_function = q.r.ray_function;
         J.iso_value = q.r.iso_value;
         J.iso_high = q.r.iso_high;
+        J.opacity_unit_distance = q.r.opacity_unit_distance;
         J.skip_empty = skip;
     }
     const double t_launch = now_s();
@@ -421,7 +422,8 @@ rt_status rt_server_submit(rt_server* s, const rt_request* req, uint64_t* ticket
     rt_status st = static_cast<rt_status>(check_request(req->volume, K, req->tf_vmin, req->tf_vmax, &req->camera,
                                                         req->width, req->height, req->step_vox, req->alpha_cutoff,
                                                         req->bg_rgba, reinterpret_cast<const float*>((uintptr_t)256),
-                                                        req->ray_function, req->iso_value, req->iso_high, &kind));
+                                                        req->ray_function, req->iso_value, req->iso_high,
+                                                        req->opacity_unit_distance, &kind));
     if (st != RT_OK) return st;
     if (kind != s->kind) return err(RT_ERR_INVALID_ARG, "volume of another storage type or layout than the server's");
     for (int i = 0; i < 4 * K; ++i)

@@ -56,6 +56,7 @@ class RenderRequest:
     ray_function: int = 0              # rt_ray_function (compositing by default)
     iso_value: float = 0.0             # iso-value, or the low end of a threshold window
     iso_high: float = 0.0              # high end of a threshold window
+    opacity_unit_distance: float = 0.0 # > 0: opacity correction to this distance (mm)
 
 
 class RenderFuture:
@@ -344,7 +345,8 @@ class GpuExecutor:
                 out = torch.empty((r.height, r.width, 4), dtype=torch.float32, device=self.device)
                 jobs.append(self._Job(self.volumes[r.volume_id], tf, r.camera, r.width, r.height, r.step_vox,
                                       r.alpha_cutoff, r.bg, out=out, skip_empty=self.skip_empty,
-                                      ray_function=r.ray_function, iso_value=r.iso_value, iso_high=r.iso_high))
+                                      ray_function=r.ray_function, iso_value=r.iso_value, iso_high=r.iso_high,
+                                      opacity_unit_distance=r.opacity_unit_distance))
             self.plans[k].launch(jobs, sample_counter=self.counters[k], stream=s)
             self.host_counts[k:k + 1].copy_(self.counters[k], non_blocking=True)
             ev = torch.cuda.Event()
@@ -430,6 +432,7 @@ class NativeServer:
         r.ray_function = int(getattr(req, "ray_function", 0))
         r.iso_value = float(getattr(req, "iso_value", 0.0))
         r.iso_high = float(getattr(req, "iso_high", 0.0))
+        r.opacity_unit_distance = float(getattr(req, "opacity_unit_distance", 0.0))
         return rt_server_submit(self.handle, r)
 
     def wait(self, ticket: int, timeout: float = -1.0):

@@ -194,3 +194,33 @@ def test_server_arena_and_argument_checks(rt):
     assert L.rt_server_create(2, 8, 1, 0, C.byref(bad), C.c_void_p(4096), need, 1 << 20, C.byref(h)) == 1
     assert L.rt_server_submit(None, None, None) == 1 and L.rt_server_release(None, 1) == 1
     assert L.rt_server_destroy(None) == 0
+
+
+def test_struct_layouts_match_the_header(rt, tmp_path):
+    """The ctypes mirrors of the ABI structs have the C compiler's sizes and
+    field offsets (compiled from include/*.h with the host C compiler)."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    structs = {"rt_camera": rt.rt_camera, "rt_render_opts": rt.rt_render_opts, "rt_render_job": rt.rt_render_job,
+               "rt_request": rt.rt_request, "rt_request_info": rt.rt_request_info,
+               "rt_server_stats": rt.rt_server_stats}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "rt_serve.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'    printf("{name} size %zu\\n", sizeof({name}));')
+        for f, _ in cls._fields_:
+            lines.append(f'    printf("{name} {f} %zu\\n", offsetof({name}, {f}));')
+    lines += ["    return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c11", "-I", inc, str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:-1]): int(l.split()[-1]) for l in out if l.strip()}
+    for name, cls in structs.items():
+        assert got[(name, "size")] == C.sizeof(cls), name
+        for f, _ in cls._fields_:
+            assert got[(name, f)] == getattr(cls, f).offset, (name, f)

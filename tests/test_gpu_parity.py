@@ -621,3 +621,55 @@ def test_u15_clamps_above_32767(rt, torch_mod, orc):
                      tie_delta=DELTA, want_band=True)
     check(got, ref, c, "u15 clamped")
     assert (v > 32767).any()
+
+
+@pytest.mark.parametrize("step,unit", [(0.5, 0.9), (0.25, 0.9), (0.8, 0.3)])
+def test_opacity_correction_matches_oracle(rt, torch_mod, orc, brain, step, unit):
+    """Opacity correction to a unit distance (table entries corrected when
+    staged): full brain view against the oracle, for u16 and u12 storage, with
+    and without skipping (bitwise equal), plain and batched (bitwise equal)."""
+    torch = torch_mod
+    cam = brain["cams"][9]
+    ref = orc.render(brain["ov"], brain["otf"], cam, 256, 256, step, 0.99, tie_delta=DELTA, want_band=True,
+                     opacity_unit=unit)
+    gv12 = rt.Volume(brain["np"], brain["sp"], storage=rt.U12)
+    for gv in (brain["gv"], gv12):
+        got, c = gpu_render(rt, torch, gv, brain["gtf"], cam, 256, 256, step, 0.99, opacity_unit_distance=unit)
+        check(got, ref, c, f"opacity unit {unit} step {step}")
+        sk, cs = gpu_render(rt, torch, gv, brain["gtf"], cam, 256, 256, step, 0.99, opacity_unit_distance=unit,
+                            skip_empty=True)
+        assert np.array_equal(sk, got) and np.array_equal(cs, c)
+        jobs = [rt.Job(gv, brain["gtf"], cam, 256, 256, step, 0.99, opacity_unit_distance=unit),
+                rt.Job(gv, brain["gtf"], cam, 256, 256, step, 0.99),               # same table, no correction
+                rt.Job(gv, brain["gtf"], cam, 256, 256, step, 0.99, opacity_unit_distance=unit, skip_empty=True)]
+        outs = rt.render_batch(jobs)
+        plain = rt.render(gv, brain["gtf"], cam, 256, 256, step, 0.99)
+        torch.cuda.synchronize()
+        assert np.array_equal(outs[0].cpu().numpy().astype(np.float64), got)
+        assert np.array_equal(outs[2].cpu().numpy().astype(np.float64), got)
+        assert torch.equal(outs[1], plain)
+
+
+def test_opacity_correction_thresholding_and_slab(rt, torch_mod, orc, small):
+    torch = torch_mod
+    cam = W.ortho_camera_small()
+    for fn, lo, hi in ((rt.THRESHOLD, 100.0, 230.0), (rt.COMPOSITE, 0.0, 0.0)):
+        got, c = gpu_render(rt, torch, small["gv"], small["gtf"], cam, 128, 128, 0.45, 0.99,
+                            opacity_unit_distance=1.7, ray_function=fn, iso_value=lo, iso_high=hi)
+        ref = orc.render(small["ov"], small["otf"], cam, 128, 128, 0.45, 0.99, tie_delta=DELTA, want_band=True,
+                         opacity_unit=1.7, ray_function=fn, iso_value=lo, iso_high=hi)
+        keep = (ref.tie & 8) == 0
+        dist = np.maximum(np.maximum(ref.band_lo - got, got - ref.band_hi), 0.0).max(-1)
+        assert dist[keep].max() <= TOL
+    # a uniform slab's opacity depends on its thickness only: 1-(1-a)^(L/u) at every step
+    v = np.full((4, 4, 4), 7, dtype=np.uint8)
+    t = np.zeros((8, 4), np.float32)
+    t[:, :3], t[:, 3] = 0.5, 0.1
+    gv, gtf = rt.Volume(v, (1, 1, 1), storage=rt.U8), rt.TransferFunction(t, 0, 10)
+    slab = W.Camera((1.5, 1.5, -10.0), (1.5, 1.5, 0.0), (0, 1, 0), False, 0.0, 1.0)
+    A = 1 - (1 - float(np.float32(0.1))) ** (3.0 / 1.5)
+    for step in (0.3, 0.5, 0.7, 1.1):
+        img, _ = gpu_render(rt, torch, gv, gtf, slab, 2, 2, step, 1.0, opacity_unit_distance=1.5)
+        np.testing.assert_allclose(img[..., 3], A, atol=2e-6)
+    with pytest.raises(rt.InvalidArgument):
+        rt.render(gv, gtf, slab, 2, 2, 0.5, 1.0, opacity_unit_distance=-1.0)
