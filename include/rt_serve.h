@@ -114,9 +114,12 @@ rt_status rt_server_release(rt_server* server, uint64_t ticket);
 
 rt_status rt_server_get_stats(rt_server* server, rt_server_stats* stats);
 
-/* Finish every queued and running request, stop the server thread and free
- * the server's streams, plans, table handles and host buffers.  Images of
- * unreleased requests stay in the caller's arena. */
+/* Finish every queued and running request (a queued request that can never
+ * be admitted because unreleased images hold the pool fails with
+ * RT_ERR_OUT_OF_MEMORY), stop the server thread and free the server's streams,
+ * plans, table handles and host buffers.  Images of unreleased requests stay
+ * in the caller's arena.  No other call on the server may run concurrently
+ * with this one or follow it. */
 rt_status rt_server_destroy(rt_server* server);
 
 #ifdef __cplusplus
