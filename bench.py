@@ -600,7 +600,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py renders on exactly one GPU: the raycaster has no multi-GPU path in this build "
+        print("bench.py renders on exactly one GPU: the raycaster has no multi-GPU path "
               "(views would shard across GPUs with no exchange); run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 

@@ -60,7 +60,7 @@ typedef enum {
     RT_ERR_INVALID_ARG = 1,   /* null pointer, bad size, bad camera, ... */
     RT_ERR_OUT_OF_MEMORY = 2, /* a caller-provided buffer is too small */
     RT_ERR_DEVICE = 3,        /* a HIP runtime call failed */
-    RT_ERR_UNSUPPORTED = 4    /* valid request outside what this build supports */
+    RT_ERR_UNSUPPORTED = 4    /* valid request outside what the library supports */
 } rt_status;
 
 /* Storage (and source) element types of a volume. */
