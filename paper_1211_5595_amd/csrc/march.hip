@@ -402,6 +402,9 @@ struct Sampler<ST_U12, LAYOUT_CELLS> {
     }
 };
 
+// Cells in flight per ray in the single-view kernel's compositing loop.
+constexpr int kRing = 4;
+
 // An empty use of the first word of a loaded cell: pins the load ahead of a
 // branch after which only one side needs it.
 template <class Raw>
@@ -671,34 +674,63 @@ __device__ __forceinline__ void march_pixel(const VD& V, const float4* __restric
             int it = 0;
             bool stale = false;
             if constexpr (PREFETCH && !SKIP) {
-                // the next sample's cell is requested before this sample is
-                // processed, so a wavefront that has its SIMD to itself (a lone
-                // view leaves most SIMDs with few wavefronts) overlaps the load
-                // with the arithmetic; its use on the exit path keeps the
-                // compiler from moving the request behind the exit test.  It
-                // costs register copies per sample, so the batched kernel, whose
-                // many wavefronts hide the latency anyway, does not use it.
-                for (;;) {
-                    const long long Qn[3] = {R.Q[0] + R.dQ[0], R.Q[1] + R.dQ[1], R.Q[2] + R.dQ[2]};
-                    const typename S::Raw nxt = S::load(rs, V.vol, cn, Qn);
-                    const float val = stored_value<S>(cur, frac32(R.Q[0]), frac32(R.Q[1]), frac32(R.Q[2]));
-                    float4 c = classify(s_tf, val, ta, tb, Km1);
-                    if (WINDOW && !in_window(val + bias, V)) c.w = 0.0f;
-                    const float Ta = T * c.w;
-                    asm volatile("" ::"v"(Ta));  // formed before T is overwritten: no copy of T
-                    Cr = fmaf(Ta, c.x, Cr);
-                    Cg = fmaf(Ta, c.y, Cg);
-                    Cb = fmaf(Ta, c.z, Cb);
-                    T = fmaf(-T, c.w, T);
-                    ++k;
-                    if (k >= R.m || T <= thr) {
-                        keep_issued(nxt);
-                        break;
+                // The cells of the next kRing samples are in flight while this
+                // sample is processed: a ring of registers, unrolled so every
+                // buffer keeps its own registers (no copies), each refilled with
+                // the cell kRing samples ahead once it has been used.  A lone
+                // view leaves most SIMDs with few wavefronts, where a sample
+                // costs the memory latency unless loads overlap.
+                // Qf is the position of sample kf, the next one to request; it
+                // stops at the ray's last full sample (m - 1), so every request
+                // is for a cell the ray itself samples -- the same cells, with
+                // the same bounds, as the loop without a ring.  (A ray that has
+                // stopped keeps requesting that last cell.)
+                typename S::Raw ring[kRing];
+                ring[0] = cur;
+                long long Qf[3] = {R.Q[0], R.Q[1], R.Q[2]};
+                int kf = 0;
+                auto advance_request = [&]() {
+                    if (kf < R.m - 1) {
+                        ++kf;
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) Qf[a] += R.dQ[a];
                     }
-                    cur = nxt;
-                    R.Q[0] = Qn[0];
-                    R.Q[1] = Qn[1];
-                    R.Q[2] = Qn[2];
+                };
+#pragma unroll
+                for (int b = 1; b < kRing; ++b) {
+                    advance_request();
+                    ring[b] = S::load(rs, V.vol, cn, Qf);
+                }
+                // Straight-line steps (no per-ray exit inside the ring): a ray
+                // that has stopped keeps stepping with its opacity forced to 0,
+                // which leaves its colour and transmittance unchanged bit for
+                // bit (T * 0 = 0, fma(-T, 0, T) = T), so every refill is issued
+                // unconditionally and each step waits only for its own cell.
+                bool live = true;  // k < m and T above the cutoff
+                for (;;) {
+#pragma unroll
+                    for (int b = 0; b < kRing; ++b) {
+                        const float val = stored_value<S>(ring[b], frac32(R.Q[0]), frac32(R.Q[1]), frac32(R.Q[2]));
+                        float4 c = classify(s_tf, val, ta, tb, Km1);
+                        if (WINDOW && !in_window(val + bias, V)) c.w = 0.0f;
+                        const float a = live ? c.w : 0.0f;
+                        const float Ta = T * a;
+                        asm volatile("" ::"v"(Ta));  // formed before T is overwritten: no copy of T
+                        Cr = fmaf(Ta, c.x, Cr);
+                        Cg = fmaf(Ta, c.y, Cg);
+                        Cb = fmaf(Ta, c.z, Cb);
+                        T = fmaf(-T, a, T);
+                        k += live ? 1 : 0;
+                        live = live && k < R.m && T > thr;
+                        advance_request();
+                        ring[b] = S::load(rs, V.vol, cn, Qf);
+#pragma unroll
+                        for (int q = 0; q < 3; ++q) R.Q[q] += R.dQ[q];
+                        // keep the steps in order: interleaving them would make the
+                        // first step wait for every cell of the ring
+                        __builtin_amdgcn_sched_barrier(0);
+                    }
+                    if (__builtin_amdgcn_ballot_w64(live) == 0) break;
                 }
             }
             for (; !(PREFETCH && !SKIP);) {
@@ -997,11 +1029,14 @@ __device__ __forceinline__ int xcd_remap(int b, int n) {
 // Occupancy: at least 8 waves per SIMD (two 1024-lane workgroups per CU),
 // which caps the marcher at 64 VGPRs.
 #define RT_MARCH_ATTRS __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8)))
+// The single-view kernel: one view of up to a few thousand wavefronts never
+// fills 8 per SIMD, so it may use the registers of 4 (its loads in flight).
+#define RT_PLAIN_ATTRS __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4)))
 
 // SKIP selects the compositing loop with empty-space skipping (a separate
 // kernel, so the plain loop keeps its registers).
 template <int KIND, int LAYOUT, bool SKIP>
-__global__ void RT_MARCH_ATTRS march_plain_kernel(const ViewDesc V, const LaunchShape ls, int tw_shift,
+__global__ void RT_PLAIN_ATTRS march_plain_kernel(const ViewDesc V, const LaunchShape ls, int tw_shift,
                                                    unsigned long long* __restrict__ counter) {
     extern __shared__ float4 s_tf[];
     uint32_t* s_mask = reinterpret_cast<uint32_t*>(s_tf + V.K + 1);
