@@ -151,7 +151,9 @@ typedef struct {
     float iso_value;                    /* RT_ISO iso-value; RT_THRESHOLD window low */
     float iso_high;                     /* RT_THRESHOLD window high */
     int tile_w, tile_h;                 /* ray tile of one wavefront, tile_w*tile_h == 64; 0 = 8x8 */
-    int waves_per_block;                /* wavefronts per workgroup, 1..16; 0 = default */
+    int waves_per_block;                /* wavefronts per workgroup, 1..16; 0 = default: 16 for
+                                         * batches; for rt_render the most (up to 16) that still
+                                         * give every compute unit a workgroup */
     int skip_empty;                     /* compositing: nonzero leaps over empty space (see below) */
     int tile_order;                     /* 1: a workgroup renders a compact block of tiles (cache
                                          * locality across the rays of a block: the better order when

@@ -486,7 +486,11 @@ struct Sampler<ST_U8B, LAYOUT_CELLS> {
         const uint32_t w = (ix & 1u) | ((iy & 1u) << 1) | ((iz & 1u) << 2);
         Raw o;
         o.w = __builtin_amdgcn_raw_buffer_load_b64(r, (blk << 6) | (w << 3), 0, 0);
-        o.par = vol.brick_par[blk];
+        // the codes come through the bounds-checked buffer; the parameters are a
+        // plain load, so a request for a position past the grid (the next sample
+        // after a ray's last, at a large step) is clamped to the last block
+        const uint32_t last = (uint32_t)vol.nb[0] * (uint32_t)vol.nb[1] * (uint32_t)vol.nb[2] - 1u;
+        o.par = vol.brick_par[min(blk, last)];
         return o;
     }
     static __device__ __forceinline__ float value(const Raw& o, float fx, float fy, float fz) {

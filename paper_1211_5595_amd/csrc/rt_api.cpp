@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -241,6 +242,12 @@ void cross(const double a[3], const double b[3], double c[3]) {
 }
 double norm(const double a[3]) { return std::sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]); }
 
+void set_waves(LaunchShape& ls, int waves) {
+    ls.waves = waves;
+    ls.bw = waves >= 4 ? (waves >= 16 ? 4 : (waves == 8 ? 4 : 2)) : waves;
+    ls.bh = waves / ls.bw;
+}
+
 // single_view: the launch renders one view alone (rt_render), which decides
 // the default tile order.
 rt_status make_shape(const rt_render_opts* opts, bool single_view, LaunchShape& ls) {
@@ -262,10 +269,32 @@ rt_status make_shape(const rt_render_opts* opts, bool single_view, LaunchShape& 
         return fail(RT_ERR_UNSUPPORTED, "waves_per_block must be 1, 2, 4, 8 or 16");
     ls.tile_w = tw;
     ls.tile_h = th;
-    ls.waves = waves;
-    ls.bw = waves >= 4 ? (waves >= 16 ? 4 : (waves == 8 ? 4 : 2)) : waves;
-    ls.bh = waves / ls.bw;
+    set_waves(ls, waves);
     return RT_OK;
+}
+
+// Compute units of the current device (queried once per device).
+int cu_count() {
+    static std::atomic<int> cache[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    int n = cache[dev].load(std::memory_order_relaxed);
+    if (n <= 0) {
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+        cache[dev].store(n, std::memory_order_relaxed);
+    }
+    return n;
+}
+
+// Default wavefronts per workgroup of a single view: as many as keep every
+// compute unit busy -- a 16-wavefront workgroup fills a CU's four SIMDs, so a
+// view of fewer tiles than 16 per CU would leave CUs idle.
+int default_waves(int W, int H, const LaunchShape& ls) {
+    const long long tiles = (long long)((W + ls.tile_w - 1) / ls.tile_w) * ((H + ls.tile_h - 1) / ls.tile_h);
+    const long long per_cu = tiles / std::max(cu_count(), 1);
+    int waves = 1;
+    while (waves < 16 && 2LL * waves <= per_cu) waves *= 2;
+    return waves;
 }
 
 rt_status make_view(const rt_volume* vol, const int64_t dims[3], const double spacing[3], const rt_tf* tf,
@@ -673,6 +702,8 @@ rt_status rt_render(const rt_volume* volume, const int64_t dims[3], const double
     LaunchShape ls;
     rt_status st = make_shape(opts, true, ls);
     if (st != RT_OK) return st;
+    if ((!opts || opts->waves_per_block == 0) && width > 0 && height > 0)
+        set_waves(ls, default_waves(width, height, ls));
     ViewDesc v;
     st = make_view(volume, dims, spacing, tf, camera, width, height, step_vox, alpha_cutoff, bg_rgba, out_dev,
                    opts ? opts->pixel_counts : nullptr, ls, opts ? opts->ray_function : 0,
