@@ -402,8 +402,13 @@ struct Sampler<ST_U12, LAYOUT_CELLS> {
     }
 };
 
-// Cells in flight per ray in the single-view kernel's compositing loop.
-constexpr int kRing = 4;
+// Cells in flight per ray in the single-view kernel's compositing loop: six
+// when a sample's cell fits 16 bytes, four for the larger ones (six of those
+// would exceed the kernel's registers).
+template <class S>
+constexpr int ring_depth() {
+    return sizeof(typename S::Raw) <= 16 ? 6 : 4;
+}
 
 // An empty use of the first word of a loaded cell: pins the load ahead of a
 // branch after which only one side needs it.
@@ -678,10 +683,10 @@ __device__ __forceinline__ void march_pixel(const VD& V, const float4* __restric
             int it = 0;
             bool stale = false;
             if constexpr (PREFETCH && !SKIP) {
-                // The cells of the next kRing samples are in flight while this
+                // The cells of the next depth samples are in flight while this
                 // sample is processed: a ring of registers, unrolled so every
                 // buffer keeps its own registers (no copies), each refilled with
-                // the cell kRing samples ahead once it has been used.  A lone
+                // the cell depth samples ahead once it has been used.  A lone
                 // view leaves most SIMDs with few wavefronts, where a sample
                 // costs the memory latency unless loads overlap.
                 // Qf is the position of sample kf, the next one to request; it
@@ -689,7 +694,8 @@ __device__ __forceinline__ void march_pixel(const VD& V, const float4* __restric
                 // is for a cell the ray itself samples -- the same cells, with
                 // the same bounds, as the loop without a ring.  (A ray that has
                 // stopped keeps requesting that last cell.)
-                typename S::Raw ring[kRing];
+                constexpr int depth = ring_depth<S>();
+                typename S::Raw ring[depth];
                 ring[0] = cur;
                 long long Qf[3] = {R.Q[0], R.Q[1], R.Q[2]};
                 int kf = 0;
@@ -701,7 +707,7 @@ __device__ __forceinline__ void march_pixel(const VD& V, const float4* __restric
                     }
                 };
 #pragma unroll
-                for (int b = 1; b < kRing; ++b) {
+                for (int b = 1; b < depth; ++b) {
                     advance_request();
                     ring[b] = S::load(rs, V.vol, cn, Qf);
                 }
@@ -713,7 +719,7 @@ __device__ __forceinline__ void march_pixel(const VD& V, const float4* __restric
                 bool live = true;  // k < m and T above the cutoff
                 for (;;) {
 #pragma unroll
-                    for (int b = 0; b < kRing; ++b) {
+                    for (int b = 0; b < depth; ++b) {
                         const float val = stored_value<S>(ring[b], frac32(R.Q[0]), frac32(R.Q[1]), frac32(R.Q[2]));
                         float4 c = classify(s_tf, val, ta, tb, Km1);
                         if (WINDOW && !in_window(val + bias, V)) c.w = 0.0f;
@@ -798,11 +804,23 @@ __device__ __forceinline__ int wave_sum(int v) {
 // Stage the table in LDS.  alpha_exp > 0: opacity correction to the sample
 // spacing, a' = 1 - (1 - a)^alpha_exp per entry (a = 0 stays exactly 0 and a = 1
 // stays 1, so empty-space skipping's opacity counts still hold).
+// Eight entries per lane are requested before any is stored, so a small
+// workgroup (one wavefront staging 4097 entries) waits for memory 8 times, not 64.
 __device__ __forceinline__ void load_tf(float4* s_tf, const float4* __restrict__ tf, int K, float alpha_exp) {
-    for (int e = threadIdx.x; e <= K; e += blockDim.x) {
-        float4 t = tf[min(e, K - 1)];
-        if (alpha_exp > 0.0f) t.w = 1.0f - exp2f(alpha_exp * log2f(1.0f - t.w));
-        s_tf[e] = t;
+    constexpr int U = 8;
+    const int step = (int)blockDim.x;
+    for (int e0 = threadIdx.x; e0 <= K; e0 += U * step) {
+        float4 t[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) t[u] = tf[min(e0 + u * step, K - 1)];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = e0 + u * step;
+            if (e <= K) {
+                if (alpha_exp > 0.0f) t[u].w = 1.0f - exp2f(alpha_exp * log2f(1.0f - t[u].w));
+                s_tf[e] = t[u];
+            }
+        }
     }
 }
 
