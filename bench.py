@@ -670,7 +670,7 @@ def main():
         diff = torch.stack([(a - b).abs().amax(-1) for a, b in zip(outs, outs16)])
         vs_u16 = {"bitwise_equal": all(torch.equal(a, b) for a, b in zip(outs, outs16)),
                   "max_abs_diff": float(diff.max()), "pixels_above_1e-5": int((diff > 1e-5).sum())}
-        del vol16, outs16, diff
+        del diff
 
     def step_batch():
         rt.render_batch(jobs, **shape)
@@ -701,6 +701,15 @@ def main():
     elif args.only:
         forms = {args.only: forms[args.only]}
     ms = {k: timed(fn, args.steps, args.warmup) for k, fn in forms.items()}
+    if vs_u16 is not None and not args.only:  # the same launch form over the 16-bit cells, for reference
+        plan16 = rt.BatchPlan(n_views, rt.U16, layout=layout, **shape)
+        jobs16 = [rt.Job(vol16, tf, cam, width, height, step, cutoff, out=o) for cam, o in zip(cams, outs16)]
+        ms16 = timed(lambda: plan16.launch(jobs16), args.steps, args.warmup)
+        vs_u16["u16_graph_ms_per_step"] = round(ms16, 4)
+        vs_u16["u16_gsamples_per_s"] = round(samples_per_step / (ms16 * 1e-3) / 1e9, 3)
+        del plan16, jobs16
+    if vs_u16 is not None:
+        del vol16, outs16
     best = min(ms, key=ms.get)
     ms_step = ms[best]
     gsps = samples_per_step / (ms_step * 1e-3) / 1e9
