@@ -682,7 +682,7 @@ __device__ __forceinline__ void march_pixel(const VD& V, const float4* __restric
             // sample is taken, so a run of leaps never waits on memory)
             int it = 0;
             bool stale = false;
-            if constexpr (PREFETCH && !SKIP) {
+            if constexpr (PREFETCH) {
                 // The cells of the next depth samples are in flight while this
                 // sample is processed: a ring of registers, unrolled so every
                 // buffer keeps its own registers (no copies), each refilled with
@@ -718,6 +718,41 @@ __device__ __forceinline__ void march_pixel(const VD& V, const float4* __restric
                 // unconditionally and each step waits only for its own cell.
                 bool live = true;  // k < m and T above the cutoff
                 for (;;) {
+                    if constexpr (SKIP) {
+                        // at the start of each round: when no live ray of the wavefront
+                        // sits in an occupied brick, each live ray leaps to its first
+                        // sample outside its brick (or super-brick, or to its end); the
+                        // ring is refilled only when samples are taken again, so a run of
+                        // leaps never waits on memory.  Stopped rays take no part (their
+                        // position runs on past their ray and is never looked up).
+                        if (V.skip_empty) {
+                            bool occupied = false;
+                            if (live) occupied = !in_empty_brick(s_mask, V.vol, R.Q);
+                            if (__builtin_amdgcn_ballot_w64(occupied) == 0) {
+                                if (live) {
+                                    k += leap(s_mask, V.vol, R.Q, R.dQ, R.m - k);
+                                    live = k < R.m;
+                                }
+                                if (__builtin_amdgcn_ballot_w64(live) == 0) break;
+                                stale = true;
+                                continue;
+                            }
+                            if (stale) {
+                                stale = false;
+                                if (live) {  // ring[b] = sample k + b, clamped to the ray's last
+#pragma unroll
+                                    for (int a = 0; a < 3; ++a) Qf[a] = R.Q[a];
+                                    kf = k;
+                                    ring[0] = S::load(rs, V.vol, cn, Qf);
+#pragma unroll
+                                    for (int b = 1; b < depth; ++b) {
+                                        advance_request();
+                                        ring[b] = S::load(rs, V.vol, cn, Qf);
+                                    }
+                                }
+                            }
+                        }
+                    }
 #pragma unroll
                     for (int b = 0; b < depth; ++b) {
                         const float val = stored_value<S>(ring[b], frac32(R.Q[0]), frac32(R.Q[1]), frac32(R.Q[2]));
@@ -743,7 +778,7 @@ __device__ __forceinline__ void march_pixel(const VD& V, const float4* __restric
                     if (__builtin_amdgcn_ballot_w64(live) == 0) break;
                 }
             }
-            for (; !(PREFETCH && !SKIP);) {
+            for (; !PREFETCH;) {
                 if constexpr (SKIP) {
                     // all live rays of the wavefront in empty bricks: each leaps to
                     // its first sample outside its brick (or to the end of its ray)
