@@ -673,3 +673,36 @@ def test_opacity_correction_thresholding_and_slab(rt, torch_mod, orc, small):
         np.testing.assert_allclose(img[..., 3], A, atol=2e-6)
     with pytest.raises(rt.InvalidArgument):
         rt.render(gv, gtf, slab, 2, 2, 0.5, 1.0, opacity_unit_distance=-1.0)
+
+
+@pytest.mark.parametrize("storage", ["U16", "U12", "U8_BRICKSCALED"])
+def test_extreme_steps_tables_and_cutoffs(rt, torch_mod, orc, storage):
+    """Steps from 0.05 voxel (rays of thousands of samples) to 6 voxels (rays of
+    one or two, shorter than the single-view kernel's ring of in-flight cells),
+    the smallest and largest tables, a cutoff reached at the first sample, a
+    value window narrower than the data, and one-pixel-wide images; plain and
+    batched renders equal the oracle, and each other bit for bit."""
+    torch = torch_mod
+    dims, sp = (40, 33, 21), (1.0, 0.8, 1.6)
+    v = W.phantom_brain(77, dims=dims, spacing=sp)
+    if storage == "U8_BRICKSCALED":
+        gv, ov = rt.Volume(v, sp, storage=rt.U8_BRICKSCALED, brick=8), orc.Volume.from_u8_bricks(v, sp, 8)
+    else:
+        gv, ov = rt.Volume(v, sp, storage=getattr(rt, storage)), orc.Volume(v, sp)
+    rng = np.random.default_rng(91)
+    cases = [(0.05, W.random_tf(4096, 1, alpha_max=0.02), 0.0, 4095.0, 0.99, 24, 20),
+             (6.0, W.random_tf(2, 2, alpha_max=0.9), 0.0, 4095.0, 1.0, 31, 17),
+             (3.3, W.random_tf(256, 3, alpha_max=0.5), 500.0, 1500.0, 0.99, 1, 40),
+             (0.7, W.random_tf(64, 4, alpha_max=1.0), 0.0, 4095.0, 0.01, 40, 1),
+             (1.9, W.random_tf(4096, 5, alpha_max=0.3), 0.0, 4095.0, 0.5, 33, 29)]
+    for step, table, lo, hi, cutoff, Wd, Hd in cases:
+        cam = W.random_camera(rng, dims, sp)
+        gtf = rt.TransferFunction(table, lo, hi)
+        got, c = gpu_render(rt, torch, gv, gtf, cam, Wd, Hd, step, cutoff)
+        ref = orc.render(ov, orc.TF(table, lo, hi), cam, Wd, Hd, step, cutoff, tie_delta=DELTA, want_band=True)
+        check(got, ref, c, f"{storage} step {step} K {table.shape[0]} cutoff {cutoff} {Wd}x{Hd}")
+        skip, cs = gpu_render(rt, torch, gv, gtf, cam, Wd, Hd, step, cutoff, skip_empty=True)
+        assert np.array_equal(skip, got) and np.array_equal(cs, c)
+        out = rt.render_batch([rt.Job(gv, gtf, cam, Wd, Hd, step, cutoff)])[0]
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy().astype(np.float64), got)
