@@ -239,7 +239,12 @@ struct Sampler<KIND, LAYOUT_LINEAR> {
     static __device__ __forceinline__ Raw load(__amdgpu_buffer_rsrc_t r, const VOL& vol, const Corners& cn,
                                                const long long Q[3]) {
         using E = Elem<KIND>;
-        const uint32_t off = __umul24(hiword(Q[2]), vol.sz) + __umul24(hiword(Q[1]), vol.sy) + hiword(Q[0]) * E::bytes;
+        // the corner offsets ride in the scalar offset, which the buffer's bounds
+        // check does not cover: a position past the padded grid (the request for
+        // the sample after a ray's last, at steps above two voxels) is clamped so
+        // that every corner stays inside the buffer; no cell of the grid moves
+        const uint32_t off = min(__umul24(hiword(Q[2]), vol.sz) + __umul24(hiword(Q[1]), vol.sy) + hiword(Q[0]) * E::bytes,
+                                 vol.data_bytes - (vol.sz + vol.sy + 2u * E::bytes));
         Raw w;
         w.c[0] = E::load(r, off, 0);
         w.c[1] = E::load(r, off, cn.c1);
@@ -525,7 +530,9 @@ struct Sampler<ST_U8B, LAYOUT_BRICKS> {
         const uint32_t lz = iz - ((uint32_t)cz << vol.bshift);
         const uint32_t bid =
             __umul24(__umul24((uint32_t)cz, (uint32_t)vol.nb[1]) + (uint32_t)cy, (uint32_t)vol.nb[0]) + (uint32_t)cx;
-        const uint32_t off = __umul24(bid, vol.brick_bytes) + __umul24(lz, vol.sz) + __umul24(ly, vol.sy) + lx;
+        // as for the linear grid: keep every corner (scalar offsets) inside the buffer
+        const uint32_t off = min(__umul24(bid, vol.brick_bytes) + __umul24(lz, vol.sz) + __umul24(ly, vol.sy) + lx,
+                                 vol.data_bytes - (vol.sz + vol.sy + 2u));
         using E = Elem<ST_U8>;
         Raw w;
         w.c[0] = E::load(r, off, 0);
