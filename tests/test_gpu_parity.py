@@ -362,6 +362,33 @@ def test_u8_brick_storage_render(rt, torch_mod, orc, brain, layout, B):
     check(got, ref, c, f"u8 bricks {layout} B={B}")
 
 
+
+@pytest.mark.parametrize("storage", ["F16", "U8_BRICKSCALED"])
+def test_precision_orbit_full_size_sampled(rt, torch_mod, orc, brain, storage):
+    """The reduced-precision workload at its full size: 8 orbit views of the
+    brain phantom at 1024x1024, step 0.25 voxel, in one batch plan, from half
+    cells or 8-bit brick codes (B = 16); 768 pixels per view against the oracle
+    on the stored field."""
+    torch = torch_mod
+    v = brain["np"]
+    if storage == "F16":
+        gv = rt.Volume(v, brain["sp"], storage=rt.F16)
+        ov = orc.Volume(v.astype(np.float16).astype(np.float64), brain["sp"])
+    else:
+        gv = rt.Volume(v, brain["sp"], storage=rt.U8_BRICKSCALED, brick=16)
+        ov = orc.Volume.from_u8_bricks(v, brain["sp"], 16)
+    cams = W.orbit_cameras(brain["dims"], brain["sp"], 8)
+    pix = [torch.zeros((1024, 1024), dtype=torch.int32, device="cuda") for _ in cams]
+    jobs = [rt.Job(gv, brain["gtf"], c, 1024, 1024, 0.25, 0.99, pixel_counts=p) for c, p in zip(cams, pix)]
+    rt.BatchPlan(len(jobs), getattr(rt, storage)).launch(jobs)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(79)
+    for vi, (cam, j, p) in enumerate(zip(cams, jobs, pix)):
+        px = rng.choice(1024 * 1024, size=768, replace=False)
+        ref = orc.render(ov, brain["otf"], cam, 1024, 1024, 0.25, 0.99, pixels=px, tie_delta=DELTA, want_band=True)
+        got = j.out.cpu().numpy().astype(np.float64).reshape(-1, 4)[px]
+        check(got, ref, p.cpu().numpy().reshape(-1)[px], f"{storage} 1024x1024 view {vi}")
+
 @pytest.mark.parametrize("B", [8, 16])
 def test_u8_brick_cells_codes_bit_exact(rt, torch_mod, orc, B):
     """Every stored cell carries its 8 corner codes from the owning brick's
@@ -572,6 +599,43 @@ def test_u12_brain_views_match_oracle(rt, torch_mod, orc, brain):
         u16, _ = gpu_render(rt, torch_mod, brain["gv"], brain["gtf"], cam, 512, 512, 0.5, 0.99)
         assert np.abs(got - u16)[(ref.tie & 1) == 0].max() <= TOL
 
+
+
+def test_timed_orbit_launch_matches_oracle(rt, torch_mod, orc, brain):
+    """The launch the throughput figure times: all 36 orbit views in one
+    graph-captured batch plan over 12-bit half cells, 4x16-pixel tiles and 16
+    wavefronts per workgroup.  Sampled pixels and their sample counts against
+    the oracle, the launch-wide counter against the per-pixel counts, and the
+    non-counting form (the one timed) bitwise equal to the counting one."""
+    torch = torch_mod
+    gv = rt.Volume(brain["np"], brain["sp"], storage=rt.U12)
+    cams = brain["cams"]
+    plan = rt.BatchPlan(len(cams), rt.U12, tile=(4, 16), waves_per_block=16)
+    pix = [torch.zeros((512, 512), dtype=torch.int32, device="cuda") for _ in cams]
+    counted = [rt.Job(gv, brain["gtf"], c, 512, 512, 0.5, 0.99, pixel_counts=p) for c, p in zip(cams, pix)]
+    counter = torch.zeros(1, dtype=torch.int64, device="cuda")
+    plan.launch(counted, sample_counter=counter)
+    torch.cuda.synchronize()
+    total = int(counter.item())
+    assert total == sum(int(p.to(torch.int64).sum()) for p in pix)
+    timed = [rt.Job(gv, brain["gtf"], c, 512, 512, 0.5, 0.99) for c in cams]
+    for _ in range(2):
+        for j in timed:
+            j.out.fill_(-1.0)
+        plan.launch(timed)
+        torch.cuda.synchronize()
+        for a, b in zip(counted, timed):
+            assert torch.equal(a.out, b.out)
+    rng = np.random.default_rng(78)
+    worst = 0.0
+    for vi, (cam, j, p) in enumerate(zip(cams, counted, pix)):
+        px = rng.choice(512 * 512, size=1024, replace=False)
+        ref = orc.render(brain["ov"], brain["otf"], cam, 512, 512, 0.5, 0.99, pixels=px, tie_delta=DELTA,
+                         want_band=True)
+        got = j.out.cpu().numpy().astype(np.float64).reshape(-1, 4)[px]
+        w, _ = check(got, ref, p.cpu().numpy().reshape(-1)[px], f"timed orbit launch, view {vi}")
+        worst = max(worst, w)
+    print(f"timed orbit launch: {total} samples, sampled worst band distance {worst:.3g}")
 
 @pytest.mark.parametrize("seed", range(6))
 def test_u12_random_small_cases(rt, torch_mod, orc, seed):
