@@ -171,6 +171,19 @@ def _timed(fn, steps, warmup):
     return e0.elapsed_time(e1) / steps
 
 
+def _limiter(form, storage):
+    """What bounds the timed kernel, with the profile summary that shows it."""
+    if form in ("batch", "graph", "skip"):
+        # the caches serve two thirds of the logical gathers, so the fraction
+        # can exceed 1; what binds is vector-instruction issue
+        text, prof = "VALU issue (VALUBusy ~97 %", f"profiles/march_batch_{storage}_brain_orbit.md"
+    else:
+        # one launch per view: the longest ray's own instruction stream
+        text, prof = "the longest ray of each lone view (one launch per view", f"profiles/march_plain_{storage}_brain_orbit_views.md"
+    here = os.path.dirname(os.path.abspath(__file__))
+    return text + (f", see {prof})" if os.path.exists(os.path.join(here, prof)) else ")")
+
+
 def _count(rt, jobs):
     import torch
     counter = torch.zeros(1, dtype=torch.int64, device="cuda")
@@ -784,10 +797,7 @@ def main():
                      "kernel": ("march_batch_kernel<" if best in ("batch", "graph", "skip") else "march_plain_kernel<")
                                + args.storage + ">",
                      "algorithmic_bytes_per_launch": int(bytes_per_launch),
-                     # the caches serve two thirds of the logical gathers, so the
-                     # fraction can exceed 1; what binds is vector-instruction issue
-                     "limiter": "VALU issue (VALUBusy ~97 %, see profiles/march_batch_" + args.storage
-                                + "_brain_orbit.md)"},
+                     "limiter": _limiter(best, args.storage)},
     }
     if line["roofline"] is not None and not args.only:  # what a plain device copy achieves on this GPU
         line["roofline"]["achievable_copy_GBps"] = round(probe_copy(1.0, 10, quiet=True), 1)
