@@ -97,6 +97,18 @@ def test_volume_bytes(rt):
         r256(r256(r256(ncb * 8) + ncb * 64) + nb * 8)
 
 
+def test_cell_layout_size_limits(rt):
+    """2^24 blocks of 2x2x2 cells at most, and block strides below 2^24: the
+    largest accepted grids and the first refused ones."""
+    for st, b in ((rt.U12, 128), (rt.U16, 128), (rt.F32, 256)):
+        assert rt.rt_volume_bytes((508, 510, 510), st) >= 255 * 256 * 256 * b
+        with pytest.raises(rt.Unsupported):
+            rt.rt_volume_bytes((510, 510, 510), st)
+    rt.rt_volume_bytes((4092, 2046, 2), rt.U16)           # 8 * 2047 * 1024 < 2^24
+    with pytest.raises(rt.Unsupported):
+        rt.rt_volume_bytes((4094, 2046, 2), rt.U16)       # 8 * 2048 * 1024 = 2^24
+
+
 @pytest.mark.parametrize("dims,storage,layout,brick,exc", [
     ((1, 4, 4), 1, 0, 0, "InvalidArgument"),
     ((4, 4, 4), 4, 0, 12, "InvalidArgument"),

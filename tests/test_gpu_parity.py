@@ -389,6 +389,52 @@ def test_precision_orbit_full_size_sampled(rt, torch_mod, orc, brain, storage):
         got = j.out.cpu().numpy().astype(np.float64).reshape(-1, 4)[px]
         check(got, ref, p.cpu().numpy().reshape(-1)[px], f"{storage} 1024x1024 view {vi}")
 
+
+@pytest.fixture(scope="module")
+def largest(rt, orc):
+    """The largest grid of the cell layout, 508 x 510 x 510 nodes (255 x 256 x
+    256 blocks of 2x2x2 cells, one block short of the 2^24 the layout takes):
+    a separable smooth field plus separable integer noise, cheap at 132 M
+    nodes, and the oracle's view of it."""
+    dims, sp = (508, 510, 510), (1.0, 1.0, 1.0)
+    ax = [np.arange(n, dtype=np.float32) for n in dims]
+    smooth = (np.sin(ax[2] / 29.0 + 0.5)[:, None, None] * np.cos(ax[1] / 23.0)[None, :, None]
+              * (1500.0 * np.sin(ax[0] / 17.0)).astype(np.float32)[None, None, :])
+    hrng = np.random.default_rng(81)
+    hz, hy, hx = (hrng.integers(0, 81, size=n).astype(np.int16) for n in dims[::-1])
+    noise = (hz[:, None, None] + hy[None, :, None]) + hx[None, None, :]
+    v = (np.rint(smooth).astype(np.int16) + (noise % 81 - 40) + 2048).astype(np.uint16)
+    del smooth, noise
+    return dims, sp, v, orc.Volume(v, sp)
+
+
+@pytest.mark.parametrize("storage", ["U12", "F32"])
+def test_largest_cell_volume(rt, torch_mod, orc, largest, storage):
+    """Cell offsets of the largest grid reach 2^31 bytes (12-bit cells) and
+    2^32 bytes (binary32 cells).  Rays through the far corner, where the
+    offsets are largest, and through the whole volume, from one launch and
+    from a batch, against the oracle on sampled pixels."""
+    torch = torch_mod
+    dims, sp, v, ov = largest
+    st = getattr(rt, storage)
+    assert rt.rt_volume_bytes(dims, st) >= (1 << (32 if storage == "F32" else 31)) - (1 << 26)
+    gv = rt.Volume(v, sp, storage=st)
+    t = W.random_tf(4096, 33, alpha_max=0.05)
+    gtf, otf = rt.TransferFunction(t, 0, 4095), orc.TF(t, 0, 4095)
+    hi = np.array([(n - 1) * s for n, s in zip(dims, sp)])
+    corner = Camera(tuple(hi + np.array([90.0, 70.0, 60.0])), tuple(hi - 60.0), (0, 0, 1), True, 40.0)
+    cams = [corner, W.orbit_cameras(dims, sp, 8)[3]]
+    rng = np.random.default_rng(80)
+    for ci, cam in enumerate(cams):
+        got, c = gpu_render(rt, torch, gv, gtf, cam, 192, 160, 0.5, 0.99)
+        out = rt.render_batch([rt.Job(gv, gtf, cam, 192, 160, 0.5, 0.99)])[0]
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy().astype(np.float64), got)
+        assert (c > 0).mean() > 0.3
+        px = rng.choice(192 * 160, size=400, replace=False)
+        ref = orc.render(ov, otf, cam, 192, 160, 0.5, 0.99, pixels=px, tie_delta=DELTA, want_band=True)
+        check(got.reshape(-1, 4)[px], ref, c.reshape(-1)[px], f"{storage} largest cell volume, camera {ci}")
+
 @pytest.mark.parametrize("B", [8, 16])
 def test_u8_brick_cells_codes_bit_exact(rt, torch_mod, orc, B):
     """Every stored cell carries its 8 corner codes from the owning brick's
