@@ -152,6 +152,10 @@ def test_null_arguments_are_reported_not_fatal(rt):
     sp = (C.c_double * 3)(1, 1, 1)
     assert L.rt_create_volume(None, 1, dims, sp, 1, 0, 0, None, 0, None, C.byref(h)) == 1
     assert L.rt_render_batch(None, 0, None, 0, None, None, None) == 1
+    # one job past the largest batch is refused before the jobs are looked at
+    over = (rt.rt_render_job * 4097)()
+    assert L.rt_render_batch(over, 4097, C.c_void_p(4096), 1 << 30, None, None, None) == 4
+    assert b"too many jobs" in L.rt_last_error()
     assert L.rt_batch_plan_launch(None, None, 0, None, None) == 1
     assert L.rt_destroy_volume(None) == 0 and L.rt_destroy_tf(None) == 0 and L.rt_batch_plan_destroy(None) == 0
     assert L.rt_status_string(2) == b"buffer too small"

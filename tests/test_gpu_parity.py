@@ -511,6 +511,45 @@ def test_batch_and_plan_bitwise_equal_plain(rt, torch_mod, small, brain):
             assert int(c2.item()) == n1
 
 
+
+def test_largest_batch_and_widest_images(rt, torch_mod, orc, small):
+    """4096 jobs, the most a batch takes (tiny images, random cameras, three
+    tables), from a one-off launch and a plan, bitwise equal to one launch per
+    view, with the launch-wide counter equal to the per-view counts; and images
+    32768 pixels wide or high, the largest side, against the oracle."""
+    torch = torch_mod
+    rng = np.random.default_rng(82)
+    dims, sp = (64, 64, 32), (1, 1, 2)
+    tfs = [rt.TransferFunction(W.random_tf(256, 40 + k, alpha_max=0.4), 0, 255) for k in range(3)]
+    specs = [(W.random_camera(rng, dims, sp), int(rng.integers(1, 6)), int(rng.integers(1, 5)), k % 3)
+             for k in range(4096)]
+    pix = [torch.zeros((h, w), dtype=torch.int32, device="cuda") for _, w, h, _ in specs]
+    jobs = [rt.Job(small["gv"], tfs[t], cam, w, h, 0.5, 0.99, pixel_counts=p) for (cam, w, h, t), p in zip(specs, pix)]
+    counter = torch.zeros(1, dtype=torch.int64, device="cuda")
+    rt.render_batch(jobs, sample_counter=counter)
+    plan = rt.BatchPlan(4096, rt.U8)
+    pj = [rt.Job(small["gv"], tfs[t], cam, w, h, 0.5, 0.99) for cam, w, h, t in specs]
+    c2 = torch.zeros(1, dtype=torch.int64, device="cuda")
+    plan.launch(pj, sample_counter=c2)
+    torch.cuda.synchronize()
+    assert int(counter.item()) == sum(int(p.sum()) for p in pix) == int(c2.item())
+    assert all(torch.equal(a.out, b.out) for a, b in zip(jobs, pj))
+    for k in range(0, 4096, 16):  # one launch per view, every 16th job
+        cam, w, h, t = specs[k]
+        ref, cnt = gpu_render(rt, torch, small["gv"], tfs[t], cam, w, h, 0.5, 0.99)
+        assert np.array_equal(jobs[k].out.cpu().numpy().astype(np.float64), ref)
+        assert np.array_equal(pix[k].cpu().numpy(), cnt)
+    with pytest.raises(rt.Unsupported):  # one job more than a batch takes, refused before any device work
+        rt.render_batch(jobs + jobs[:1], workspace=plan.ws)
+    c = W.box_center(dims, sp)
+    for Wd, Hd in ((32768, 2), (2, 32768)):
+        hh = 40.0 * min(1.0, Hd / Wd)  # the wider side spans 80 mm
+        cam = Camera(tuple(c + np.array([0.0, -120.0, 15.0])), tuple(c), (0, 0, 1), False, 0.0, hh)
+        got, cnt = gpu_render(rt, torch, small["gv"], small["gtf"], cam, Wd, Hd, 0.5, 0.99)
+        ref = orc.render(small["ov"], small["otf"], cam, Wd, Hd, 0.5, 0.99, tie_delta=DELTA, want_band=True)
+        check(got, ref, cnt, f"{Wd}x{Hd}")
+        assert (cnt > 0).mean() > 0.5
+
 # ---------------------------------------------------------------------------
 # error paths that need live handles
 # ---------------------------------------------------------------------------
