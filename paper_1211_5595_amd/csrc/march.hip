@@ -38,7 +38,37 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, uint3
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, kRsrcWord3);
 }
 
-// Per-lane state after the ray set-up.
+// Member-wise copy of a volume description from any address space (the
+// fields that are not used afterwards cost nothing).
+template <class T>
+__device__ __forceinline__ VolDev copy_vol(const T& v) {
+    VolDev o;
+    o.data = v.data;
+    o.brick_par = v.brick_par;
+    o.data_bytes = v.data_bytes;
+    o.sy = v.sy;
+    o.sz = v.sz;
+    o.brick_bytes = v.brick_bytes;
+    for (int a = 0; a < 3; ++a) {
+        o.n[a] = v.n[a];
+        o.nb[a] = v.nb[a];
+        o.enb[a] = v.enb[a];
+        o.snb[a] = v.snb[a];
+    }
+    o.bshift = v.bshift;
+    o.kind = v.kind;
+    o.layout = v.layout;
+    o.ess_range = v.ess_range;
+    o.eshift = v.eshift;
+    o.esy = v.esy;
+    o.esz = v.esz;
+    o.ess_super = v.ess_super;
+    o.ssy = v.ssy;
+    o.ssz = v.ssz;
+    return o;
+}
+
+// Per-lane state after the ray set-up.// Per-lane state after the ray set-up.
 struct Ray {
     long long Q[3];   // padded index-space position of the next full sample, 32.32 fixed point
     long long dQ[3];  // increment per sample
@@ -785,6 +815,13 @@ __device__ __forceinline__ void march_pixel(const VD& V, const float4* __restric
                     if (__builtin_amdgcn_ballot_w64(live) == 0) break;
                 }
             }
+            // The cell strides and the buffer bound pinned in scalar registers:
+            // left to the compiler they are reloaded from the view description
+            // in every iteration, a scalar load the next cell request waits for.
+            VolDev vol = copy_vol(V.vol);
+            asm volatile("" : "+s"(vol.sy), "+s"(vol.sz));
+            __amdgpu_buffer_rsrc_t rsp = rs;
+            asm volatile("" : "+s"(rsp));
             for (; !PREFETCH;) {
                 if constexpr (SKIP) {
                     // all live rays of the wavefront in empty bricks: each leaps to
@@ -798,7 +835,7 @@ __device__ __forceinline__ void march_pixel(const VD& V, const float4* __restric
                         continue;
                     }
                     if (stale) {
-                        cur = S::load(rs, V.vol, cn, R.Q);
+                        cur = S::load(rsp, vol, cn, R.Q);
                         stale = false;
                     }
                 }
@@ -816,7 +853,7 @@ __device__ __forceinline__ void march_pixel(const VD& V, const float4* __restric
                 R.Q[0] += R.dQ[0];
                 R.Q[1] += R.dQ[1];
                 R.Q[2] += R.dQ[2];
-                cur = S::load(rs, V.vol, cn, R.Q);
+                cur = S::load(rsp, vol, cn, R.Q);
             }
         }
         if (R.wp > 0.0f && T > thr) {
