@@ -123,6 +123,49 @@ def cpu_baseline(vol_np, tf_np, cams, spacing, width, height, step, cutoff, vmax
                             "sample": "orbit view 0, whole image", "seconds": dt1}}
 
 
+def small_config(reps=200):
+    """The small correctness workload (the 64x64x32 8-bit phantom, one
+    orthographic 128x128 view, step 0.5, cutoff 0.99): the GPU's single-view
+    time (HIP events around each launch, p50 over reps) and the oracle's on
+    the same view, all host threads."""
+    import torch
+
+    import oracle
+    import paper_1211_5595_amd as rt
+    import workloads as W
+
+    cfg = W.CONFIG_SMALL
+    vs, ts = cfg["volume"], cfg["tf"]
+    width, height, step, cutoff = cfg["width"], cfg["height"], cfg["step_vox"], cfg["cutoff"]
+    v = W.phantom_small(vs.seed, dims=vs.dims, spacing=vs.spacing)
+    t = W.random_tf(ts.K, ts.seed, alpha_max=ts.alpha_max)
+    cam = W.ortho_camera_small(vs.dims, vs.spacing)
+    vol = rt.Volume(v, vs.spacing, storage=rt.U8)
+    tf = rt.TransferFunction(t, ts.vmin, ts.vmax)
+    counter = torch.zeros(1, dtype=torch.int64, device="cuda")
+    out = rt.render(vol, tf, cam, width, height, step, cutoff, sample_counter=counter)
+    torch.cuda.synchronize()
+    samples = int(counter.item())
+    stream = torch.cuda.current_stream()
+    lat = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        rt.render(vol, tf, cam, width, height, step, cutoff, out=out)
+        e1.record(stream)
+        e1.synchronize()
+        lat.append(e0.elapsed_time(e1))
+    p50 = percentile(lat, 50)
+    V, T = oracle.Volume(v, vs.spacing), oracle.TF(t, ts.vmin, ts.vmax)
+    t0 = time.perf_counter()
+    r = oracle.render(V, T, cam, width, height, step, cutoff)
+    dt = time.perf_counter() - t0
+    return {"workload": "small-64x64x32-u8-ortho-128x128", "samples": samples,
+            "gpu_p50_ms": p50, "gpu_gsamples_per_s": round(samples / (p50 * 1e-3) / 1e9, 3),
+            "cpu_oracle_ms": round(dt * 1e3, 3), "cpu_gsamples_per_s": round(int(r.counts.sum()) / dt / 1e9, 4),
+            "cpu_cores": oracle.max_threads(), "oracle_samples": int(r.counts.sum())}
+
+
 def _cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as f:
@@ -250,6 +293,7 @@ def bench_precision(args):
     tf = rt.TransferFunction(tf_np, ts.vmin, ts.vmax)
     otf = oracle.TF(tf_np, ts.vmin, ts.vmax)
     err_views = [0, 3]
+    cpu = None
     ref_u16 = {}
     results = {}
     for name, storage, brick, elem_bytes in [("u16", rt.U16, 0, 2), ("u12", rt.U12, 0, 2), ("f16", rt.F16, 0, 2),
@@ -269,6 +313,13 @@ def bench_precision(args):
             ofield = oracle.Volume.from_u8_bricks(vol_np, vs.spacing, 16)
         plan.launch(jobs)
         torch.cuda.synchronize()
+        if name == "u16":  # the oracle's own time on one whole view of this workload, all host threads
+            t0 = time.perf_counter()
+            r0 = oracle.render(ofield, otf, cams[0], size, size, step, cutoff)
+            dt0 = time.perf_counter() - t0
+            cpu = {"value": round(int(r0.counts.sum()) / dt0 / 1e9, 4), "unit": "Gsamples/s",
+                   "cores": oracle.max_threads(), "kind": "oracle", "seconds": round(dt0, 3),
+                   "sample": f"view 0, whole {size}x{size} image, 16-bit field"}
         arith_max, arith_sum, stor_max, stor_sum, npx = 0.0, 0.0, 0.0, 0.0, 0
         for vi in err_views:
             got = outs[vi].cpu().numpy().astype(np.float64)
@@ -297,7 +348,7 @@ def bench_precision(args):
                      {"workload": "brain-precision-8x1024x1024-step0.25", "volume": list(vs.dims),
                       "views": n_views, "image": [size, size], "step_vox": step, "alpha_cutoff": cutoff,
                       "tf_entries": ts.K, "storage": ["u16", "u12", "f16", "u8_brick16"], "launch": "graph"},
-                     by_storage=results)
+                     by_storage=results, cpu_baseline=cpu)
     print(json.dumps(line), flush=True)
 
 
@@ -828,6 +879,7 @@ def main():
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(vol_np, tf_np, cams, vs.spacing, width, height, step, cutoff, ts.vmax,
                                             args.cpu_budget)
+        line["small_config"] = small_config()
     print(json.dumps(line), flush=True)
 
 
