@@ -3,8 +3,9 @@
 Every served image must equal, bit for bit, the image rt_render gives for the
 same request alone: in a mixed stream of volumes, image sizes, tables of
 different sizes and ray functions; under an image pool so small that requests
-wait for memory (first come, first served); and after requests fail or the
-server shuts down with work queued.
+wait for memory (first come, first served); with several client threads
+calling at once; and after requests fail or the server shuts down with work
+queued.
 """
 import time
 
@@ -191,3 +192,50 @@ def test_shutdown_finishes_work_and_fails_what_cannot_run(rt, torch_mod, vols):
     for k in range(20):
         srv2.submit(RenderRequest(0, cams[k % 3], 128, 96, W.random_tf(256, k)))
     srv2.close()                                  # returns once all 20 have rendered
+
+
+def test_concurrent_clients(rt, torch_mod, vols):
+    """Four client threads submit, wait for and release their own requests at
+    the same time (the C calls run without the interpreter lock), through a
+    pool that holds only some of the images at once: every image equals the
+    request rendered alone and the counters balance."""
+    import threading
+
+    from paper_1211_5595_amd.serve import NativeServer
+    torch = torch_mod
+    srv = NativeServer(4 << 20, n_streams=3, max_batch=8, storage=rt.U12)
+    for i, (v, sp) in enumerate(vols):
+        srv.add_volume(i, v, sp)
+    per = [make_requests(rt, vols, 30, 60 + c) for c in range(4)]
+    out = [[None] * 30 for _ in range(4)]
+    errors = []
+
+    def client(c):
+        try:
+            tickets = []
+            for k, r in enumerate(per[c]):
+                tickets.append(srv.submit(r))
+                if k % 4 == 3:  # collect in bursts, oldest first
+                    while tickets:
+                        j = k + 1 - len(tickets)
+                        out[c][j] = srv.result(tickets.pop(0), per[c][j].width, per[c][j].height)
+            for j in range(30 - len(tickets), 30):
+                out[c][j] = srv.result(tickets.pop(0), per[c][j].width, per[c][j].height)
+        except Exception as e:  # reported by the main thread
+            errors.append(e)
+
+    threads = [threading.Thread(target=client, args=(c,)) for c in range(4)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join(timeout=120)
+    assert not any(t.is_alive() for t in threads), "a client thread did not finish"
+    assert not errors, errors
+    st = srv.stats()
+    assert st.submitted == 120 and st.completed == 120 and st.failed == 0
+    assert st.pool_in_use == 0 and st.queued == 0 and st.running == 0
+    assert st.pool_peak <= st.pool_bytes
+    for c in range(4):
+        for r, img in zip(per[c], out[c]):
+            assert torch.equal(img, alone(rt, torch, srv, r))
+    srv.close()
