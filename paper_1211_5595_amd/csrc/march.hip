@@ -1287,10 +1287,6 @@ hipError_t skip_range_launch(const VolDev& vol, hipStream_t s) {
     return hipGetLastError();
 }
 
-__global__ void batch_reset_kernel(unsigned int* queue) {
-    if (threadIdx.x == 0) *queue = 0u;
-}
-
 int log2i(int x) {
     int s = 0;
     while ((1 << s) < x) ++s;
@@ -1423,11 +1419,6 @@ hipError_t launch_march_batch(int kind, int layout, void* workspace, int grid, c
             return C ? batch_launch<ST_U12, LAYOUT_CELLS>(workspace, grid, ls, max_k, skip, s) : hipErrorInvalidValue;
         default: return hipErrorInvalidValue;
     }
-}
-
-hipError_t launch_batch_reset(void* workspace, hipStream_t s) {
-    hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, s, static_cast<unsigned int*>(workspace));
-    return hipGetLastError();
 }
 
 int batch_persistent_grid(const LaunchShape& ls, int max_k) {

@@ -782,8 +782,9 @@ rt_status rt_batch_plan_create(int max_jobs, int storage, int layout, void* work
         delete p;
         return hip_fail(e, "hipStreamCreate");
     }
+    // The graph holds the kernel alone: each launch first copies the job
+    // table, whose header starts the block queue at zero.
     e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-    if (e == hipSuccess) e = launch_batch_reset(workspace, cs);
     if (e == hipSuccess)
         e = launch_march_batch(p->kind / 4, p->kind % 4, workspace, p->grid, ls, kMaxK, opts && opts->skip_empty, cs);
     hipGraph_t g = nullptr;
