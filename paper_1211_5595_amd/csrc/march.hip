@@ -926,10 +926,14 @@ __device__ __forceinline__ void project_pixel(const VD& V, const float4* __restr
         return;
     }
     if (R.m > 0) {
-        typename S::Raw cur = S::load(rs, V.vol, cn, R.Q);
+        VolDev vol = copy_vol(V.vol);  // strides and bound pinned, as in march_pixel
+        asm volatile("" : "+s"(vol.sy), "+s"(vol.sz));
+        __amdgpu_buffer_rsrc_t rsp = rs;
+        asm volatile("" : "+s"(rsp));
+        typename S::Raw cur = S::load(rsp, vol, cn, R.Q);
         for (;;) {
             const long long Qn[3] = {R.Q[0] + R.dQ[0], R.Q[1] + R.dQ[1], R.Q[2] + R.dQ[2]};
-            const typename S::Raw nxt = S::load(rs, V.vol, cn, Qn);
+            const typename S::Raw nxt = S::load(rsp, vol, cn, Qn);
             const float val = S::value(cur, frac32(R.Q[0]), frac32(R.Q[1]), frac32(R.Q[2]));
             if (RED == RF_MAX) {
                 acc = fmaxf(acc, val);
@@ -987,10 +991,14 @@ __device__ __forceinline__ void iso_pixel(const VD& V, const float4* __restrict_
     long long P1[3] = {R.Q[0], R.Q[1], R.Q[2]};  // hit sample
     long long P0[3] = {0, 0, 0};                 // the sample before it
     if (R.m > 0) {
-        typename S::Raw cur = S::load(rs, V.vol, cn, R.Q);
+        VolDev vol = copy_vol(V.vol);  // strides and bound pinned, as in march_pixel
+        asm volatile("" : "+s"(vol.sy), "+s"(vol.sz));
+        __amdgpu_buffer_rsrc_t rsp = rs;
+        asm volatile("" : "+s"(rsp));
+        typename S::Raw cur = S::load(rsp, vol, cn, R.Q);
         for (;;) {
             const long long Qn[3] = {R.Q[0] + R.dQ[0], R.Q[1] + R.dQ[1], R.Q[2] + R.dQ[2]};
-            const typename S::Raw nxt = S::load(rs, V.vol, cn, Qn);
+            const typename S::Raw nxt = S::load(rsp, vol, cn, Qn);
             const float val = S::value(cur, frac32(R.Q[0]), frac32(R.Q[1]), frac32(R.Q[2]));
             if (val >= iso) {
                 hit = true;
