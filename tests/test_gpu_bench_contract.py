@@ -1,0 +1,44 @@
+"""bench.py's output line on the GPU: the fields and their consistency (one
+short run at a pinned launch shape, with the oracle's CPU baseline)."""
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_orbit_line_fields_and_consistency():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--steps", "3", "--warmup", "1",
+                        "--shape", "4x16x16", "--cpu-budget", "2"], capture_output=True, text=True, timeout=600)
+    assert r.returncode == 0, r.stderr[-2000:]
+    line = json.loads(r.stdout.strip().splitlines()[-1])
+    for k, v in (("n_gpus", 1), ("steps", 3), ("warmup", 1), ("higher_is_better", True), ("scaling", "weak"),
+                 ("vs_baseline", None), ("data", "synthetic"), ("unit", "Gsamples/s")):
+        assert line[k] == v, k
+    assert line["config"]["workload"] == "brain-orbit-36x512x512-u16"
+    assert line["config"]["tile"] == [4, 16] and line["config"]["waves_per_block"] == 16
+    samples, ms = line["samples_per_step"], line["ms_per_step"]
+    assert samples > 0 and ms > 0
+    assert abs(line["value"] - samples / (ms * 1e-3) / 1e9) <= 1e-3 * line["value"] + 1e-3
+    assert abs(line["fps"] - 36 / (ms * 1e-3)) <= 1e-3 * line["fps"] + 0.1
+    rf = line["roofline"]
+    assert rf["bound"] == "hbm" and rf["unit"] == "GB/s" and rf["peak"] == 8000.0
+    assert rf["algorithmic_bytes_per_launch"] == samples * 16 + 36 * 512 * 512 * 16
+    assert abs(rf["achieved"] - rf["algorithmic_bytes_per_launch"] / (ms * 1e-3) / 1e9) <= 0.1 + 1e-3 * rf["achieved"]
+    assert abs(rf["frac"] - rf["achieved"] / rf["peak"]) <= 1e-3
+    assert rf["traffic"] is None or rf["traffic"] > 0
+    cb = line["cpu_baseline"]
+    assert cb["kind"] == "oracle" and cb["unit"] == "Gsamples/s" and cb["value"] > 0 and cb["cores"] >= 1
+    assert cb["sample"]
+    sk = line["skip_empty"]
+    assert sk["images_bitwise_equal"] is True and sk["ms_per_step"] > 0
+    sc = line["small_config"]
+    assert sc["samples"] == sc["oracle_samples"] > 0
