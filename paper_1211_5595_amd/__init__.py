@@ -496,11 +496,15 @@ _ws_cache = {}
 
 def render_batch(jobs: Sequence[Job], sample_counter=None, workspace=None, tile=(0, 0), waves_per_block=0,
                  stream=None, tile_order=0):
-    """Render all jobs in one persistent launch (job table copied per call)."""
+    """Render all jobs in one persistent launch (job table copied per call).
+    Without ``workspace``, one is kept per device, batch size and stream: calls
+    on one stream reuse it in stream order, and calls on different streams
+    never share one (a job table copied for one stream could otherwise land
+    while another stream's launch still reads the same memory)."""
     n = len(jobs)
     dev = jobs[0].out.device
     if workspace is None:
-        key = (str(dev), n)
+        key = (str(dev), n, _stream_ptr(stream).value)
         workspace = _ws_cache.get(key)
         if workspace is None:
             workspace = _ws_cache[key] = _Workspace(n, dev)

@@ -550,6 +550,24 @@ def test_largest_batch_and_widest_images(rt, torch_mod, orc, small):
         check(got, ref, cnt, f"{Wd}x{Hd}")
         assert (cnt > 0).mean() > 0.5
 
+
+def test_one_off_batches_on_two_streams(rt, torch_mod, brain):
+    """Batches of the same size issued on two streams without waiting for each
+    other: each stream has its own job table, so both render what was asked."""
+    torch = torch_mod
+    cams = brain["cams"]
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    torch.cuda.synchronize()
+    ja = [rt.Job(brain["gv"], brain["gtf"], c, 160, 120, 0.5, 0.99) for c in cams[0:4]]
+    jb = [rt.Job(brain["gv"], brain["gtf"], c, 160, 120, 0.5, 0.99) for c in cams[20:24]]
+    for _ in range(3):
+        rt.render_batch(ja, stream=s1)
+        rt.render_batch(jb, stream=s2)
+    torch.cuda.synchronize()
+    for j, cam in zip(ja + jb, cams[0:4] + cams[20:24]):
+        ref, _ = gpu_render(rt, torch, brain["gv"], brain["gtf"], cam, 160, 120, 0.5, 0.99)
+        assert np.array_equal(j.out.cpu().numpy().astype(np.float64), ref)
+
 # ---------------------------------------------------------------------------
 # error paths that need live handles
 # ---------------------------------------------------------------------------
