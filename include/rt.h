@@ -281,7 +281,8 @@ rt_status rt_batch_workspace_bytes(int max_jobs, size_t* bytes);
  * in one persistent launch that pulls
  * ray tiles from a device work queue.  Copies the job table into `workspace`
  * (>= rt_batch_workspace_bytes(n)) on `stream`; the job array may be reused
- * once the call returns.  Results are bitwise identical to rt_render of each
+ * once the call returns.  A workspace holds one batch at a time: batches that
+ * may run at once (on different streams) need workspaces of their own.  Results are bitwise identical to rt_render of each
  * view.  Errors: as rt_render, plus RT_ERR_OUT_OF_MEMORY (workspace too
  * small) and RT_ERR_UNSUPPORTED (mixed storage types or layouts). */
 rt_status rt_render_batch(const rt_render_job* jobs, int n, void* workspace, size_t ws_bytes,
