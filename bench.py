@@ -634,10 +634,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--probe-copy", action="store_true")
-    ap.add_argument("--no-autotune", action="store_true", help="orbit: keep the default 8x8 tiles, 16 waves")
+    ap.add_argument("--no-autotune", action="store_true", help="orbit: keep the default 8x8 tiles, 12 waves")
     ap.add_argument("--only", choices=["batch", "plain", "graph", "skip"], default=None,
                     help="time one launch form only (for profiling); skip = the graph form with empty-space "
                          "skipping")
+    ap.add_argument("--shape-skip", default=None, help="orbit: launch shape TWxTHxWAVES of the skipping form "
+                    "(default: --shape, or its own autotuned shape); up to 16 waves, against 12 for fixed steps")
     ap.add_argument("--shape", default=None, help="orbit: fixed launch shape TWxTHxWAVES (e.g. 4x16x16) "
                                                   "instead of the autotuner's")
     ap.add_argument("--ingest-traffic", default=None, metavar="DIR",
@@ -706,15 +708,19 @@ def main():
     outs = [torch.empty((height, width, 4), dtype=torch.float32, device="cuda") for _ in range(n_views)]
     jobs = [rt.Job(vol, tf, cam, width, height, step, cutoff, out=o) for cam, o in zip(cams, outs)]
     tuned = None
+    def parse_shape(text):
+        tw, th, wv = (int(x) for x in text.split("x"))
+        return dict(tile=(tw, th), waves_per_block=wv)
+
+    shape_skip = parse_shape(args.shape_skip) if args.shape_skip else None
     if args.shape:
-        tw, th, wv = (int(x) for x in args.shape.split("x"))
-        shape = dict(tile=(tw, th), waves_per_block=wv)
+        shape = parse_shape(args.shape)
     elif not args.no_autotune:
         from paper_1211_5595_amd import autotune
         tuned = autotune.tune_launch(vol, tf, cams, width, height, step, cutoff, reps=3)
         shape = dict(tile=tuple(tuned["tile"]), waves_per_block=tuned["waves_per_block"])
     else:
-        shape = dict(tile=(8, 8), waves_per_block=16)
+        shape = dict(tile=(8, 8), waves_per_block=12)
     plan = rt.BatchPlan(n_views, storage, layout=layout, **shape)
 
     # untimed counting pass, with per-pixel counts for the samples per hitting ray
@@ -758,7 +764,7 @@ def main():
 
     forms = {"batch": step_batch, "graph": step_graph, "plain": step_plain}
     if args.only == "skip":
-        plan_s = rt.BatchPlan(n_views, storage, layout=layout, skip_empty=True, **shape)
+        plan_s = rt.BatchPlan(n_views, storage, layout=layout, skip_empty=True, **(shape_skip or shape))
         jobs_s = [rt.Job(vol, tf, cam, width, height, step, cutoff, out=o, skip_empty=True)
                   for cam, o in zip(cams, outs)]
         forms = {"skip": lambda: plan_s.launch(jobs_s)}
@@ -800,7 +806,7 @@ def main():
 
     lat = []
     if not args.only:
-        lat = single_view_latency(rt.make_opts(**shape), outs)
+        lat = single_view_latency(rt.make_opts(), outs)  # rt_render's own default launch shape
 
     # roofline of the dominant kernel: algorithmic bytes = 8 trilinear corners
     # x 2 B per sample + 16 B per output pixel, per launch
@@ -856,8 +862,8 @@ def main():
     # composited-sample count, fewer samples gathered; reported beside the
     # fixed-step figure, never as it
     if not args.only:
-        shape_s = shape
-        if tuned is not None:
+        shape_s = shape_skip or shape
+        if tuned is not None and shape_skip is None:
             from paper_1211_5595_amd import autotune
             t_s = autotune.tune_launch(vol, tf, cams, width, height, step, cutoff, reps=3, skip_empty=True)
             shape_s = dict(tile=tuple(t_s["tile"]), waves_per_block=t_s["waves_per_block"])

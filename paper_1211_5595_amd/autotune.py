@@ -1,7 +1,7 @@
 """Autotuner for the marcher's launch shape and a volume's storage and layout.
 
 Tunables: the ray tile of one wavefront (8x8, 16x4, 4x16, 32x2 pixels), the
-wavefronts per workgroup (4, 8, 16) and, per volume at creation, the storage
+wavefronts per workgroup (4, 8, 12 for fixed steps; 4, 8, 16 with skipping) and, per volume at creation, the storage
 layout (cell-packed, polynomial cells for integer data, or linear; for 8-bit
 brick storage the brick edge 8, 16 or 32) or, for integer data, the storage
 type among the encodings that hold the grid exactly (tune_storage).  Tile shape and wavefronts never
@@ -22,7 +22,10 @@ import threading
 from typing import Callable, Dict, Iterable, List, Optional, Sequence, Tuple
 
 TILES: List[Tuple[int, int]] = [(8, 8), (16, 4), (4, 16), (32, 2)]
-WAVES: List[int] = [4, 8, 16]
+# wavefronts per workgroup: the fixed-step batched kernel takes at most 12,
+# the skipping one 16
+WAVES: List[int] = [4, 8, 12]
+WAVES_SKIP: List[int] = [4, 8, 16]
 DEFAULT_CACHE = os.environ.get("RT_AUTOTUNE_CACHE",
                                os.path.join(os.path.expanduser("~"), ".cache", "rtvol", "autotune.json"))
 
@@ -101,7 +104,7 @@ def _time_ms(fn, reps: int) -> float:
 
 
 def tune_launch(volume, tf, cameras, width: int, height: int, step_vox: float = 0.5, alpha_cutoff: float = 0.99,
-                reps: int = 3, tiles: Sequence[Tuple[int, int]] = TILES, waves: Sequence[int] = WAVES,
+                reps: int = 3, tiles: Sequence[Tuple[int, int]] = TILES, waves: Optional[Sequence[int]] = None,
                 cache: Optional[Cache] = None, force: bool = False, skip_empty: bool = False) -> dict:
     """Choose tile shape and wavefronts per workgroup for batched renders of
     `cameras` (representative views) of this volume at width x height (with
@@ -116,6 +119,8 @@ def tune_launch(volume, tf, cameras, width: int, height: int, step_vox: float = 
     outs = [torch.empty((height, width, 4), dtype=torch.float32, device=volume.buf.device) for _ in cameras]
     jobs = [Job(volume, tf, c, width, height, step_vox, alpha_cutoff, out=o, skip_empty=skip_empty)
             for c, o in zip(cameras, outs)]
+    if waves is None:
+        waves = WAVES_SKIP if skip_empty else WAVES
     cands = [(t, w) for t in tiles for w in waves]
     best, table = pick_best(cands, lambda c: _time_ms(lambda: render_batch(jobs, tile=c[0], waves_per_block=c[1]),
                                                       reps))

@@ -822,7 +822,56 @@ __device__ __forceinline__ void march_pixel(const VD& V, const float4* __restric
             asm volatile("" : "+s"(vol.sy), "+s"(vol.sz));
             __amdgpu_buffer_rsrc_t rsp = rs;
             asm volatile("" : "+s"(rsp));
-            for (; !PREFETCH;) {
+            if constexpr (!PREFETCH && !SKIP) {
+                // Fixed steps in the batched kernel: the cell of sample k+1 is
+                // requested before sample k is processed, so each load has a
+                // whole sample's work to arrive; the two cells alternate
+                // between two register sets (the loop is unrolled by two).  The
+                // request after a ray's last sample reads a cell one step past
+                // it, through the same bounded reads as every other cell, and
+                // is never used.
+                typename S::Raw wa = cur, wb;
+                for (;;) {
+                    long long Qn[3];
+#pragma unroll
+                    for (int q = 0; q < 3; ++q) Qn[q] = R.Q[q] + R.dQ[q];
+                    wb = S::load(rsp, vol, cn, Qn);
+                    {
+                        const float val = stored_value<S>(wa, frac32(R.Q[0]), frac32(R.Q[1]), frac32(R.Q[2]));
+                        float4 c = classify(s_tf, val, ta, tb, Km1);
+                        if (WINDOW && !in_window(val + bias, V)) c.w = 0.0f;
+                        const float Ta = T * c.w;
+                        asm volatile("" ::"v"(Ta));  // formed before T is overwritten: no copy of T
+                        Cr = fmaf(Ta, c.x, Cr);
+                        Cg = fmaf(Ta, c.y, Cg);
+                        Cb = fmaf(Ta, c.z, Cb);
+                        T = fmaf(-T, c.w, T);
+                        ++k;
+                        if (k >= R.m || T <= thr) break;
+                    }
+#pragma unroll
+                    for (int q = 0; q < 3; ++q) R.Q[q] = Qn[q];
+#pragma unroll
+                    for (int q = 0; q < 3; ++q) Qn[q] = R.Q[q] + R.dQ[q];
+                    wa = S::load(rsp, vol, cn, Qn);
+                    {
+                        const float val = stored_value<S>(wb, frac32(R.Q[0]), frac32(R.Q[1]), frac32(R.Q[2]));
+                        float4 c = classify(s_tf, val, ta, tb, Km1);
+                        if (WINDOW && !in_window(val + bias, V)) c.w = 0.0f;
+                        const float Ta = T * c.w;
+                        asm volatile("" ::"v"(Ta));  // formed before T is overwritten: no copy of T
+                        Cr = fmaf(Ta, c.x, Cr);
+                        Cg = fmaf(Ta, c.y, Cg);
+                        Cb = fmaf(Ta, c.z, Cb);
+                        T = fmaf(-T, c.w, T);
+                        ++k;
+                        if (k >= R.m || T <= thr) break;
+                    }
+#pragma unroll
+                    for (int q = 0; q < 3; ++q) R.Q[q] = Qn[q];
+                }
+            }
+            for (; !PREFETCH && SKIP;) {
                 if constexpr (SKIP) {
                     // all live rays of the wavefront in empty bricks: each leaps to
                     // its first sample outside its brick (or to the end of its ray)
@@ -1135,9 +1184,13 @@ __device__ __forceinline__ int xcd_remap(int b, int n) {
     return x * per + min(x, rem) + idx;
 }
 
-// Occupancy: at least 8 waves per SIMD (two 1024-lane workgroups per CU),
-// which caps the marcher at 64 VGPRs.
-#define RT_MARCH_ATTRS __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8)))
+// Occupancy of the batched kernels.  Fixed-step marching: 12-wavefront
+// workgroups, two per CU (6 waves per SIMD, up to 80 VGPRs), which leaves the
+// registers to keep the next sample's cell in flight while the current one is
+// processed.  With empty-space skipping: 16-wavefront workgroups, two per CU
+// (8 waves per SIMD, 64 VGPRs).  Either way two workgroups share a CU's LDS.
+#define RT_BATCH_ATTRS __launch_bounds__(768) __attribute__((amdgpu_waves_per_eu(6)))
+#define RT_BATCH_SKIP_ATTRS __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8)))
 // The single-view kernel: one view of up to a few thousand wavefronts never
 // fills 8 per SIMD, so it may use the registers of 4 (its loads in flight).
 #define RT_PLAIN_ATTRS __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4)))
@@ -1169,8 +1222,8 @@ typedef __attribute__((address_space(4))) const int CInt;
 typedef __attribute__((address_space(4))) const BatchHeader CBatchHeader;
 
 template <int KIND, int LAYOUT, bool SKIP>
-__global__ void RT_MARCH_ATTRS march_batch_kernel(char* __restrict__ ws, const LaunchShape ls, int tw_shift,
-                                                   int tf_entries) {
+__device__ __forceinline__ void batch_body(char* __restrict__ ws, const LaunchShape& ls, int tw_shift,
+                                           int tf_entries) {
     extern __shared__ float4 s_tf[];
     uint32_t* s_mask = reinterpret_cast<uint32_t*>(s_tf + tf_entries);
     int* s_claim = reinterpret_cast<int*>(s_mask + kSkipMaskBytes / 4);
@@ -1221,6 +1274,18 @@ __global__ void RT_MARCH_ATTRS march_batch_kernel(char* __restrict__ ws, const L
         render_block<KIND, LAYOUT, SKIP, false, CViewDesc>(V, s_tf, s_mask, g - prefix[lo], ls, tw_shift, counter);
         __syncthreads();
     }
+}
+
+template <int KIND, int LAYOUT>
+__global__ void RT_BATCH_ATTRS march_batch_kernel(char* __restrict__ ws, const LaunchShape ls, int tw_shift,
+                                                  int tf_entries) {
+    batch_body<KIND, LAYOUT, false>(ws, ls, tw_shift, tf_entries);
+}
+
+template <int KIND, int LAYOUT>
+__global__ void RT_BATCH_SKIP_ATTRS march_batch_skip_kernel(char* __restrict__ ws, const LaunchShape ls,
+                                                            int tw_shift, int tf_entries) {
+    batch_body<KIND, LAYOUT, true>(ws, ls, tw_shift, tf_entries);
 }
 
 // Value range of every skip brick, one workgroup per brick: each of its
@@ -1326,12 +1391,18 @@ template <int KIND, int LAYOUT, bool SKIP>
 hipError_t batch_launch_k(void* ws, int grid, const LaunchShape& ls, int max_k, hipStream_t s) {
     const int tf_entries = max_k + 1;
     const size_t lds = (size_t)tf_entries * sizeof(float4) + kSkipMaskBytes + 16;
-    static const hipError_t attr = hipFuncSetAttribute((const void*)march_batch_kernel<KIND, LAYOUT, SKIP>,
-                                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+    const void* fn = SKIP ? (const void*)march_batch_skip_kernel<KIND, LAYOUT>
+                          : (const void*)march_batch_kernel<KIND, LAYOUT>;
+    static const hipError_t attr = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                                        (int)((kMaxK + 1) * sizeof(float4) + kSkipMaskBytes + 16));
     (void)attr;
-    hipLaunchKernelGGL((march_batch_kernel<KIND, LAYOUT, SKIP>), dim3(grid), dim3(64 * ls.waves), lds, s,
-                       static_cast<char*>(ws), ls, log2i(ls.tile_w), tf_entries);
+    if (ls.waves > (SKIP ? 16 : 12)) return hipErrorInvalidConfiguration;  // the shape checks refuse this first
+    if constexpr (SKIP)
+        hipLaunchKernelGGL((march_batch_skip_kernel<KIND, LAYOUT>), dim3(grid), dim3(64 * ls.waves), lds, s,
+                           static_cast<char*>(ws), ls, log2i(ls.tile_w), tf_entries);
+    else
+        hipLaunchKernelGGL((march_batch_kernel<KIND, LAYOUT>), dim3(grid), dim3(64 * ls.waves), lds, s,
+                           static_cast<char*>(ws), ls, log2i(ls.tile_w), tf_entries);
     return hipGetLastError();
 }
 
@@ -1429,15 +1500,16 @@ hipError_t launch_march_batch(int kind, int layout, void* workspace, int grid, c
     }
 }
 
-int batch_persistent_grid(const LaunchShape& ls, int max_k) {
+int batch_persistent_grid(const LaunchShape& ls, int max_k, bool skip) {
     int dev = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
     const size_t lds = (size_t)(max_k + 1) * sizeof(float4) + kSkipMaskBytes + 16;
-    (void)hipFuncSetAttribute((const void*)march_batch_kernel<ST_U16, LAYOUT_CELLS, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                        (int)((kMaxK + 1) * sizeof(float4) + kSkipMaskBytes + 16));
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)march_batch_kernel<ST_U16, LAYOUT_CELLS, false>,
-                                                     64 * ls.waves, lds) != hipSuccess)
+    const void* fn = skip ? (const void*)march_batch_skip_kernel<ST_U16, LAYOUT_CELLS>
+                          : (const void*)march_batch_kernel<ST_U16, LAYOUT_CELLS>;
+    (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)((kMaxK + 1) * sizeof(float4) + kSkipMaskBytes + 16));
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64 * ls.waves, lds) != hipSuccess)
         per_cu = 1;
     if (per_cu < 1) per_cu = 1;
     return cus * per_cu;

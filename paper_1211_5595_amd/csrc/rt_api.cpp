@@ -242,16 +242,20 @@ void cross(const double a[3], const double b[3], double c[3]) {
 }
 double norm(const double a[3]) { return std::sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]); }
 
+enum { LAUNCH_SINGLE = 0, LAUNCH_BATCH = 1, LAUNCH_BATCH_SKIP = 2 };
+
 void set_waves(LaunchShape& ls, int waves) {
     ls.waves = waves;
-    ls.bw = waves >= 4 ? (waves >= 16 ? 4 : (waves == 8 ? 4 : 2)) : waves;
+    ls.bw = waves >= 8 ? 4 : (waves == 4 ? 2 : waves);  // 8 = 4x2, 12 = 4x3, 16 = 4x4 tiles
     ls.bh = waves / ls.bw;
 }
 
-// single_view: the launch renders one view alone (rt_render), which decides
-// the default tile order.
-rt_status make_shape(const rt_render_opts* opts, bool single_view, LaunchShape& ls) {
-    int tw = 8, th = 8, waves = 16;
+// launch: LAUNCH_SINGLE (rt_render: spread tiles by default), LAUNCH_BATCH
+// (the fixed-step batched kernel: 12-wavefront workgroups by default, at most
+// 12) or LAUNCH_BATCH_SKIP (the batched kernel with empty-space skipping).
+rt_status make_shape(const rt_render_opts* opts, int launch, LaunchShape& ls) {
+    const bool single_view = launch == LAUNCH_SINGLE;
+    int tw = 8, th = 8, waves = launch == LAUNCH_BATCH ? 12 : 16;
     if (opts) {
         if (opts->tile_w || opts->tile_h) {
             tw = opts->tile_w;
@@ -265,8 +269,11 @@ rt_status make_shape(const rt_render_opts* opts, bool single_view, LaunchShape& 
     ls.order = order == 2 || (order == 0 && single_view) ? 1 : 0;  // 1 = spread
     if (tw <= 0 || th <= 0 || tw * th != 64 || (tw & (tw - 1)))
         return fail(RT_ERR_UNSUPPORTED, "tile must be tile_w x tile_h = 64 with tile_w a power of two");
-    if (waves != 1 && waves != 2 && waves != 4 && waves != 8 && waves != 16)
-        return fail(RT_ERR_UNSUPPORTED, "waves_per_block must be 1, 2, 4, 8 or 16");
+    if (waves != 1 && waves != 2 && waves != 4 && waves != 8 && waves != 12 && waves != 16)
+        return fail(RT_ERR_UNSUPPORTED, "waves_per_block must be 1, 2, 4, 8, 12 or 16");
+    if (launch == LAUNCH_BATCH && waves > 12)
+        return fail(RT_ERR_UNSUPPORTED, "a batched launch without empty-space skipping takes at most 12 waves per "
+                                        "workgroup");
     ls.tile_w = tw;
     ls.tile_h = th;
     set_waves(ls, waves);
@@ -501,7 +508,7 @@ int check_request(const rt_volume* vol, int K, double vmin, double vmax, const v
     probe.vmin = vmin;
     probe.vmax = vmax;
     LaunchShape ls;
-    rt_status st = make_shape(nullptr, false, ls);
+    rt_status st = make_shape(nullptr, LAUNCH_BATCH_SKIP, ls);  // any valid shape: only the view is checked
     if (st != RT_OK) return st;
     ViewDesc v;
     st = make_view(vol, nullptr, nullptr, &probe, static_cast<const rt_camera*>(camera), W, H, step_vox, cutoff, bg,
@@ -700,7 +707,7 @@ rt_status rt_render(const rt_volume* volume, const int64_t dims[3], const double
                     const float bg_rgba[4], float* out_dev, const rt_render_opts* opts, void* stream) {
     if (!dims) return fail(RT_ERR_INVALID_ARG, "dims is NULL");
     LaunchShape ls;
-    rt_status st = make_shape(opts, true, ls);
+    rt_status st = make_shape(opts, LAUNCH_SINGLE, ls);
     if (st != RT_OK) return st;
     if ((!opts || opts->waves_per_block == 0) && width > 0 && height > 0)
         set_waves(ls, default_waves(width, height, ls));
@@ -726,8 +733,10 @@ rt_status rt_render_batch(const rt_render_job* jobs, int n, void* workspace, siz
                           unsigned long long* sample_counter, const rt_render_opts* opts, void* stream) {
     if (!workspace) return fail(RT_ERR_INVALID_ARG, "workspace is NULL");
     if (((uintptr_t)workspace & 255) != 0) return fail(RT_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+    bool any_skip = false;
+    for (int i = 0; jobs && i < n && i <= kMaxBatchJobs; ++i) any_skip = any_skip || jobs[i].skip_empty;
     LaunchShape ls;
-    rt_status st = make_shape(opts, false, ls);
+    rt_status st = make_shape(opts, any_skip ? LAUNCH_BATCH_SKIP : LAUNCH_BATCH, ls);
     if (st != RT_OK) return st;
     std::vector<ViewDesc> descs;
     std::vector<int> prefix;
@@ -746,9 +755,8 @@ rt_status rt_render_batch(const rt_render_job* jobs, int n, void* workspace, siz
     e = hipEventRecord(g_staging.ev, s);
     if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
     g_staging.pending = true;
-    const int grid = std::min(batch_persistent_grid(ls, max_k), std::max(prefix.back(), 1));
-    bool skip = false;
-    for (const ViewDesc& d : descs) skip = skip || d.skip_empty;
+    const bool skip = any_skip;  // the kernel the shape was checked for
+    const int grid = std::min(batch_persistent_grid(ls, max_k, skip), std::max(prefix.back(), 1));
     e = launch_march_batch(kind / 4, kind % 4, workspace, grid, ls, max_k, skip, s);
     if (e != hipSuccess) return hip_fail(e, "batch launch");
     return RT_OK;
@@ -765,7 +773,7 @@ rt_status rt_batch_plan_create(int max_jobs, int storage, int layout, void* work
     if (storage < RT_U8 || storage > RT_U12) return fail(RT_ERR_INVALID_ARG, "unknown storage type");
     if (!layout_allowed(storage, layout)) return fail(RT_ERR_INVALID_ARG, "layout not available for this storage type");
     LaunchShape ls;
-    rt_status st = make_shape(opts, false, ls);
+    rt_status st = make_shape(opts, opts && opts->skip_empty ? LAUNCH_BATCH_SKIP : LAUNCH_BATCH, ls);
     if (st != RT_OK) return st;
     rt_batch_plan* p = new (std::nothrow) rt_batch_plan;
     if (!p) return fail(RT_ERR_OUT_OF_MEMORY, "host allocation failed");
@@ -773,7 +781,7 @@ rt_status rt_batch_plan_create(int max_jobs, int storage, int layout, void* work
     p->max_jobs = max_jobs;
     p->kind = storage_layout_kind(storage, layout);
     p->ls = ls;
-    p->grid = batch_persistent_grid(ls, kMaxK);
+    p->grid = batch_persistent_grid(ls, kMaxK, opts && opts->skip_empty);
     p->ws = workspace;
     p->ws_bytes = ws_bytes;
     hipStream_t cs;

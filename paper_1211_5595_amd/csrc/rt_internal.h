@@ -140,7 +140,7 @@ hipError_t launch_march_plain(const ViewDesc& v, const LaunchShape& ls, unsigned
 // skip: use the kernel with empty-space skipping (for the jobs that ask for it).
 hipError_t launch_march_batch(int kind, int layout, void* workspace, int grid, const LaunchShape& ls, int max_k,
                               bool skip, hipStream_t s);
-int batch_persistent_grid(const LaunchShape& ls, int max_k);
+int batch_persistent_grid(const LaunchShape& ls, int max_k, bool skip);
 
 // Per skip brick value range of a volume in its storage layout (march.hip).
 hipError_t launch_skip_ranges(const VolDev& vol, hipStream_t s);

@@ -174,6 +174,17 @@ def test_launch_options_are_checked_before_any_device_work(rt):
                      (dict(tile=(16, 8)), 4), (dict(waves_per_block=3), 4)):
         o = rt.make_opts(**kw)
         assert L.rt_render(None, dims, None, None, None, 8, 8, 0.5, 0.99, None, None, C.byref(o), None) == code, kw
+    # fixed-step batches take at most 12 wavefronts per workgroup, batches with skipping 16
+    jobs = (rt.rt_render_job * 1)()
+    o = rt.make_opts(waves_per_block=16)
+    assert L.rt_render_batch(jobs, 1, C.c_void_p(4096), 1 << 30, None, C.byref(o), None) == 4
+    assert b"at most 12" in L.rt_last_error()
+    jobs[0].skip_empty = 1
+    assert L.rt_render_batch(jobs, 1, C.c_void_p(4096), 1 << 30, None, C.byref(o), None) == 1  # shape accepted
+    assert b"volume" in L.rt_last_error()
+    o = rt.make_opts(waves_per_block=12)
+    jobs[0].skip_empty = 0
+    assert L.rt_render_batch(jobs, 1, C.c_void_p(4096), 1 << 30, None, C.byref(o), None) == 1
 
 
 def test_product_path_does_not_import_oracle():

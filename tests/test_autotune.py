@@ -38,7 +38,7 @@ def test_tuned_launch_is_bitwise_equal_and_not_slower(tmp_path):
     cache = at.Cache(str(tmp_path / "c.json"))
     res = at.tune_launch(vol, tf, cams, 384, 384, cache=cache, reps=2)
     assert tuple(res["tile"]) in at.TILES and res["waves_per_block"] in at.WAVES
-    assert res["ms"] <= res["timings_ms"][str(((8, 8), 16))] + 1e-9
+    assert res["ms"] <= res["timings_ms"][str(((8, 8), 12))] + 1e-9
     assert at.tune_launch(vol, tf, cams, 384, 384, cache=cache) == res            # served from the cache
     a = rt.render(vol, tf, cams[2], 384, 384)
     b = rt.render(vol, tf, cams[2], 384, 384, tile=tuple(res["tile"]), waves_per_block=res["waves_per_block"])

@@ -17,14 +17,14 @@ def test_orbit_line_fields_and_consistency():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--steps", "3", "--warmup", "1",
-                        "--shape", "4x16x16", "--cpu-budget", "2"], capture_output=True, text=True, timeout=600)
+                        "--shape", "4x16x12", "--cpu-budget", "2"], capture_output=True, text=True, timeout=600)
     assert r.returncode == 0, r.stderr[-2000:]
     line = json.loads(r.stdout.strip().splitlines()[-1])
     for k, v in (("n_gpus", 1), ("steps", 3), ("warmup", 1), ("higher_is_better", True), ("scaling", "weak"),
                  ("vs_baseline", None), ("data", "synthetic"), ("unit", "Gsamples/s")):
         assert line[k] == v, k
     assert line["config"]["workload"] == "brain-orbit-36x512x512-u16"
-    assert line["config"]["tile"] == [4, 16] and line["config"]["waves_per_block"] == 16
+    assert line["config"]["tile"] == [4, 16] and line["config"]["waves_per_block"] == 12
     samples, ms = line["samples_per_step"], line["ms_per_step"]
     assert samples > 0 and ms > 0
     assert abs(line["value"] - samples / (ms * 1e-3) / 1e9) <= 1e-3 * line["value"] + 1e-3
