@@ -371,6 +371,77 @@ def test_tie_band_brackets_stopping_points(orc):
     assert r.band_hi[0, 0, 3] == pytest.approx(a3, abs=1e-15)
 
 
+def _slab_1px(orc, a, cutoff, tie_delta, nz=40):
+    vol = orc.Volume(np.full((nz, 4, 4), 1.0), (1, 1, 1))
+    tf = orc.TF(const_tf(4, (1, 1, 1), a), 0, 2)
+    cam = Camera((1.5, 1.5, -10.0), (1.5, 1.5, 0.0), (0, 1, 0), False, 0.0, 1.0)
+    return orc.render(vol, tf, cam, 1, 1, 1.0, cutoff, tie_delta=tie_delta, want_band=True)
+
+
+@pytest.mark.parametrize("a,cutoff,n_stop", [(0.5, 0.75, 2), (0.5, 0.875, 3), (0.75, 0.9375, 2), (1.0, 1.0, 1),
+                                             (1.0, 0.5, 1)])
+@pytest.mark.parametrize("tie_delta", [0.0, 1e-6])
+def test_cutoff_reached_exactly_stops(orc, a, cutoff, n_stop, tie_delta):
+    """The ray stops after the first sample with 1-T >= cutoff, equality
+    included.  Opacities that are powers of two make 1-T exact in binary64:
+    a = 0.5 gives 1-T = 0.5, 0.75, 0.875, ... and a = 1 gives 1-T = 1 after
+    one sample, so a cutoff equal to one of these values must stop the ray on
+    that very sample (a strict test would take one sample more -- or, for a
+    = 1 at cutoff 1, never stop).  The counted samples and the pixel are those
+    of the stopping sample."""
+    r = _slab_1px(orc, a, cutoff, tie_delta)
+    assert r.counts[0, 0] == n_stop
+    assert r.image[0, 0, 3] == 1 - (1 - a) ** n_stop
+
+
+def test_tie_band_reaches_past_the_stopping_sample(orc):
+    """Binary64 stops at sample 2 with 1-T = 0.75 just above the cutoff
+    0.75 - 1e-7, inside the band [cutoff - d, cutoff + d) with d = 1e-6: a
+    binary32 ray may round its opacity below the cutoff and take sample 3.
+    The band must therefore run on past the stopping sample up to the first
+    state with 1-T >= cutoff + d, the state after sample 3 (1-T = 0.875),
+    while the pixel and count stay those of sample 2."""
+    r = _slab_1px(orc, 0.5, 0.75 - 1e-7, 1e-6)
+    assert r.counts[0, 0] == 2
+    assert r.image[0, 0, 3] == 0.75
+    assert r.tie[0, 0] & 1
+    assert r.band_lo[0, 0, 3] == 0.75
+    assert r.band_hi[0, 0, 3] == 0.875
+    assert r.band_hi[0, 0, 0] == 0.875   # white colour: rgb equals the opacity
+
+
+def test_tie_band_starts_before_the_cutoff(orc):
+    """The mirror case: binary64 opacity after sample 2 (0.75) sits just below
+    the cutoff 0.75 + 1e-7, so binary64 stops at sample 3, yet a binary32 ray
+    may stop at sample 2; the band opens at sample 2 and closes at sample 3."""
+    r = _slab_1px(orc, 0.5, 0.75 + 1e-7, 1e-6)
+    assert r.counts[0, 0] == 3
+    assert r.image[0, 0, 3] == 0.875
+    assert r.tie[0, 0] & 1
+    assert r.band_lo[0, 0, 3] == 0.75
+    assert r.band_hi[0, 0, 3] == 0.875
+
+
+def test_tie_band_edges_include_equality(orc):
+    """The band opens at the first state with 1-T >= cutoff - d and closes at
+    the first with 1-T >= cutoff + d, both inclusive.  a = 0.5 gives the exact
+    opacities 0.5, 0.75, 0.875, 0.9375; cutoff 0.8125 with d = 0.0625 puts
+    both edges exactly on them (0.75 and 0.875)."""
+    r = _slab_1px(orc, 0.5, 0.8125, 0.0625)
+    assert r.counts[0, 0] == 3
+    assert r.band_lo[0, 0, 3] == 0.75
+    assert r.band_hi[0, 0, 3] == 0.875
+
+
+def test_tie_band_closed_when_far_from_cutoff(orc):
+    """With the stopping opacity well clear of the cutoff (0.75 against
+    0.7, d = 1e-6) there is no tie: the band is the single stopping state."""
+    r = _slab_1px(orc, 0.5, 0.7, 1e-6)
+    assert r.counts[0, 0] == 2
+    assert not (r.tie[0, 0] & 1)
+    assert r.band_lo[0, 0, 3] == 0.75 and r.band_hi[0, 0, 3] == 0.75
+
+
 def test_transparent_tf_returns_background(orc):
     v = W.phantom_small(1)
     tf = orc.TF(const_tf(256, (1, 0.5, 0.25), 0.0), 0, 255)
