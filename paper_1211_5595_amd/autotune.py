@@ -103,13 +103,23 @@ def _time_ms(fn, reps: int) -> float:
     return times[len(times) // 2]
 
 
+def launch_candidates(skip_empty: bool = False, tiles: Sequence[Tuple[int, int]] = TILES,
+                      waves: Optional[Sequence[int]] = None) -> List[Tuple[Tuple[int, int], int]]:
+    """(tile, wavefronts per workgroup) pairs the launch tuner times."""
+    if waves is None:
+        waves = WAVES_SKIP if skip_empty else WAVES
+    return [(tuple(t), int(w)) for t in tiles for w in waves]
+
+
 def tune_launch(volume, tf, cameras, width: int, height: int, step_vox: float = 0.5, alpha_cutoff: float = 0.99,
                 reps: int = 3, tiles: Sequence[Tuple[int, int]] = TILES, waves: Optional[Sequence[int]] = None,
                 cache: Optional[Cache] = None, force: bool = False, skip_empty: bool = False) -> dict:
     """Choose tile shape and wavefronts per workgroup for batched renders of
     `cameras` (representative views) of this volume at width x height (with
-    empty-space skipping when skip_empty: that kernel has its own best shape)."""
-    from . import Job, render_batch
+    empty-space skipping when skip_empty: that kernel has its own best shape).
+    Each candidate is timed as it would run: a batch plan (the persistent
+    launch captured in a graph) per shape, replayed."""
+    from . import BatchPlan, Job
     import torch
     key = launch_key(_gpu_arch(), volume.storage, volume.layout, volume.dims, width, height, skip_empty)
     if cache is not None and not force:
@@ -119,13 +129,19 @@ def tune_launch(volume, tf, cameras, width: int, height: int, step_vox: float = 
     outs = [torch.empty((height, width, 4), dtype=torch.float32, device=volume.buf.device) for _ in cameras]
     jobs = [Job(volume, tf, c, width, height, step_vox, alpha_cutoff, out=o, skip_empty=skip_empty)
             for c, o in zip(cameras, outs)]
-    if waves is None:
-        waves = WAVES_SKIP if skip_empty else WAVES
-    cands = [(t, w) for t in tiles for w in waves]
-    best, table = pick_best(cands, lambda c: _time_ms(lambda: render_batch(jobs, tile=c[0], waves_per_block=c[1]),
-                                                      reps))
+
+    def measure(c):
+        plan = BatchPlan(len(jobs), volume.storage, tile=c[0], waves_per_block=c[1], layout=volume.layout,
+                         skip_empty=skip_empty)
+        try:
+            return _time_ms(lambda: plan.launch(jobs), reps)
+        finally:
+            torch.cuda.synchronize()
+            plan.close()
+
+    best, table = pick_best(launch_candidates(skip_empty, tiles, waves), measure)
     result = {"tile": list(best[0]), "waves_per_block": best[1], "ms": table[str(best)], "timings_ms": table,
-              "key": key}
+              "key": key, "timed": "batch plan (graph replay)"}
     if cache is not None:
         cache.put(key, result)
     return result
