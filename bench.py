@@ -26,9 +26,24 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+# Vector-ALU issue peak: every SIMD (4 per compute unit) issues one wave64
+# VALU instruction per 4 cycles, i.e. 16 lane-operations per cycle, at the
+# 2.4 GHz peak engine clock: 256 CUs x 4 x 16 x 2.4 GHz = 39.3 T lane-ops/s.
+# (The 157.3 TFLOP/s fp32 vector figure counts an FMA as two flops and packed
+# fp32 as two lanes: 157.3 / 4.)  Packed fp32 is not used by this library.
+CLOCK_GHZ = 2.4
+SIMDS_PER_CU = 4
+LANE_OPS_PER_SIMD_CYCLE = 16
+N_XCC = 8
 KERNEL_SOURCES = ["paper_1211_5595_amd/csrc/march.hip", "paper_1211_5595_amd/csrc/ff_math.h",
                   "paper_1211_5595_amd/csrc/rt_internal.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+VALU_FILE = os.path.join(ROOT, "profiles", "valu_counters.json")
+
+
+def valu_peak_tops(cus: int = 256) -> float:
+    """Non-packed VALU issue peak in T lane-operations per second."""
+    return cus * SIMDS_PER_CU * LANE_OPS_PER_SIMD_CYCLE * CLOCK_GHZ / 1e3
 
 
 def kernel_hash() -> str:
@@ -87,6 +102,71 @@ def ingest_traffic(d, key, copy_bytes=1 << 30):
     print(json.dumps({key: data[key]}))
 
 
+def load_valu(workload: str):
+    """VALU counters per launch of the timed kernel (rocprofv3), if they were
+    taken on the current kernel sources."""
+    try:
+        data = json.load(open(VALU_FILE))
+    except (OSError, ValueError):
+        return None
+    rec = data.get(workload)
+    if not rec or rec.get("kernel_hash") != kernel_hash():
+        return None
+    return rec
+
+
+def ingest_valu(d, key, samples, cus=256, kernel="march_batch_kernel<6, 0>"):
+    """Raw SQ/GRBM counters of the marcher (medians per dispatch of one
+    rocprofv3 --pmc pass, CSVs under DIR/valu) turned into issue figures:
+    SQ_INSTS_VALU wave instructions (each 4 cycles of a 16-lane SIMD) against
+    the cycles the GPU was busy (GRBM_GUI_ACTIVE, summed over the XCDs) and
+    against the dispatch time at the 2.4 GHz peak clock; lane utilisation
+    SQ_THREAD_CYCLES_VALU / (64 SQ_ACTIVE_INST_VALU).  `samples` is the
+    composited-sample count of one launch (bench.py's counting pass)."""
+    import csv
+    import glob
+    path = glob.glob(os.path.join(d, "valu", "*counter_collection.csv"))[0]
+    march_k = "void rtv::(anonymous namespace)::" + kernel
+    med = lambda c: _counter_per_dispatch(path, march_k, c)
+    insts = med("SQ_INSTS_VALU")
+    gui = med("GRBM_GUI_ACTIVE") / N_XCC
+    thread = med("SQ_THREAD_CYCLES_VALU")
+    active = med("SQ_ACTIVE_INST_VALU")
+    durs = sorted(float(r["End_Timestamp"]) - float(r["Start_Timestamp"]) for r in csv.DictReader(open(path))
+                  if r["Kernel_Name"].startswith(march_k) and r["Counter_Name"] == "SQ_INSTS_VALU"
+                  and r.get("End_Timestamp"))
+    ns = durs[len(durs) // 2] if durs else None
+    simds = cus * SIMDS_PER_CU
+    rec = {"kernel_hash": kernel_hash(), "sq_insts_valu": insts, "grbm_gui_active_cycles": gui,
+           "sq_thread_cycles_valu": thread, "sq_active_inst_valu": active, "samples_per_launch": int(samples),
+           "valu_wave_insts_per_sample": insts / samples,
+           "lane_utilisation": thread / (64.0 * active) if active else None,
+           "issue_frac_of_busy_cycles": insts * 4.0 / (simds * gui) if gui else None}
+    if ns:
+        rec["dispatch_ns"] = ns
+        rec["clock_GHz"] = gui / ns if gui else None
+        rec["issue_frac_at_peak_clock"] = insts * 4.0 / (simds * CLOCK_GHZ * ns)
+    try:
+        data = json.load(open(VALU_FILE))
+    except (OSError, ValueError):
+        data = {}
+    data[key] = rec
+    with open(VALU_FILE, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    print(json.dumps({key: rec}))
+
+
+def valu_roofline(samples, ms_per_launch, valu_per_sample, cus):
+    """Instruction-issue roofline of one launch: the VALU lane-operations the
+    composited samples require (samples x VALU instructions per sample of the
+    compositing loop, read from the built code object) per second, against
+    the non-packed VALU issue peak."""
+    peak = valu_peak_tops(cus)
+    achieved = samples * valu_per_sample / (ms_per_launch * 1e-3) / 1e12
+    return {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3), "unit": "T VALU lane-ops/s",
+            "frac": round(achieved / peak, 4)}
+
+
 def percentile(xs, p):
     xs = sorted(xs)
     if not xs:
@@ -118,7 +198,7 @@ def cpu_baseline(vol_np, tf_np, cams, spacing, width, height, step, cutoff, vmax
     dt1 = time.perf_counter() - t1
     return {"value": samples / dt / 1e9, "unit": "Gsamples/s", "cores": oracle.max_threads(), "kind": "oracle",
             "sample": f"{n_views} of the {len(cams)} orbit views, {width}x{height}, whole images",
-            "fps": n_views / dt, "seconds": dt, "cpu_model": _cpu_model(),
+            "fps": n_views / dt, "seconds": dt, **_lscpu(),
             "single_core": {"value": int(r1.counts.sum()) / dt1 / 1e9, "unit": "Gsamples/s", "cores": 1,
                             "sample": "orbit view 0, whole image", "seconds": dt1}}
 
@@ -166,15 +246,30 @@ def small_config(reps=200):
             "cpu_cores": oracle.max_threads(), "oracle_samples": int(r.counts.sum())}
 
 
-def _cpu_model() -> str:
+def _lscpu() -> dict:
+    """CPU model and processor count as lscpu and nproc report them."""
+    import subprocess
+    out = {"cpu_model": "unknown", "lscpu_cpus": None, "nproc": None}
     try:
-        with open("/proc/cpuinfo") as f:
-            for line in f:
-                if line.startswith("model name"):
-                    return line.split(":", 1)[1].strip()
-    except OSError:
+        r = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10)
+        for line in r.stdout.splitlines():
+            k, _, v = line.partition(":")
+            if k.strip() == "Model name":
+                out["cpu_model"] = v.strip()
+            elif k.strip() == "CPU(s)":
+                out["lscpu_cpus"] = int(v.strip())
+    except (OSError, ValueError, subprocess.SubprocessError):
         pass
-    return "unknown"
+    try:
+        r = subprocess.run(["nproc"], capture_output=True, text=True, timeout=10)
+        out["nproc"] = int(r.stdout.strip())
+    except (OSError, ValueError, subprocess.SubprocessError):
+        pass
+    return out
+
+
+def _cpu_model() -> str:
+    return _lscpu()["cpu_model"]
 
 
 def probe_copy(gib: float = 1.0, reps: int = 10, quiet: bool = False):
@@ -219,7 +314,8 @@ def _limiter(form, storage):
     if form in ("batch", "graph", "skip"):
         # the caches serve two thirds of the logical gathers, so the fraction
         # can exceed 1; what binds is vector-instruction issue
-        text, prof = "VALU issue (VALUBusy ~97 %", f"profiles/march_batch_{storage}_brain_orbit.md"
+        text, prof = "VALU instruction issue (raw SQ_INSTS_VALU over busy cycles", \
+            f"profiles/march_batch_{storage}_brain_orbit.md"
     else:
         # one launch per view: the longest ray's own instruction stream
         text, prof = "the longest ray of each lone view (one launch per view", f"profiles/march_plain_{storage}_brain_orbit_views.md"
@@ -645,8 +741,12 @@ def main():
     ap.add_argument("--ingest-traffic", default=None, metavar="DIR",
                     help="read rocprofv3 FETCH_SIZE/WRITE_SIZE CSVs from DIR/{fetch,write,copy_fetch,copy_write} "
                          "and record the orbit kernel's HBM bytes per launch in profiles/traffic.json")
-    ap.add_argument("--traffic-key", default="brain-orbit-36x512x512-u16:cells:graph",
+    ap.add_argument("--traffic-key", default="brain-orbit-36x512x512-u12:cells:graph",
                     help="workload:layout:form the ingested counters belong to")
+    ap.add_argument("--ingest-valu", default=None, metavar="DIR",
+                    help="read a rocprofv3 SQ/GRBM counter CSV from DIR/valu and record the orbit kernel's VALU "
+                         "issue figures in profiles/valu_counters.json (key --traffic-key; needs --valu-samples)")
+    ap.add_argument("--valu-samples", type=int, default=0, help="composited samples per launch (for --ingest-valu)")
     ap.add_argument("--requests", type=int, default=4000, help="serve workload: number of requests")
     ap.add_argument("--workload", choices=["orbit", "precision", "batch", "serve", "projection"], default="orbit",
                     help="orbit: 36 views of the 256x256x160 u16 phantom at 512^2 (default); precision: "
@@ -681,6 +781,10 @@ def main():
         return
     if args.ingest_traffic:
         return ingest_traffic(args.ingest_traffic, args.traffic_key)
+    if args.ingest_valu:
+        if args.valu_samples <= 0:
+            raise SystemExit("--ingest-valu needs --valu-samples")
+        return ingest_valu(args.ingest_valu, args.traffic_key, args.valu_samples)
     if args.workload == "precision":
         return bench_precision(args)
     if args.workload == "batch":
@@ -808,18 +912,56 @@ def main():
     if not args.only:
         lat = single_view_latency(rt.make_opts(), outs)  # rt_render's own default launch shape
 
-    # roofline of the dominant kernel: algorithmic bytes = 8 trilinear corners
-    # x 2 B per sample + 16 B per output pixel, per launch
+    # roofline of the dominant kernel.  The binding resource is vector-ALU
+    # instruction issue: the VALU work the composited samples require
+    # (samples x VALU instructions per sample of the compositing loop, counted
+    # in the built code object) per second against the non-packed issue
+    # peak.  Beside it, the logical gather bytes (8 trilinear corners x 2 B
+    # per sample + 16 B per output pixel; the caches serve most of them, so
+    # they are not a ceiling) and the fabric bytes the counters measured.
     algo_bytes = samples_per_step * 16 + n_views * width * height * 16
     launches_per_step = 1 if best in ("batch", "graph", "skip") else n_views
     bytes_per_launch = algo_bytes / launches_per_step
+    samples_per_launch = samples_per_step / launches_per_step
     ms_per_launch = ms_step / launches_per_step
-    achieved = bytes_per_launch / (ms_per_launch * 1e-3) / 1e9
-    workload = "brain-orbit-36x512x512-u16"
-    traffic = load_traffic(workload + ":" + args.layout + ("" if args.storage == "u16" else "-" + args.storage)
-                           + ":" + best)
-    if best == "skip":  # skipped samples are never gathered: no algorithmic-byte roofline for this form
-        achieved, traffic = None, None
+    workload = f"brain-orbit-36x512x512-{args.storage}"
+    key = workload + ":" + args.layout + ":" + best
+    traffic = load_traffic(key)
+    roof = None
+    if best != "skip":  # skipped samples are never gathered: no per-sample roofline for that form
+        from paper_1211_5595_amd import isa
+        batch_form = best in ("batch", "graph")
+        kname = "march_batch_kernel" if batch_form else "march_plain_kernel"
+        lp = isa.loop_profile(rt.LIB_PATH, storage, layout, kname)
+        if lp is None:
+            raise SystemExit(f"no compositing loop found for {kname}<{storage}, {layout}> in {rt.LIB_PATH}")
+        cus = torch.cuda.get_device_properties(0).multi_processor_count
+        roof = valu_roofline(samples_per_launch, ms_per_launch, lp["valu_per_sample"], cus)
+        gb = lambda b: round(b / (ms_per_launch * 1e-3) / 1e9, 1)
+        roof.update({
+            "traffic": traffic,
+            "kernel": kname + "<" + args.storage + ">",
+            "valu_per_sample": lp["valu_per_sample"],
+            "valu_per_sample_from": "VALU instructions per sample of the compositing loop in the built gfx950 "
+                                    "code object (paper_1211_5595_amd/isa.py)",
+            "samples_per_launch": int(samples_per_launch),
+            "limiter": _limiter(best, args.storage),
+            "logical_gather": {"bytes_per_launch": int(bytes_per_launch), "GB_per_s": gb(bytes_per_launch),
+                               "frac_of_hbm_peak": round(bytes_per_launch / (ms_per_launch * 1e-3) / 1e9
+                                                         / PEAK_HBM_GBS, 4),
+                               "note": "8 corners x 2 B per sample + 16 B per pixel; L1/L2 serve most of "
+                                       "these gathers, so this figure is not a ceiling and can exceed 1"},
+            "fabric": None if traffic is None else {
+                "bytes_per_launch": traffic, "GB_per_s": gb(traffic),
+                "frac_of_hbm_peak": round(traffic / (ms_per_launch * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+                "note": "FETCH_SIZE x 2 + WRITE_SIZE x 1 per launch (scales from a plain copy); reads served "
+                        "by the Infinity Cache count as fetched"},
+        })
+        cnt = load_valu(key)
+        if cnt is not None:
+            roof["counters"] = {k: cnt.get(k) for k in ("sq_insts_valu", "valu_wave_insts_per_sample",
+                                                       "lane_utilisation", "issue_frac_of_busy_cycles",
+                                                       "issue_frac_at_peak_clock", "clock_GHz")}
 
     line = {
         "metric": "ray samples/sec (G/s) + fps at 512x512 over 256x256x160; p50/p99 render latency",
@@ -834,7 +976,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": workload, "volume": list(vs.dims), "spacing": list(vs.spacing), "storage": args.storage,
+        "config": {"workload": workload, "volume": list(vs.dims), "spacing": list(vs.spacing),
+                   "source_dtype": "u16 (12-bit range)", "storage": args.storage,
                    "image": [width, height], "views": n_views, "step_vox": step, "alpha_cutoff": cutoff,
                    "tf_entries": ts.K, "launch": best, "layout": args.layout, "tile": list(shape["tile"]),
                    "waves_per_block": shape["waves_per_block"]},
@@ -848,16 +991,10 @@ def main():
         "gsamples_per_s_by_form": {k: round(samples_per_step / (v * 1e-3) / 1e9, 3) for k, v in ms.items()},
         "latency_ms": {"single_view_p50": percentile(lat, 50), "single_view_p99": percentile(lat, 99),
                        "orbit_step": round(ms_step, 4)} if lat else None,
-        "roofline": None if achieved is None else {
-                     "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
-                     "kernel": ("march_batch_kernel<" if best in ("batch", "graph", "skip") else "march_plain_kernel<")
-                               + args.storage + ">",
-                     "algorithmic_bytes_per_launch": int(bytes_per_launch),
-                     "limiter": _limiter(best, args.storage)},
+        "roofline": roof,
     }
-    if line["roofline"] is not None and not args.only:  # what a plain device copy achieves on this GPU
-        line["roofline"]["achievable_copy_GBps"] = round(probe_copy(1.0, 10, quiet=True), 1)
+    if roof is not None and not args.only:  # what a plain device copy achieves on this GPU
+        roof["achievable_copy_GBps"] = round(probe_copy(1.0, 10, quiet=True), 1)
     # exact empty-space skipping over the same views: same images, same
     # composited-sample count, fewer samples gathered; reported beside the
     # fixed-step figure, never as it

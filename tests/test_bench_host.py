@@ -13,7 +13,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 sys.path.insert(0, ROOT)
 import bench  # noqa: E402
 
-MARCH = "void rtv::(anonymous namespace)::march_batch_kernel<6, 0, false>(char*, rtv::LaunchShape, int, int)"
+MARCH = "void rtv::(anonymous namespace)::march_batch_kernel<6, 0>(char*, rtv::LaunchShape, int, int)"
 COPY = "__amd_rocclr_copyBuffer"
 
 
@@ -79,10 +79,64 @@ def test_percentile_interpolates():
 
 
 def test_limiter_names_the_timed_kernel():
-    assert bench._limiter("graph", "u12").startswith("VALU issue")
+    assert bench._limiter("graph", "u12").startswith("VALU instruction issue")
     assert bench._limiter("plain", "u12").startswith("the longest ray")
     for form, st in (("graph", "u12"), ("plain", "u16"), ("skip", "u15")):
         note = bench._limiter(form, st)
         assert note.count("(") == note.count(")")
         if "see " in note:
             assert os.path.exists(os.path.join(ROOT, note.split("see ")[1].rstrip(")")))
+
+
+def test_ingest_valu_issue_figures(tmp_path, monkeypatch):
+    """Raw counters to issue fractions: 4 cycles per wave64 VALU instruction
+    on each of 4 SIMDs per CU, busy cycles summed over the 8 XCDs."""
+    d = tmp_path / "prof" / "valu"
+    os.makedirs(d)
+    rows = []
+    for disp, scale in ((0, 1.0), (1, 1.0), (2, 3.0)):   # the third dispatch an outlier: medians are taken
+        for c, v in (("SQ_INSTS_VALU", 1.0e9 * scale), ("GRBM_GUI_ACTIVE", 8 * 5.0e6 * scale),
+                     ("SQ_THREAD_CYCLES_VALU", 57.6e9 * scale), ("SQ_ACTIVE_INST_VALU", 1.0e9 * scale)):
+            rows.append({"Dispatch_Id": disp, "Kernel_Name": MARCH, "Counter_Name": c, "Counter_Value": v,
+                         "Start_Timestamp": 0, "End_Timestamp": int(2.0e6 * scale)})
+    with open(d / "x_counter_collection.csv", "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=list(rows[0]))
+        w.writeheader()
+        w.writerows(rows)
+    vf = tmp_path / "valu.json"
+    monkeypatch.setattr(bench, "VALU_FILE", str(vf))
+    bench.ingest_valu(str(tmp_path / "prof"), "w", samples=5.0e10)
+    rec = bench.load_valu("w")
+    assert rec is not None and rec["kernel_hash"] == bench.kernel_hash()
+    assert rec["issue_frac_of_busy_cycles"] == pytest.approx(1.0e9 * 4 / (1024 * 5.0e6))
+    assert rec["clock_GHz"] == pytest.approx(2.5)
+    assert rec["issue_frac_at_peak_clock"] == pytest.approx(1.0e9 * 4 / (1024 * 2.4 * 2.0e6))
+    assert rec["lane_utilisation"] == pytest.approx(0.9)
+    assert rec["valu_wave_insts_per_sample"] == pytest.approx(0.02)
+    rec["kernel_hash"] = "0" * 16
+    json.dump({"w": rec}, open(vf, "w"))
+    assert bench.load_valu("w") is None
+
+
+def test_valu_roofline_is_a_ceiling():
+    peak = bench.valu_peak_tops(256)
+    assert peak == pytest.approx(256 * 4 * 16 * 2.4 / 1e3)
+    r = bench.valu_roofline(1.0e9, 2.0, 50.0, 256)
+    assert r["bound"] == "alu" and r["achieved"] == pytest.approx(25.0, abs=1e-3)
+    assert r["frac"] == pytest.approx(25.0 / peak, abs=1e-4) and r["frac"] <= 1.0
+
+
+def test_isa_loop_counts_from_the_built_library():
+    """The compositing loop of the batched kernel is found in the built code
+    object: two 16-byte table reads per sample, one cell load per sample for
+    the cell layout."""
+    import paper_1211_5595_amd as rt
+    from paper_1211_5595_amd import isa
+    if not os.path.exists(rt.LIB_PATH):
+        pytest.skip("library not built")
+    for kind in (rt.U12, rt.U16):
+        lp = isa.loop_profile(rt.LIB_PATH, kind, rt.LAYOUT_CELLS)
+        assert lp is not None and lp["lds_per_sample"] == 2.0 and lp["vmem_per_sample"] == 1.0
+        assert 30.0 <= lp["valu_per_sample"] <= 90.0
+    assert isa.loop_profile(rt.LIB_PATH, rt.U12, rt.LAYOUT_CELLS)["valu_per_sample"] < \
+        isa.loop_profile(rt.LIB_PATH, rt.U16, rt.LAYOUT_CELLS)["valu_per_sample"]

@@ -23,21 +23,32 @@ def test_orbit_line_fields_and_consistency():
     for k, v in (("n_gpus", 1), ("steps", 3), ("warmup", 1), ("higher_is_better", True), ("scaling", "weak"),
                  ("vs_baseline", None), ("data", "synthetic"), ("unit", "Gsamples/s")):
         assert line[k] == v, k
-    assert line["config"]["workload"] == "brain-orbit-36x512x512-u16"
+    assert line["config"]["workload"] == "brain-orbit-36x512x512-u12" and line["config"]["storage"] == "u12"
     assert line["config"]["tile"] == [4, 16] and line["config"]["waves_per_block"] == 12
     samples, ms = line["samples_per_step"], line["ms_per_step"]
     assert samples > 0 and ms > 0
     assert abs(line["value"] - samples / (ms * 1e-3) / 1e9) <= 1e-3 * line["value"] + 1e-3
     assert abs(line["fps"] - 36 / (ms * 1e-3)) <= 1e-3 * line["fps"] + 0.1
     rf = line["roofline"]
-    assert rf["bound"] == "hbm" and rf["unit"] == "GB/s" and rf["peak"] == 8000.0
-    assert rf["algorithmic_bytes_per_launch"] == samples * 16 + 36 * 512 * 512 * 16
-    assert abs(rf["achieved"] - rf["algorithmic_bytes_per_launch"] / (ms * 1e-3) / 1e9) <= 0.1 + 1e-3 * rf["achieved"]
+    # the binding resource: VALU issue, a true ceiling
+    assert rf["bound"] == "alu" and rf["unit"] == "T VALU lane-ops/s"
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    assert abs(rf["peak"] - cus * 4 * 16 * 2.4 / 1e3) <= 1e-3
+    assert rf["samples_per_launch"] == samples
+    assert 40.0 <= rf["valu_per_sample"] <= 90.0
+    assert abs(rf["achieved"] - samples * rf["valu_per_sample"] / (ms * 1e-3) / 1e12) <= 1e-3 * rf["achieved"] + 1e-3
     assert abs(rf["frac"] - rf["achieved"] / rf["peak"]) <= 1e-3
-    assert rf["traffic"] is None or rf["traffic"] > 0
+    assert 0.0 < rf["frac"] <= 1.0
+    lg = rf["logical_gather"]
+    assert lg["bytes_per_launch"] == samples * 16 + 36 * 512 * 512 * 16
+    assert abs(lg["GB_per_s"] - lg["bytes_per_launch"] / (ms * 1e-3) / 1e9) <= 0.1 + 1e-3 * lg["GB_per_s"]
+    assert rf["traffic"] is None or (rf["traffic"] > 0 and 0.0 < rf["fabric"]["frac_of_hbm_peak"] <= 1.0)
+    if rf.get("counters"):
+        c = rf["counters"]
+        assert 0.0 < c["issue_frac_of_busy_cycles"] <= 1.0 and 0.0 < c["lane_utilisation"] <= 1.0
     cb = line["cpu_baseline"]
     assert cb["kind"] == "oracle" and cb["unit"] == "Gsamples/s" and cb["value"] > 0 and cb["cores"] >= 1
-    assert cb["sample"]
+    assert cb["sample"] and cb["cpu_model"] and cb["nproc"] >= 1
     sk = line["skip_empty"]
     assert sk["images_bitwise_equal"] is True and sk["ms_per_step"] > 0
     sc = line["small_config"]
