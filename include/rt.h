@@ -303,6 +303,22 @@ rt_status rt_batch_plan_launch(rt_batch_plan* plan, const rt_render_job* jobs, i
                                unsigned long long* sample_counter, void* stream);
 rt_status rt_batch_plan_destroy(rt_batch_plan* plan);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid device allocation): rt_render_batch
+ * with its workspace in a device array inside the library instead of a
+ * caller buffer.  Takes at most 64 jobs (RT_ERR_UNSUPPORTED above that,
+ * before any device work); otherwise arguments, errors and results are those
+ * of rt_render_batch, images bitwise identical.  The header, block prefix and
+ * job table are delivered to the array by small kernels whose arguments carry
+ * them (about 43 KB of device memory per GPU, held until the process ends),
+ * so the call makes no device or pinned-host allocation and no copy from
+ * pageable memory.  The array of the current device is used; `stream` must
+ * belong to it.  Every call on one GPU shares that array: calls that may
+ * overlap on one GPU (other threads, other streams) race and must be ordered
+ * by the caller. */
+rt_status rt_render_batch_noalloc(const rt_render_job* jobs, int n, unsigned long long* sample_counter,
+                                  const rt_render_opts* opts, void* stream);
+
 /* ---------------------------------------------------------------------------
  * Diagnostics
  * ------------------------------------------------------------------------- */

@@ -23,7 +23,7 @@ __all__ = [
     "U8", "U16", "F16", "F32", "U8_BRICKSCALED", "U15", "U12", "COMPOSITE", "MIP", "XRAY", "AVERAGE", "ISO", "THRESHOLD",
     "lib", "rt_volume_bytes", "rt_create_volume", "rt_destroy_volume", "rt_tf_bytes",
     "rt_set_transfer_function", "rt_destroy_tf", "rt_render", "rt_batch_workspace_bytes",
-    "rt_render_batch", "rt_batch_plan_create", "rt_batch_plan_launch", "rt_batch_plan_destroy",
+    "rt_render_batch", "rt_render_batch_noalloc", "rt_batch_plan_create", "rt_batch_plan_launch", "rt_batch_plan_destroy",
     "rt_server_arena_bytes", "rt_server_create", "rt_server_submit", "rt_server_wait", "rt_server_release",
     "rt_server_get_stats", "rt_server_destroy", "REQ_QUEUED", "REQ_RUNNING", "REQ_DONE", "REQ_FAILED",
     "Volume", "TransferFunction", "BatchPlan", "render", "render_batch", "Job",
@@ -136,6 +136,7 @@ def lib():
                                      C.POINTER(vp)],
             "rt_batch_plan_launch": [vp, C.POINTER(rt_render_job), C.c_int, vp, vp],
             "rt_batch_plan_destroy": [vp],
+            "rt_render_batch_noalloc": [C.POINTER(rt_render_job), C.c_int, vp, C.POINTER(rt_render_opts), vp],
             "rt_server_arena_bytes": [C.c_int, C.c_int, C.c_size_t, szp],
             "rt_server_create": [C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(rt_render_opts), vp, C.c_size_t,
                                  C.c_size_t, C.POINTER(vp)],
@@ -276,6 +277,14 @@ def rt_render_batch(jobs, ws_ptr: int, ws_bytes: int, counter_ptr: Optional[int]
     arr = (rt_render_job * len(jobs))(*jobs)
     _check(lib().rt_render_batch(arr, len(jobs), C.c_void_p(ws_ptr), int(ws_bytes), C.c_void_p(counter_ptr),
                                  C.byref(opts) if opts is not None else None, _stream_ptr(stream)), "rt_render_batch")
+
+
+def rt_render_batch_noalloc(jobs, counter_ptr: Optional[int] = None, opts: Optional[rt_render_opts] = None,
+                            stream=None):
+    arr = (rt_render_job * len(jobs))(*jobs)
+    _check(lib().rt_render_batch_noalloc(arr, len(jobs), C.c_void_p(counter_ptr),
+                                         C.byref(opts) if opts is not None else None, _stream_ptr(stream)),
+           "rt_render_batch_noalloc")
 
 
 def rt_batch_plan_create(max_jobs: int, storage: int, layout: int, ws_ptr: int, ws_bytes: int,

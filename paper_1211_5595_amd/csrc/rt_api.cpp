@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -430,14 +431,13 @@ size_t prefix_bytes() { return kBatchPrefixBytes; }
 
 size_t batch_ws_bytes(int max_jobs) { return kBatchHeaderBytes + prefix_bytes() + (size_t)max_jobs * sizeof(ViewDesc); }
 
-// Fill header, prefix and job table for n jobs into host memory `h`; returns
-// the bytes to copy.
-rt_status build_batch(const rt_render_job* jobs, int n, const LaunchShape& ls, int* kind,
-                      int* max_k, std::vector<ViewDesc>& descs, std::vector<int>& prefix) {
+// Validate n jobs and fill their view descriptions descs[0..n) and block
+// prefix prefix[0..n] (prefix[i] = first workgroup block of job i).
+rt_status build_batch_into(const rt_render_job* jobs, int n, const LaunchShape& ls, int* kind, int* max_k,
+                           ViewDesc* descs, int* prefix) {
     if (!jobs || n < 1) return fail(RT_ERR_INVALID_ARG, "empty batch");
     if (n > kMaxBatchJobs) return fail(RT_ERR_UNSUPPORTED, "too many jobs in one batch");
-    descs.resize(n);
-    prefix.assign(n + 1, 0);
+    prefix[0] = 0;
     *kind = -1;
     *max_k = 2;
     for (int i = 0; i < n; ++i) {
@@ -458,18 +458,34 @@ rt_status build_batch(const rt_render_job* jobs, int n, const LaunchShape& ls, i
     return RT_OK;
 }
 
-void write_batch_host(void* h, const std::vector<ViewDesc>& descs, const std::vector<int>& prefix, int max_k,
-                      unsigned long long* counter) {
-    char* b = static_cast<char*>(h);
+rt_status build_batch(const rt_render_job* jobs, int n, const LaunchShape& ls, int* kind,
+                      int* max_k, std::vector<ViewDesc>& descs, std::vector<int>& prefix) {
+    if (!jobs || n < 1) return fail(RT_ERR_INVALID_ARG, "empty batch");
+    if (n > kMaxBatchJobs) return fail(RT_ERR_UNSUPPORTED, "too many jobs in one batch");
+    descs.resize(n);
+    prefix.assign(n + 1, 0);
+    return build_batch_into(jobs, n, ls, kind, max_k, descs.data(), prefix.data());
+}
+
+// The workspace header of a batch of n jobs.
+void make_batch_header(void* h, int n, int total_blocks, int max_k, unsigned long long* counter) {
     BatchHeader hdr;
     std::memset(&hdr, 0, sizeof(hdr));
     hdr.queue = 0;
-    hdr.n_jobs = (unsigned)descs.size();
-    hdr.total_blocks = (unsigned)prefix.back();
+    hdr.n_jobs = (unsigned)n;
+    hdr.total_blocks = (unsigned)total_blocks;
     hdr.tf_lds_entries = max_k + 1;
     hdr.counter = counter;
-    std::memset(b, 0, kBatchHeaderBytes);
-    std::memcpy(b, &hdr, sizeof(hdr));
+    std::memset(h, 0, kBatchHeaderBytes);
+    std::memcpy(h, &hdr, sizeof(hdr));
+}
+
+// Header, prefix and job table for n jobs into host memory `h` (the
+// workspace image to copy).
+void write_batch_host(void* h, const std::vector<ViewDesc>& descs, const std::vector<int>& prefix, int max_k,
+                      unsigned long long* counter) {
+    char* b = static_cast<char*>(h);
+    make_batch_header(b, (int)descs.size(), prefix.back(), max_k, counter);
     std::memcpy(b + kBatchHeaderBytes, prefix.data(), prefix.size() * sizeof(int));
     std::memcpy(b + kBatchHeaderBytes + prefix_bytes(), descs.data(), descs.size() * sizeof(ViewDesc));
 }
@@ -855,6 +871,114 @@ rt_status rt_batch_plan_destroy(rt_batch_plan* p) {
     if (p->copy_done) (void)hipEventDestroy(p->copy_done);
     if (p->staging) (void)hipHostFree(p->staging);
     delete p;
+    return RT_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// rt_render_batch_noalloc: the batched launch with its workspace in this
+// file's device array `scratch` (one copy per GPU, held until the process
+// ends).  The header, block prefix and job table reach it through the
+// arguments of small fill kernels (the runtime copies kernel arguments at
+// launch), so the call needs no device or pinned host allocation and no copy
+// from pageable memory.  Calls that overlap on one GPU share the array and
+// race; each call rewrites the header, whose block queue word starts at zero.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int kNoAllocMaxJobs = 64;
+constexpr size_t kNoAllocDescOffset = kBatchHeaderBytes + kBatchPrefixBytes;
+constexpr size_t kNoAllocBytes = kNoAllocDescOffset + (size_t)kNoAllocMaxJobs * sizeof(ViewDesc) + 16;
+constexpr int kFillPayload = 3584;  // table bytes per fill launch (kernel arguments stay under 4 KiB)
+constexpr int kMaxDevices = 64;
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+struct FillChunk {
+    uint32_t dst_offset;  // byte offset in the workspace, 16-byte aligned
+    uint32_t bytes;       // multiple of 16, at most kFillPayload
+    uint32_t pad[2];
+    uint4 data[kFillPayload / 16];
+};
+
+__global__ void __launch_bounds__(256) fill_workspace_kernel(unsigned char* __restrict__ ws, const FillChunk c) {
+    for (uint32_t i = threadIdx.x; i * 16u < c.bytes; i += blockDim.x)
+        *reinterpret_cast<uint4*>(ws + c.dst_offset + i * 16u) = c.data[i];
+}
+
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices];  // device address of `scratch` per device, set on first use
+
+// The current device's address of `scratch`, looked up once per device with
+// that device current.
+rt_status scratch_address(void** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(RT_ERR_UNSUPPORTED, "device index beyond 63");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!p) return fail(RT_ERR_DEVICE, "hipGetSymbolAddress(scratch) returned NULL");
+        g_scratch_dev[dev] = p;
+    }
+    *out = g_scratch_dev[dev];
+    return RT_OK;
+}
+
+// Copy `bytes` (rounded up to 16; the source must be readable that far) from
+// host memory to ws + dst_offset in fill launches on stream s.
+hipError_t fill_workspace(unsigned char* ws, size_t dst_offset, const void* src, size_t bytes, hipStream_t s) {
+    const unsigned char* p = static_cast<const unsigned char*>(src);
+    const size_t total = (bytes + 15) & ~(size_t)15;
+    for (size_t done = 0; done < total; done += kFillPayload) {
+        FillChunk c;
+        c.dst_offset = (uint32_t)(dst_offset + done);
+        c.bytes = (uint32_t)std::min(total - done, (size_t)kFillPayload);
+        c.pad[0] = c.pad[1] = 0;
+        std::memcpy(c.data, p + done, c.bytes);
+        hipLaunchKernelGGL(fill_workspace_kernel, dim3(1), dim3(256), 0, s, ws, c);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+rt_status rt_render_batch_noalloc(const rt_render_job* jobs, int n, unsigned long long* sample_counter,
+                                  const rt_render_opts* opts, void* stream) {
+    if (n > kNoAllocMaxJobs) return fail(RT_ERR_UNSUPPORTED, "rt_render_batch_noalloc takes at most 64 jobs");
+    bool any_skip = false;
+    for (int i = 0; jobs && i < n; ++i) any_skip = any_skip || jobs[i].skip_empty;
+    LaunchShape ls;
+    rt_status st = make_shape(opts, any_skip ? LAUNCH_BATCH_SKIP : LAUNCH_BATCH, ls);
+    if (st != RT_OK) return st;
+    // header + prefix, and the job table (one spare entry: the 16-byte
+    // rounding of a copy stays inside the arrays)
+    alignas(16) unsigned char head[kBatchHeaderBytes + ((kNoAllocMaxJobs + 1) * sizeof(int) + 15) / 16 * 16];
+    alignas(16) ViewDesc descs[kNoAllocMaxJobs + 1];
+    int* prefix = reinterpret_cast<int*>(head + kBatchHeaderBytes);
+    int kind, max_k;
+    st = build_batch_into(jobs, n, ls, &kind, &max_k, descs, prefix);
+    if (st != RT_OK) return st;
+    make_batch_header(head, n, prefix[n], max_k, sample_counter);
+    void* ws = nullptr;
+    st = scratch_address(&ws);
+    if (st != RT_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    unsigned char* w = static_cast<unsigned char*>(ws);
+    hipError_t e = fill_workspace(w, 0, head, kBatchHeaderBytes + (size_t)(n + 1) * sizeof(int), s);
+    if (e == hipSuccess) e = fill_workspace(w, kNoAllocDescOffset, descs, (size_t)n * sizeof(ViewDesc), s);
+    if (e != hipSuccess) return hip_fail(e, "workspace fill");
+    const int grid = std::min(batch_persistent_grid(ls, max_k, any_skip), std::max(prefix[n], 1));
+    e = launch_march_batch(kind / 4, kind % 4, ws, grid, ls, max_k, any_skip, s);
+    if (e != hipSuccess) return hip_fail(e, "batch launch");
     return RT_OK;
 }
 
