@@ -26,14 +26,16 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
-# Vector-ALU issue peak: every SIMD (4 per compute unit) issues one wave64
-# VALU instruction per 4 cycles, i.e. 16 lane-operations per cycle, at the
-# 2.4 GHz peak engine clock: 256 CUs x 4 x 16 x 2.4 GHz = 39.3 T lane-ops/s.
-# (The 157.3 TFLOP/s fp32 vector figure counts an FMA as two flops and packed
-# fp32 as two lanes: 157.3 / 4.)  Packed fp32 is not used by this library.
+# Vector-ALU peak: MI355X's fp32 vector rate, 157.3 TFLOP/s, counts a fused
+# multiply-add as two flops, i.e. 78.6 T lane-operations per second: 256 CUs x
+# 4 SIMDs x 32 lanes per cycle x 2.4 GHz (a wave64 instruction every 2 cycles
+# per SIMD; independent VALU instructions of two waves can issue together).
+# Every VALU instruction counts as one lane-operation per lane, whatever its
+# own rate (conversions, 24-bit multiplies and mixed-precision FMAs issue at
+# half that rate, 64-bit adds slower still).
 CLOCK_GHZ = 2.4
 SIMDS_PER_CU = 4
-LANE_OPS_PER_SIMD_CYCLE = 16
+LANE_OPS_PER_SIMD_CYCLE = 32
 N_XCC = 8
 KERNEL_SOURCES = ["paper_1211_5595_amd/csrc/march.hip", "paper_1211_5595_amd/csrc/ff_math.h",
                   "paper_1211_5595_amd/csrc/rt_internal.h"]
@@ -42,7 +44,7 @@ VALU_FILE = os.path.join(ROOT, "profiles", "valu_counters.json")
 
 
 def valu_peak_tops(cus: int = 256) -> float:
-    """Non-packed VALU issue peak in T lane-operations per second."""
+    """VALU peak in T lane-operations per second (the fp32 vector rate)."""
     return cus * SIMDS_PER_CU * LANE_OPS_PER_SIMD_CYCLE * CLOCK_GHZ / 1e3
 
 
@@ -118,11 +120,12 @@ def load_valu(workload: str):
 def ingest_valu(d, key, samples, cus=256, kernel="march_batch_kernel<6, 0>"):
     """Raw SQ/GRBM counters of the marcher (medians per dispatch of one
     rocprofv3 --pmc pass, CSVs under DIR/valu) turned into issue figures:
-    SQ_INSTS_VALU wave instructions (each 4 cycles of a 16-lane SIMD) against
-    the cycles the GPU was busy (GRBM_GUI_ACTIVE, summed over the XCDs) and
-    against the dispatch time at the 2.4 GHz peak clock; lane utilisation
-    SQ_THREAD_CYCLES_VALU / (64 SQ_ACTIVE_INST_VALU).  `samples` is the
-    composited-sample count of one launch (bench.py's counting pass)."""
+    SQ_INSTS_VALU wave instructions x 64 lanes against the VALU peak of 32
+    lane-operations per SIMD per cycle, over the cycles the GPU was busy
+    (GRBM_GUI_ACTIVE, summed over the XCDs) and over the dispatch time at the
+    2.4 GHz peak clock; lane utilisation SQ_THREAD_CYCLES_VALU / (64
+    SQ_ACTIVE_INST_VALU).  `samples` is the composited-sample count of one
+    launch (bench.py's counting pass)."""
     import csv
     import glob
     path = glob.glob(os.path.join(d, "valu", "*counter_collection.csv"))[0]
@@ -141,11 +144,11 @@ def ingest_valu(d, key, samples, cus=256, kernel="march_batch_kernel<6, 0>"):
            "sq_thread_cycles_valu": thread, "sq_active_inst_valu": active, "samples_per_launch": int(samples),
            "valu_wave_insts_per_sample": insts / samples,
            "lane_utilisation": thread / (64.0 * active) if active else None,
-           "issue_frac_of_busy_cycles": insts * 4.0 / (simds * gui) if gui else None}
+           "issue_frac_of_busy_cycles": insts * 64.0 / (simds * LANE_OPS_PER_SIMD_CYCLE * gui) if gui else None}
     if ns:
         rec["dispatch_ns"] = ns
         rec["clock_GHz"] = gui / ns if gui else None
-        rec["issue_frac_at_peak_clock"] = insts * 4.0 / (simds * CLOCK_GHZ * ns)
+        rec["issue_frac_at_peak_clock"] = insts * 64.0 / (simds * LANE_OPS_PER_SIMD_CYCLE * CLOCK_GHZ * ns)
     try:
         data = json.load(open(VALU_FILE))
     except (OSError, ValueError):
@@ -157,10 +160,10 @@ def ingest_valu(d, key, samples, cus=256, kernel="march_batch_kernel<6, 0>"):
 
 
 def valu_roofline(samples, ms_per_launch, valu_per_sample, cus):
-    """Instruction-issue roofline of one launch: the VALU lane-operations the
+    """Vector-ALU roofline of one launch: the VALU lane-operations the
     composited samples require (samples x VALU instructions per sample of the
     compositing loop, read from the built code object) per second, against
-    the non-packed VALU issue peak."""
+    the fp32 vector peak in lane-operations."""
     peak = valu_peak_tops(cus)
     achieved = samples * valu_per_sample / (ms_per_launch * 1e-3) / 1e12
     return {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3), "unit": "T VALU lane-ops/s",

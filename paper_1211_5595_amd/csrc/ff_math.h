@@ -1,7 +1,8 @@
 // ff_math.h -- float-float ("double-single") arithmetic for the per-ray
 // set-up on the device.  Error-free transformations after Knuth (TwoSum),
-// Dekker (FastTwoSum) and the FMA form of TwoProduct; division and square
-// root by one or two Newton corrections of the binary32 result.  Relative
+// Dekker (FastTwoSum) and the FMA form of TwoProduct; quotient, reciprocal
+// and reciprocal square root from the hardware's binary32 estimates with
+// Newton corrections against float-float residuals.  Relative
 // error of each operation is a small multiple of 2^-44.  The library is
 // built with -ffp-contract=off so the compiler keeps every rounding step.
 #pragma once
@@ -56,22 +57,35 @@ __device__ __forceinline__ ff ff_mul_f(ff a, float b) {
     return fast_two_sum(p.hi, p.lo);
 }
 
+// a / b: quotient digits from the hardware reciprocal estimate of b.hi
+// (within one unit in the last place), each corrected against the exact
+// float-float residual, so the estimate's error does not reach the result.
 __device__ __forceinline__ ff ff_div(ff a, ff b) {
-    float q1 = a.hi / b.hi;
+    const float rb = __builtin_amdgcn_rcpf(b.hi);
+    const float q1 = a.hi * rb;
     ff r = ff_sub(a, ff_mul_f(b, q1));
-    float q2 = r.hi / b.hi;
+    const float q2 = r.hi * rb;
     r = ff_sub(r, ff_mul_f(b, q2));
-    float q3 = r.hi / b.hi;
+    const float q3 = r.hi * rb;
     ff q = fast_two_sum(q1, q2);
     return ff_add(q, ff_make(q3));
 }
 
-// a > 0.
-__device__ __forceinline__ ff ff_sqrt(ff a) {
-    float x = sqrtf(a.hi);
-    ff r = ff_sub(a, two_prod(x, x));
-    float c = r.hi / (2.0f * x);
-    return fast_two_sum(x, c);
+// 1 / b, b != 0: the hardware estimate x (within one unit in the last place)
+// with one Newton correction x + x (1 - b x), the residual in float-float.
+__device__ __forceinline__ ff ff_rcp(ff b) {
+    const float x = __builtin_amdgcn_rcpf(b.hi);
+    const ff e = ff_sub(ff_make(1.0f), ff_mul_f(b, x));
+    return fast_two_sum(x, x * e.hi);
+}
+
+// 1 / sqrt(a), a > 0: the hardware estimate y (within one unit in the last
+// place) with one Newton correction y + y (1 - a y^2) / 2, the residual
+// 1 - a y^2 formed in float-float.
+__device__ __forceinline__ ff ff_rsqrt(ff a) {
+    const float y = __builtin_amdgcn_rsqf(a.hi);
+    const ff e = ff_sub(ff_make(1.0f), ff_mul(a, two_prod(y, y)));
+    return fast_two_sum(y, y * (0.5f * e.hi));
 }
 
 __device__ __forceinline__ bool ff_lt(ff a, ff b) { return a.hi < b.hi || (a.hi == b.hi && a.lo < b.lo); }
@@ -87,15 +101,17 @@ __device__ __forceinline__ int ff_floor_int(ff a) {
     return m;
 }
 
-// Signed 32.32 fixed point of a float-float value (|a| < 2^30): returns
+// Signed 32.32 fixed point of a float-float value (|a| < 2^22): returns
 // round(a * 2^32) within one unit.  hi * 2^32 and lo * 2^32 are exact
 // power-of-two scalings; each is an integer-valued binary32 number (or is
-// rounded to one) and converts to int64 exactly.  Subtracting floor(hi)
-// from hi instead would drop a bit whenever -1 < hi < 0.
+// rounded to one) and converts exactly, hi's to a 64-bit integer and lo's,
+// below 2^31 in magnitude, to a 32-bit one.  Subtracting floor(hi) from hi
+// instead would drop a bit whenever -1 < hi < 0 (and so would splitting
+// hi * 2^32 at 2^32 with a floor).
 __device__ __forceinline__ long long ff_to_fixed32(ff a) {
     const long long H = (long long)rintf(a.hi * 4294967296.0f);
-    const long long L = (long long)rintf(a.lo * 4294967296.0f);
-    return H + L;
+    const int L = (int)rintf(a.lo * 4294967296.0f);
+    return H + (long long)L;
 }
 
 }  // namespace rtv

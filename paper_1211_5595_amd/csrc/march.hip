@@ -89,36 +89,47 @@ template <class VD>
 __device__ __forceinline__ bool setup_ray(const VD& V, int i, int j, Ray& R) {
     const float a = (float)(2 * i + 1 - V.W);
     const float b = (float)(V.H - 2 * j - 1);
-    ff o[3], d[3];
+    // The ray in padded index space: origin oq and direction dq per mm of
+    // the ray parameter t (the world ray divided by the spacing, plus 1 on
+    // the origin), so sample positions are oq + t dq with no further scaling.
+    ff oq[3], dq[3], lo[3], hi[3];
     if (V.perspective) {
         ff r[3];
 #pragma unroll
         for (int ax = 0; ax < 3; ++ax) r[ax] = ff_add(ff_add(ldff(V.w[ax]), ff_mul_f(ldff(V.U[ax]), a)), ff_mul_f(ldff(V.V[ax]), b));
         ff n2 = ff_add(ff_add(ff_mul(r[0], r[0]), ff_mul(r[1], r[1])), ff_mul(r[2], r[2]));
-        ff inv = ff_div(ff_make(1.0f), ff_sqrt(n2));
+        ff inv = ff_rsqrt(n2);
 #pragma unroll
         for (int ax = 0; ax < 3; ++ax) {
-            o[ax] = ldff(V.eye[ax]);
-            d[ax] = ff_mul(r[ax], inv);
+            oq[ax] = ldff(V.eye_q[ax]);
+            dq[ax] = ff_mul(r[ax], ff_mul(inv, ldff(V.inv_sp[ax])));
+            lo[ax] = ldff(V.face_lo_q[ax]);
+            hi[ax] = ldff(V.face_hi_q[ax]);
         }
     } else {
 #pragma unroll
         for (int ax = 0; ax < 3; ++ax) {
-            o[ax] = ff_add(ff_add(ldff(V.eye[ax]), ff_mul_f(ldff(V.U[ax]), a)), ff_mul_f(ldff(V.V[ax]), b));
-            d[ax] = ldff(V.w[ax]);
+            oq[ax] = ff_add(ff_add(ldff(V.eye_q[ax]), ff_mul_f(ldff(V.U_q[ax]), a)), ff_mul_f(ldff(V.V_q[ax]), b));
+            dq[ax] = ldff(V.w_q[ax]);
+            lo[ax] = ff_sub(ff_make(1.0f), oq[ax]);
+            hi[ax] = ff_sub(ff_make((float)V.vol.n[ax]), oq[ax]);
         }
     }
-    // Slab test against the closed box.
+    // Slab test against the closed box [1, n] (lo and hi are its faces
+    // relative to the origin).  An axis the ray runs parallel to is tested in
+    // world units, as the box [0, (n-1) s] against the origin.
     ff tin = ff_make(-INFINITY), tout = ff_make(INFINITY);
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
-        if (d[ax].hi == 0.0f) {
-            if (ff_lt(o[ax], ff_make(0.0f)) || ff_lt(ldff(V.box_hi[ax]), o[ax])) return false;
+        if (dq[ax].hi == 0.0f) {
+            ff o = ldff(V.eye[ax]);
+            if (!V.perspective) o = ff_add(ff_add(o, ff_mul_f(ldff(V.U[ax]), a)), ff_mul_f(ldff(V.V[ax]), b));
+            if (ff_lt(o, ff_make(0.0f)) || ff_lt(ldff(V.box_hi[ax]), o)) return false;
             continue;
         }
-        ff rd = ff_div(ff_make(1.0f), d[ax]);
-        ff t0 = ff_mul(ff_neg(o[ax]), rd);
-        ff t1 = ff_mul(ff_sub(ldff(V.box_hi[ax]), o[ax]), rd);
+        const ff rd = ff_rcp(dq[ax]);
+        ff t0 = ff_mul(lo[ax], rd);
+        ff t1 = ff_mul(hi[ax], rd);
         if (ff_lt(t1, t0)) {
             ff x = t0;
             t0 = t1;
@@ -129,9 +140,11 @@ __device__ __forceinline__ bool setup_ray(const VD& V, int i, int j, Ray& R) {
     }
     const ff tnear = ff_max(tin, ff_make(0.0f));
     if (!ff_lt(tnear, tout)) return false;
-    // Evenly spaced samples: m segments of dt and a remainder r in [0, dt).
+    // Evenly spaced samples: m segments of dt and a remainder r in [0, dt)
+    // (the quotient's floor from the reciprocal, then made exact against the
+    // float-float remainder).
     const ff L = ff_sub(tout, tnear);
-    int m = ff_floor_int(ff_div(L, ldff(V.dt)));
+    int m = ff_floor_int(ff_mul(L, ldff(V.inv_dt)));
     ff r = ff_sub(L, ff_mul_f(ldff(V.dt), (float)m));
     if (r.hi < 0.0f) {
         m -= 1;
@@ -146,23 +159,20 @@ __device__ __forceinline__ bool setup_ray(const VD& V, int i, int j, Ray& R) {
         r = ff_make(0.0f);
     }
     R.m = m;
-    // First sample at tnear + dt/2; positions in padded index space q + 1.
-    const ff s0 = ff_add(tnear, ff_mul_f(ldff(V.dt), 0.5f));
+    // First sample at tnear + dt/2.
+    const ff dt = ldff(V.dt);
+    const ff s0 = ff_add(tnear, ff{0.5f * dt.hi, 0.5f * dt.lo});
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
-        ff p = ff_add(o[ax], ff_mul(s0, d[ax]));
-        R.Q[ax] = ff_to_fixed32(ff_add(ff_mul(p, ldff(V.inv_sp[ax])), ff_make(1.0f)));
-        R.dQ[ax] = ff_to_fixed32(ff_mul(ff_mul(ldff(V.dt), d[ax]), ldff(V.inv_sp[ax])));
+        R.Q[ax] = ff_to_fixed32(ff_add(oq[ax], ff_mul(s0, dq[ax])));
+        R.dQ[ax] = ff_to_fixed32(ff_mul(dt, dq[ax]));
     }
     R.wp = 0.0f;
     if (r.hi > 0.0f) {
-        const ff sp = ff_add(ff_add(tnear, ff_mul_f(ldff(V.dt), (float)m)), ff_mul_f(r, 0.5f));
+        const ff sp = ff_add(ff_add(tnear, ff_mul_f(dt, (float)m)), ff{0.5f * r.hi, 0.5f * r.lo});
 #pragma unroll
-        for (int ax = 0; ax < 3; ++ax) {
-            ff p = ff_add(o[ax], ff_mul(sp, d[ax]));
-            R.Qp[ax] = ff_to_fixed32(ff_add(ff_mul(p, ldff(V.inv_sp[ax])), ff_make(1.0f)));
-        }
-        R.wp = r.hi / ldff(V.dt).hi;
+        for (int ax = 0; ax < 3; ++ax) R.Qp[ax] = ff_to_fixed32(ff_add(oq[ax], ff_mul(sp, dq[ax])));
+        R.wp = r.hi * __builtin_amdgcn_rcpf(dt.hi);
     }
     return true;
 }
@@ -823,53 +833,66 @@ __device__ __forceinline__ void march_pixel(const VD& V, const float4* __restric
             __amdgpu_buffer_rsrc_t rsp = rs;
             asm volatile("" : "+s"(rsp));
             if constexpr (!PREFETCH && !SKIP) {
-                // Fixed steps in the batched kernel: the cell of sample k+1 is
-                // requested before sample k is processed, so each load has a
-                // whole sample's work to arrive; the two cells alternate
-                // between two register sets (the loop is unrolled by two).  The
-                // request after a ray's last sample reads a cell one step past
-                // it, through the same bounded reads as every other cell, and
-                // is never used.
+                // Fixed steps in the batched kernel.  The cell of the next
+                // sample is requested before the current one is processed, so
+                // each load has a whole sample's work to arrive.  Samples go in
+                // pairs: the loop body processes sample A (cell wa) and then,
+                // unless A stopped the ray, sample B (cell wb), with one exit
+                // test per pair; an odd count starts with one sample alone.  With
+                // no exit between A and B, every register keeps one role and the
+                // loop carries its state without copies.  The request after a
+                // ray's last sample reads a cell one step past it, through the
+                // same bounded reads as every other cell, and is never used.
+                // Scheduling barriers keep each request where it is written (left
+                // to the scheduler, the request for sample B sank below sample A's
+                // work and B waited for its whole latency).
+                long long P[3] = {R.Q[0], R.Q[1], R.Q[2]};
                 typename S::Raw wa = cur, wb;
-                for (;;) {
-                    long long Qn[3];
+                int r = R.m;  // full samples not yet composited
+                bool go = true;
+                auto composite = [&](const typename S::Raw& w, const long long* at) {
+                    const float val = stored_value<S>(w, frac32(at[0]), frac32(at[1]), frac32(at[2]));
+                    float4 c = classify(s_tf, val, ta, tb, Km1);
+                    if (WINDOW && !in_window(val + bias, V)) c.w = 0.0f;
+                    const float Ta = T * c.w;
+                    asm volatile("" ::"v"(Ta));  // formed before T is overwritten: no copy of T
+                    Cr = fmaf(Ta, c.x, Cr);
+                    Cg = fmaf(Ta, c.y, Cg);
+                    Cb = fmaf(Ta, c.z, Cb);
+                    T = fmaf(-T, c.w, T);
+                };
+                if (r & 1) {
+                    long long Pn[3];
 #pragma unroll
-                    for (int q = 0; q < 3; ++q) Qn[q] = R.Q[q] + R.dQ[q];
-                    wb = S::load(rsp, vol, cn, Qn);
-                    {
-                        const float val = stored_value<S>(wa, frac32(R.Q[0]), frac32(R.Q[1]), frac32(R.Q[2]));
-                        float4 c = classify(s_tf, val, ta, tb, Km1);
-                        if (WINDOW && !in_window(val + bias, V)) c.w = 0.0f;
-                        const float Ta = T * c.w;
-                        asm volatile("" ::"v"(Ta));  // formed before T is overwritten: no copy of T
-                        Cr = fmaf(Ta, c.x, Cr);
-                        Cg = fmaf(Ta, c.y, Cg);
-                        Cb = fmaf(Ta, c.z, Cb);
-                        T = fmaf(-T, c.w, T);
-                        ++k;
-                        if (k >= R.m || T <= thr) break;
-                    }
+                    for (int q = 0; q < 3; ++q) Pn[q] = P[q] + R.dQ[q];
+                    wb = S::load(rsp, vol, cn, Pn);
+                    composite(wa, P);
+                    r -= 1;
+                    go = r > 0 && T > thr;
 #pragma unroll
-                    for (int q = 0; q < 3; ++q) R.Q[q] = Qn[q];
-#pragma unroll
-                    for (int q = 0; q < 3; ++q) Qn[q] = R.Q[q] + R.dQ[q];
-                    wa = S::load(rsp, vol, cn, Qn);
-                    {
-                        const float val = stored_value<S>(wb, frac32(R.Q[0]), frac32(R.Q[1]), frac32(R.Q[2]));
-                        float4 c = classify(s_tf, val, ta, tb, Km1);
-                        if (WINDOW && !in_window(val + bias, V)) c.w = 0.0f;
-                        const float Ta = T * c.w;
-                        asm volatile("" ::"v"(Ta));  // formed before T is overwritten: no copy of T
-                        Cr = fmaf(Ta, c.x, Cr);
-                        Cg = fmaf(Ta, c.y, Cg);
-                        Cb = fmaf(Ta, c.z, Cb);
-                        T = fmaf(-T, c.w, T);
-                        ++k;
-                        if (k >= R.m || T <= thr) break;
-                    }
-#pragma unroll
-                    for (int q = 0; q < 3; ++q) R.Q[q] = Qn[q];
+                    for (int q = 0; q < 3; ++q) P[q] = Pn[q];
+                    wa = wb;
                 }
+                bool liveA = true;
+                if (go) {
+                    for (;;) {
+                        long long P1[3];
+#pragma unroll
+                        for (int q = 0; q < 3; ++q) P1[q] = P[q] + R.dQ[q];
+                        wb = S::load(rsp, vol, cn, P1);
+                        __builtin_amdgcn_sched_barrier(0);
+                        composite(wa, P);
+                        liveA = T > thr;  // r >= 2 here: sample B exists
+#pragma unroll
+                        for (int q = 0; q < 3; ++q) P[q] = P1[q] + R.dQ[q];
+                        wa = S::load(rsp, vol, cn, P);
+                        __builtin_amdgcn_sched_barrier(0);
+                        if (liveA) composite(wb, P1);
+                        r -= 2;
+                        if (!(liveA && r > 0 && T > thr)) break;
+                    }
+                }
+                k = R.m - r - (liveA ? 0 : 1);
             }
             for (; !PREFETCH && SKIP;) {
                 if constexpr (SKIP) {

@@ -366,8 +366,16 @@ rt_status make_view(const rt_volume* vol, const int64_t dims[3], const double sp
         v.V[a] = to_ff(scale * vv[a]);
         v.inv_sp[a] = to_ff(1.0 / sp[a]);
         v.box_hi[a] = to_ff((double)(vol->dims[a] - 1) * sp[a]);
+        const double eq = cam->eye[a] / sp[a] + 1.0;
+        v.eye_q[a] = to_ff(eq);
+        v.U_q[a] = to_ff(scale * u[a] / sp[a]);
+        v.V_q[a] = to_ff(scale * vv[a] / sp[a]);
+        v.w_q[a] = to_ff(w[a] / sp[a]);
+        v.face_lo_q[a] = to_ff(1.0 - eq);
+        v.face_hi_q[a] = to_ff((double)vol->dims[a] - eq);
     }
     v.dt = to_ff(dt);
+    v.inv_dt = to_ff(1.0 / dt);
     v.thr = (float)(1.0 - cutoff);
     for (int c = 0; c < 4; ++c) v.bg[c] = bg ? bg[c] : 0.0f;
     v.W = W;

@@ -90,6 +90,15 @@ struct ViewDesc {
     ff inv_sp[3];     // 1 / spacing
     ff box_hi[3];     // (n-1) * spacing, mm
     ff dt;            // sample spacing, mm
+    ff inv_dt;        // 1 / dt
+    // The same frame in padded index space (index = position / spacing + 1,
+    // the volume box [1, n] per axis): eye, and per-pixel offsets U, V and the
+    // orthographic direction w, each divided by the spacing; and, for the
+    // pinhole (whose rays all start at the eye), the box faces relative to the
+    // eye, 1 - eye_q and n - eye_q.
+    ff eye_q[3];
+    ff U_q[3], V_q[3], w_q[3];
+    ff face_lo_q[3], face_hi_q[3];
     float thr;        // stop once transmittance T <= thr (= 1 - cutoff)
     float bg[4];
     int32_t W, H, perspective;

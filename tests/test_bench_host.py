@@ -89,8 +89,9 @@ def test_limiter_names_the_timed_kernel():
 
 
 def test_ingest_valu_issue_figures(tmp_path, monkeypatch):
-    """Raw counters to issue fractions: 4 cycles per wave64 VALU instruction
-    on each of 4 SIMDs per CU, busy cycles summed over the 8 XCDs."""
+    """Raw counters to issue fractions: 64 lane-operations per wave64 VALU
+    instruction against 32 per SIMD per cycle on each of 4 SIMDs per CU, busy
+    cycles summed over the 8 XCDs."""
     d = tmp_path / "prof" / "valu"
     os.makedirs(d)
     rows = []
@@ -108,9 +109,9 @@ def test_ingest_valu_issue_figures(tmp_path, monkeypatch):
     bench.ingest_valu(str(tmp_path / "prof"), "w", samples=5.0e10)
     rec = bench.load_valu("w")
     assert rec is not None and rec["kernel_hash"] == bench.kernel_hash()
-    assert rec["issue_frac_of_busy_cycles"] == pytest.approx(1.0e9 * 4 / (1024 * 5.0e6))
+    assert rec["issue_frac_of_busy_cycles"] == pytest.approx(1.0e9 * 2 / (1024 * 5.0e6))
     assert rec["clock_GHz"] == pytest.approx(2.5)
-    assert rec["issue_frac_at_peak_clock"] == pytest.approx(1.0e9 * 4 / (1024 * 2.4 * 2.0e6))
+    assert rec["issue_frac_at_peak_clock"] == pytest.approx(1.0e9 * 2 / (1024 * 2.4 * 2.0e6))
     assert rec["lane_utilisation"] == pytest.approx(0.9)
     assert rec["valu_wave_insts_per_sample"] == pytest.approx(0.02)
     rec["kernel_hash"] = "0" * 16
@@ -120,7 +121,7 @@ def test_ingest_valu_issue_figures(tmp_path, monkeypatch):
 
 def test_valu_roofline_is_a_ceiling():
     peak = bench.valu_peak_tops(256)
-    assert peak == pytest.approx(256 * 4 * 16 * 2.4 / 1e3)
+    assert peak == pytest.approx(256 * 4 * 32 * 2.4 / 1e3)
     r = bench.valu_roofline(1.0e9, 2.0, 50.0, 256)
     assert r["bound"] == "alu" and r["achieved"] == pytest.approx(25.0, abs=1e-3)
     assert r["frac"] == pytest.approx(25.0 / peak, abs=1e-4) and r["frac"] <= 1.0

@@ -33,7 +33,7 @@ def test_orbit_line_fields_and_consistency():
     # the binding resource: VALU issue, a true ceiling
     assert rf["bound"] == "alu" and rf["unit"] == "T VALU lane-ops/s"
     cus = torch.cuda.get_device_properties(0).multi_processor_count
-    assert abs(rf["peak"] - cus * 4 * 16 * 2.4 / 1e3) <= 1e-3
+    assert abs(rf["peak"] - cus * 4 * 32 * 2.4 / 1e3) <= 1e-3
     assert rf["samples_per_launch"] == samples
     assert 40.0 <= rf["valu_per_sample"] <= 90.0
     assert abs(rf["achieved"] - samples * rf["valu_per_sample"] / (ms * 1e-3) / 1e12) <= 1e-3 * rf["achieved"] + 1e-3
