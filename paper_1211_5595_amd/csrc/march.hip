@@ -722,8 +722,16 @@ __device__ __forceinline__ void march_pixel(const VD& V, const float4* __restric
         const float ta = V.tf_a, thr = V.thr;
         float tb = bias != 0.0f ? fmaf(bias, ta, V.tf_b) : V.tf_b;
         asm("" : "+v"(tb));  // held in a vector register: fma(val, ta, tb) may read one scalar only
+        // The cell strides and the buffer bound pinned in scalar registers:
+        // left to the compiler they are reloaded from the view description in
+        // every iteration (a scalar load the next cell request waits for), or
+        // kept from the kernel's start and spilled.
+        VolDev vol = copy_vol(V.vol);
+        asm volatile("" : "+s"(vol.sy), "+s"(vol.sz));
+        __amdgpu_buffer_rsrc_t rsp = rs;
+        asm volatile("" : "+s"(rsp));
         if (R.m > 0) {
-            typename S::Raw cur = S::load(rs, V.vol, cn, R.Q);
+            typename S::Raw cur = S::load(rsp, vol, cn, R.Q);
             // wavefront-uniform: the bricks are looked at every 4th sample and
             // after each leap; a leap leaves `cur` stale (reloaded only when a
             // sample is taken, so a run of leaps never waits on memory)
@@ -756,7 +764,7 @@ __device__ __forceinline__ void march_pixel(const VD& V, const float4* __restric
 #pragma unroll
                 for (int b = 1; b < depth; ++b) {
                     advance_request();
-                    ring[b] = S::load(rs, V.vol, cn, Qf);
+                    ring[b] = S::load(rsp, vol, cn, Qf);
                 }
                 // Straight-line steps (no per-ray exit inside the ring): a ray
                 // that has stopped keeps stepping with its opacity forced to 0,
@@ -790,11 +798,11 @@ __device__ __forceinline__ void march_pixel(const VD& V, const float4* __restric
 #pragma unroll
                                     for (int a = 0; a < 3; ++a) Qf[a] = R.Q[a];
                                     kf = k;
-                                    ring[0] = S::load(rs, V.vol, cn, Qf);
+                                    ring[0] = S::load(rsp, vol, cn, Qf);
 #pragma unroll
                                     for (int b = 1; b < depth; ++b) {
                                         advance_request();
-                                        ring[b] = S::load(rs, V.vol, cn, Qf);
+                                        ring[b] = S::load(rsp, vol, cn, Qf);
                                     }
                                 }
                             }
@@ -815,7 +823,7 @@ __device__ __forceinline__ void march_pixel(const VD& V, const float4* __restric
                         k += live ? 1 : 0;
                         live = live && k < R.m && T > thr;
                         advance_request();
-                        ring[b] = S::load(rs, V.vol, cn, Qf);
+                        ring[b] = S::load(rsp, vol, cn, Qf);
 #pragma unroll
                         for (int q = 0; q < 3; ++q) R.Q[q] += R.dQ[q];
                         // keep the steps in order: interleaving them would make the
@@ -825,13 +833,6 @@ __device__ __forceinline__ void march_pixel(const VD& V, const float4* __restric
                     if (__builtin_amdgcn_ballot_w64(live) == 0) break;
                 }
             }
-            // The cell strides and the buffer bound pinned in scalar registers:
-            // left to the compiler they are reloaded from the view description
-            // in every iteration, a scalar load the next cell request waits for.
-            VolDev vol = copy_vol(V.vol);
-            asm volatile("" : "+s"(vol.sy), "+s"(vol.sz));
-            __amdgpu_buffer_rsrc_t rsp = rs;
-            asm volatile("" : "+s"(rsp));
             if constexpr (!PREFETCH && !SKIP) {
                 // Fixed steps in the batched kernel.  The cell of the next
                 // sample is requested before the current one is processed, so
@@ -929,7 +930,7 @@ __device__ __forceinline__ void march_pixel(const VD& V, const float4* __restric
             }
         }
         if (R.wp > 0.0f && T > thr) {
-            const typename S::Raw w = S::load(rs, V.vol, cn, R.Qp);
+            const typename S::Raw w = S::load(rsp, vol, cn, R.Qp);
             const float val = stored_value<S>(w, frac32(R.Qp[0]), frac32(R.Qp[1]), frac32(R.Qp[2]));
             float4 c = classify(s_tf, val, ta, tb, Km1);
             if (WINDOW && !in_window(val + bias, V)) c.w = 0.0f;
@@ -1148,8 +1149,11 @@ __device__ __forceinline__ void iso_pixel(const VD& V, const float4* __restrict_
 }
 
 // PREFETCH: the compositing loop requests the next cell before processing the
-// current sample (the single-view kernel; see march_pixel).
-template <int KIND, int LAYOUT, bool SKIP, bool PREFETCH, class VD>
+// current sample (the single-view kernel; see march_pixel).  COMP_ONLY: the
+// view is known to composite, so only that path is compiled (the single-view
+// kernel of a compositing view: one ray function keeps its view parameters out
+// of spilled scalar registers).
+template <int KIND, int LAYOUT, bool SKIP, bool PREFETCH, class VD, bool COMP_ONLY = false>
 __device__ __forceinline__ void render_block(const VD& V, const float4* __restrict__ s_tf,
                                              const uint32_t* __restrict__ s_mask, int blk, const LaunchShape& ls,
                                              int tw_shift, unsigned long long* __restrict__ counter) {
@@ -1175,7 +1179,7 @@ __device__ __forceinline__ void render_block(const VD& V, const float4* __restri
         const int fn = V.ray_function;  // uniform over the view
         // the skipping loop keeps a per-ray counter anyway (leaps differ per ray)
         const bool want_count = SKIP || V.counts != nullptr || counter != nullptr;
-        if (fn == RT_FN_COMPOSITE) {
+        if (COMP_ONLY || fn == RT_FN_COMPOSITE) {
             if (want_count)
                 march_pixel<KIND, LAYOUT, SKIP, false, true, PREFETCH, VD>(V, s_tf, s_mask, rs, cn, i, j, px, count);
             else
@@ -1220,7 +1224,7 @@ __device__ __forceinline__ int xcd_remap(int b, int n) {
 
 // SKIP selects the compositing loop with empty-space skipping (a separate
 // kernel, so the plain loop keeps its registers).
-template <int KIND, int LAYOUT, bool SKIP>
+template <int KIND, int LAYOUT, bool SKIP, bool COMP_ONLY>
 __global__ void RT_PLAIN_ATTRS march_plain_kernel(const ViewDesc V, const LaunchShape ls, int tw_shift,
                                                    unsigned long long* __restrict__ counter) {
     extern __shared__ float4 s_tf[];
@@ -1228,7 +1232,8 @@ __global__ void RT_PLAIN_ATTRS march_plain_kernel(const ViewDesc V, const Launch
     load_tf(s_tf, V.tf, V.K, V.alpha_exp);
     if (SKIP) build_skip_mask(s_mask, V);
     __syncthreads();
-    render_block<KIND, LAYOUT, SKIP, true, ViewDesc>(V, s_tf, s_mask, xcd_remap(blockIdx.x, gridDim.x), ls, tw_shift,
+    render_block<KIND, LAYOUT, SKIP, true, ViewDesc, COMP_ONLY>(V, s_tf, s_mask, xcd_remap(blockIdx.x, gridDim.x), ls,
+                                                               tw_shift,
                                                counter);
 }
 
@@ -1389,25 +1394,30 @@ int log2i(int x) {
     return s;
 }
 
-template <int KIND, int LAYOUT, bool SKIP>
+template <int KIND, int LAYOUT, bool SKIP, bool COMP_ONLY>
 hipError_t plain_launch_k(const ViewDesc& v, const LaunchShape& ls, unsigned long long* counter, hipStream_t s) {
     const int nblk = v.nblocks;
     if (nblk <= 0) return hipSuccess;
     const size_t lds = (size_t)(v.K + 1) * sizeof(float4) + (v.skip_empty ? (size_t)kSkipMaskBytes : 0);
     // once per kernel, thread-safe (function-local static initialisation)
-    static const hipError_t attr = hipFuncSetAttribute((const void*)march_plain_kernel<KIND, LAYOUT, SKIP>,
-                                                       hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                       (int)((kMaxK + 1) * sizeof(float4) + kSkipMaskBytes));
+    static const hipError_t attr =
+        hipFuncSetAttribute((const void*)march_plain_kernel<KIND, LAYOUT, SKIP, COMP_ONLY>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)((kMaxK + 1) * sizeof(float4) + kSkipMaskBytes));
     (void)attr;
-    hipLaunchKernelGGL((march_plain_kernel<KIND, LAYOUT, SKIP>), dim3(nblk), dim3(64 * ls.waves), lds, s, v, ls,
-                       log2i(ls.tile_w), counter);
+    hipLaunchKernelGGL((march_plain_kernel<KIND, LAYOUT, SKIP, COMP_ONLY>), dim3(nblk), dim3(64 * ls.waves), lds, s,
+                       v, ls, log2i(ls.tile_w), counter);
     return hipGetLastError();
 }
 
 template <int KIND, int LAYOUT>
 hipError_t plain_launch(const ViewDesc& v, const LaunchShape& ls, unsigned long long* counter, hipStream_t s) {
-    return v.skip_empty ? plain_launch_k<KIND, LAYOUT, true>(v, ls, counter, s)
-                        : plain_launch_k<KIND, LAYOUT, false>(v, ls, counter, s);
+    const bool comp = v.ray_function == RT_FN_COMPOSITE;
+    if (v.skip_empty)
+        return comp ? plain_launch_k<KIND, LAYOUT, true, true>(v, ls, counter, s)
+                    : plain_launch_k<KIND, LAYOUT, true, false>(v, ls, counter, s);
+    return comp ? plain_launch_k<KIND, LAYOUT, false, true>(v, ls, counter, s)
+                : plain_launch_k<KIND, LAYOUT, false, false>(v, ls, counter, s);
 }
 
 template <int KIND, int LAYOUT, bool SKIP>

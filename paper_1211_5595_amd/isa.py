@@ -101,12 +101,18 @@ def _loops(ins: List[Tuple[int, str, str]]) -> List[Tuple[int, int]]:
     return sorted(set(outer))
 
 
-def loop_profile(lib_path: str, kind: int, layout: int, kernel: str = "march_batch_kernel") -> Optional[Dict]:
+def loop_profile(lib_path: str, kind: int, layout: int, kernel: str = "march_batch_kernel",
+                 tail: Optional[str] = None) -> Optional[Dict]:
     """VALU (and other) instructions per sample of the compositing loop of
-    kernel<kind, layout> in the built library, or None when not found."""
+    kernel<kind, layout, ...> in the built library, or None when not found.
+    `tail` is the mangled rest of the template arguments (the batched kernel
+    has none; the single-view kernel's fixed-step compositing instantiation,
+    <kind, layout, false, true>, is the default for it)."""
+    if tail is None:
+        tail = "Lb0ELb1E" if kernel == "march_plain_kernel" else ""
     with tempfile.TemporaryDirectory() as wd:
         for co in _code_objects(lib_path, wd):
-            pat = re.compile(r"\d+" + kernel + rf"ILi{kind}ELi{layout}E(?:Lb0E)?E")
+            pat = re.compile(r"\d+" + kernel + rf"ILi{kind}ELi{layout}E{tail}E")
             syms = [s for s in _symbols(co) if pat.search(s)]
             if not syms:
                 continue
