@@ -38,6 +38,21 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, uint3
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, kRsrcWord3);
 }
 
+// The volume's buffer descriptor: raw (byte offsets, byte bound) for the
+// linear and brick layouts; structured with the cell as the record for the
+// cell-packed layouts (8 bytes for 8-bit codes, 32 for binary32 and
+// polynomial cells, 16 otherwise).
+template <int KIND, int LAYOUT>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_vol_rsrc(const void* p, uint32_t bytes) {
+    if constexpr (LAYOUT == LAYOUT_CELLS || LAYOUT == LAYOUT_POLY) {
+        constexpr int shift = LAYOUT == LAYOUT_POLY || KIND == ST_F32 ? 5 : (KIND == ST_U8 || KIND == ST_U8B) ? 3 : 4;
+        return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)(1 << shift), (int)(bytes >> shift),
+                                                 kRsrcWord3);
+    } else {
+        return make_rsrc(p, bytes);
+    }
+}
+
 // Member-wise copy of a volume description from any address space (the
 // fields that are not used afterwards cost nothing).
 template <class T>
@@ -306,14 +321,23 @@ typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
+// Structured-buffer loads of the cell-packed layouts: the descriptor's record
+// size is the cell's, the hardware scales the record index (no byte-offset
+// shift per sample), and the bounds check counts records -- an index past the
+// last cell reads zero, as an offset past the end of a raw buffer does.
+__device__ u32x4 struct_load_b128(__amdgpu_buffer_rsrc_t r, uint32_t index, uint32_t voffset, uint32_t soffset,
+                                  int aux) __asm("llvm.amdgcn.struct.ptr.buffer.load.v4i32");
+__device__ u32x2 struct_load_b64(__amdgpu_buffer_rsrc_t r, uint32_t index, uint32_t voffset, uint32_t soffset,
+                                 int aux) __asm("llvm.amdgcn.struct.ptr.buffer.load.v2i32");
+
 template <int KIND>
 struct CellBits;
 template <>
 struct CellBits<ST_U8> {
     static constexpr int shift = 3;
     using Raw = u32x2;
-    static __device__ __forceinline__ Raw load(__amdgpu_buffer_rsrc_t r, uint32_t off) {
-        return __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+    static __device__ __forceinline__ Raw load(__amdgpu_buffer_rsrc_t r, uint32_t cell) {
+        return struct_load_b64(r, cell, 0, 0, 0);
     }
     static __device__ __forceinline__ void unpack(const Raw& w, float c[8]) {
 #pragma unroll
@@ -324,8 +348,8 @@ template <>
 struct CellBits<ST_U16> {
     static constexpr int shift = 4;
     using Raw = u32x4;
-    static __device__ __forceinline__ Raw load(__amdgpu_buffer_rsrc_t r, uint32_t off) {
-        return __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+    static __device__ __forceinline__ Raw load(__amdgpu_buffer_rsrc_t r, uint32_t cell) {
+        return struct_load_b128(r, cell, 0, 0, 0);
     }
     static __device__ __forceinline__ void unpack(const Raw& w, float c[8]) {
 #pragma unroll
@@ -339,8 +363,8 @@ template <>
 struct CellBits<ST_F16> {
     static constexpr int shift = 4;
     using Raw = u32x4;
-    static __device__ __forceinline__ Raw load(__amdgpu_buffer_rsrc_t r, uint32_t off) {
-        return __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+    static __device__ __forceinline__ Raw load(__amdgpu_buffer_rsrc_t r, uint32_t cell) {
+        return struct_load_b128(r, cell, 0, 0, 0);
     }
     static __device__ __forceinline__ void unpack(const Raw& w, float c[8]) {
 #pragma unroll
@@ -357,10 +381,10 @@ struct CellBits<ST_F32> {
         u32x4 a;
         u32x4 b;
     };
-    static __device__ __forceinline__ Raw load(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    static __device__ __forceinline__ Raw load(__amdgpu_buffer_rsrc_t r, uint32_t cell) {
         Raw w;
-        w.a = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
-        w.b = __builtin_amdgcn_raw_buffer_load_b128(r, off, 16, 0);
+        w.a = struct_load_b128(r, cell, 0, 0, 0);
+        w.b = struct_load_b128(r, cell, 16, 0, 0);
         return w;
     }
     static __device__ __forceinline__ void unpack(const Raw& w, float c[8]) {
@@ -401,7 +425,7 @@ struct Sampler<ST_U15, LAYOUT_CELLS> {
     template <class VOL>
     static __device__ __forceinline__ Raw load(__amdgpu_buffer_rsrc_t r, const VOL& vol, const Corners&,
                                                const long long Q[3]) {
-        return __builtin_amdgcn_raw_buffer_load_b128(r, cell_index(vol, Q) << 4, 0, 0);
+        return struct_load_b128(r, cell_index(vol, Q), 0, 0, 0);
     }
     static __device__ __forceinline__ float value(const Raw& w, float fx, float fy, float fz) {
         float x[4];
@@ -434,7 +458,7 @@ struct Sampler<ST_U12, LAYOUT_CELLS> {
     template <class VOL>
     static __device__ __forceinline__ Raw load(__amdgpu_buffer_rsrc_t r, const VOL& vol, const Corners&,
                                                const long long Q[3]) {
-        return __builtin_amdgcn_raw_buffer_load_b128(r, cell_index(vol, Q) << 4, 0, 0);
+        return struct_load_b128(r, cell_index(vol, Q), 0, 0, 0);
     }
     static __device__ __forceinline__ float stored(const Raw& w, float fx, float fy, float fz) {
         float x[4];
@@ -491,7 +515,7 @@ struct Sampler<KIND, LAYOUT_CELLS> {
     template <class VOL>
     static __device__ __forceinline__ Raw load(__amdgpu_buffer_rsrc_t r, const VOL& vol, const Corners&,
                                                const long long Q[3]) {
-        return B::load(r, cell_index(vol, Q) << B::shift);
+        return B::load(r, cell_index(vol, Q));
     }
     static __device__ __forceinline__ float value(const Raw& w, float fx, float fy, float fz) {
         float c[8];
@@ -509,7 +533,7 @@ struct Sampler<KIND, LAYOUT_POLY> {
     template <class VOL>
     static __device__ __forceinline__ Raw load(__amdgpu_buffer_rsrc_t r, const VOL& vol, const Corners&,
                                                const long long Q[3]) {
-        return B::load(r, cell_index(vol, Q) << 5);
+        return B::load(r, cell_index(vol, Q));
     }
     static __device__ __forceinline__ float value(const Raw& w, float fx, float fy, float fz) {
         const f32x4 a = __builtin_bit_cast(f32x4, w.a), b = __builtin_bit_cast(f32x4, w.b);
@@ -535,7 +559,7 @@ struct Sampler<ST_U8B, LAYOUT_CELLS> {
         const uint32_t blk = __umul24(__umul24(iz >> 1, (uint32_t)vol.nb[1]) + (iy >> 1), (uint32_t)vol.nb[0]) + (ix >> 1);
         const uint32_t w = (ix & 1u) | ((iy & 1u) << 1) | ((iz & 1u) << 2);
         Raw o;
-        o.w = __builtin_amdgcn_raw_buffer_load_b64(r, (blk << 6) | (w << 3), 0, 0);
+        o.w = struct_load_b64(r, (blk << 3) | w, 0, 0, 0);
         // the codes come through the bounds-checked buffer; the parameters are a
         // plain load, so a request for a position past the grid (the next sample
         // after a ray's last, at a large step) is clamped to the last block
@@ -1171,7 +1195,7 @@ __device__ __forceinline__ void render_block(const VD& V, const float4* __restri
         tx = t - ty * V.tiles_x;
     }
     const int i = tx * ls.tile_w + (lane & (ls.tile_w - 1)), j = ty * ls.tile_h + (lane >> tw_shift);
-    const __amdgpu_buffer_rsrc_t rs = make_rsrc(V.vol.data, V.vol.data_bytes);
+    const __amdgpu_buffer_rsrc_t rs = make_vol_rsrc<KIND, LAYOUT>(V.vol.data, V.vol.data_bytes);
     const Corners cn = corners_of(LAYOUT == LAYOUT_BRICKS ? 1u : Elem<KIND>::bytes, V.vol.sy, V.vol.sz);
     int count = 0;
     if (i < V.W && j < V.H) {
@@ -1329,7 +1353,7 @@ __global__ void __launch_bounds__(256) skip_range_kernel(const VolDev vol) {
     const int E = 1 << vol.eshift;
     const int x0 = bx * E, y0 = by * E, z0 = bz * E;
     const int ex = min(E, vol.n[0] + 1 - x0), ey = min(E, vol.n[1] + 1 - y0), ez = min(E, vol.n[2] + 1 - z0);
-    const __amdgpu_buffer_rsrc_t rs = make_rsrc(vol.data, vol.data_bytes);
+    const __amdgpu_buffer_rsrc_t rs = make_vol_rsrc<KIND, LAYOUT>(vol.data, vol.data_bytes);
     const Corners cn = corners_of(LAYOUT == LAYOUT_BRICKS ? 1u : Elem<KIND>::bytes, vol.sy, vol.sz);
     float lo = INFINITY, hi = -INFINITY;
     int nan = 0;
