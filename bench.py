@@ -117,7 +117,7 @@ def load_valu(workload: str):
     return rec
 
 
-def ingest_valu(d, key, samples, cus=256, kernel="march_batch_kernel<6, 0>"):
+def ingest_valu(d, key, samples, cus=256, kernel="march_batch_kernel<6, 4>"):
     """Raw SQ/GRBM counters of the marcher (medians per dispatch of one
     rocprofv3 --pmc pass, CSVs under DIR/valu) turned into issue figures:
     SQ_INSTS_VALU wave instructions x 64 lanes against the VALU peak of 32
@@ -312,16 +312,17 @@ def _timed(fn, steps, warmup):
     return e0.elapsed_time(e1) / steps
 
 
-def _limiter(form, storage):
+def _limiter(form, storage, layout="quads"):
     """What bounds the timed kernel, with the profile summary that shows it."""
     if form in ("batch", "graph", "skip"):
         # the caches serve two thirds of the logical gathers, so the fraction
         # can exceed 1; what binds is vector-instruction issue
         text, prof = "VALU instruction issue (raw SQ_INSTS_VALU over busy cycles", \
-            f"profiles/march_batch_{storage}_brain_orbit.md"
+            f"profiles/march_batch_{storage}_{layout}_brain_orbit.md"
     else:
         # one launch per view: the longest ray's own instruction stream
-        text, prof = "the longest ray of each lone view (one launch per view", f"profiles/march_plain_{storage}_brain_orbit_views.md"
+        text, prof = "the longest ray of each lone view (one launch per view", \
+            f"profiles/march_plain_{storage}_{layout}_brain_orbit_views.md"
     here = os.path.dirname(os.path.abspath(__file__))
     return text + (f", see {prof})" if os.path.exists(os.path.join(here, prof)) else ")")
 
@@ -358,6 +359,11 @@ def _plain_caller(rt, jobs):
 def _storage(rt, args):
     """Device storage of the 12-bit uint16 phantoms (every choice holds them exactly)."""
     return {"u16": rt.U16, "u15": rt.U15, "u12": rt.U12}[args.storage]
+
+
+def _layout(rt, args):
+    return {"cells": rt.LAYOUT_CELLS, "poly": rt.LAYOUT_POLY, "linear": rt.LAYOUT_LINEAR,
+            "quads": rt.LAYOUT_QUADS}[args.layout]
 
 
 def _contract(metric, value, unit, args, ms_step, dtype, config, **extra):
@@ -469,12 +475,12 @@ def bench_projection(args):
     vol_np = W.phantom_brain(vs.seed, dims=vs.dims, spacing=vs.spacing)
     cams = W.orbit_cameras(vs.dims, vs.spacing, n_views)
     torch.cuda.set_device(0)
-    st = _storage(rt, args)
-    vol = rt.Volume(vol_np, vs.spacing, storage=st)
+    st, lay = _storage(rt, args), _layout(rt, args)
+    vol = rt.Volume(vol_np, vs.spacing, storage=st, layout=lay)
     tf_np = W.random_tf(ts.K, ts.seed, alpha_max=ts.alpha_max)
     results = {}
-    plan = rt.BatchPlan(n_views, st)
-    plan_s = rt.BatchPlan(n_views, st, skip_empty=True)
+    plan = rt.BatchPlan(n_views, st, layout=lay)
+    plan_s = rt.BatchPlan(n_views, st, layout=lay, skip_empty=True)
     for name, fn, top, lo, hi, skip in [("composite", rt.COMPOSITE, ts.vmax, 0.0, 0.0, False),
                                         ("mip", rt.MIP, ts.vmax, 0.0, 0.0, False),
                                         ("xray", rt.XRAY, ts.vmax * 150.0, 0.0, 0.0, False),
@@ -497,8 +503,8 @@ def bench_projection(args):
                          round((samples * 16 + n_views * width * height * 16) / (ms * 1e-3) / 1e9, 1)}
     line = _contract("ray samples/sec (G/s) + fps per ray function at 512x512 over 256x256x160",
                      results["mip"]["gsamples_per_s"], "Gsamples/s", args, results["mip"]["ms_per_launch"], "f32",
-                     {"workload": "brain-ray-functions-36x512x512-u16", "volume": list(vs.dims), "views": n_views,
-                      "storage": args.storage,
+                     {"workload": f"brain-ray-functions-36x512x512-{args.storage}-{args.layout}",
+                      "volume": list(vs.dims), "views": n_views, "storage": args.storage, "layout": args.layout,
                       "image": [width, height], "step_vox": step, "tf_entries": ts.K,
                       "ray_functions": list(results), "launch": "graph"},
                      by_ray_function=results)
@@ -520,19 +526,19 @@ def bench_batch(args):
     vols, tfs = [], []
     for i, sp in enumerate(specs):
         v = W.phantom_brain(sp.seed, dims=sp.dims, spacing=sp.spacing)
-        vols.append(rt.Volume(v, sp.spacing, storage=_storage(rt, args)))
+        vols.append(rt.Volume(v, sp.spacing, storage=_storage(rt, args), layout=_layout(rt, args)))
         tfs.append(rt.TransferFunction(W.random_tf(4096, 1000 + i, alpha_max=0.05), 0.0, 4095.0))
         print(f"volume {i} {sp.dims} ready", file=sys.stderr, flush=True)
     gen_s = time.perf_counter() - t0
     jobs = [rt.Job(vols[vi], tfs[vi], cam, side, side, 0.5, 0.99) for vi, cam, side in views]
-    plan = rt.BatchPlan(len(jobs), _storage(rt, args))
+    plan = rt.BatchPlan(len(jobs), _storage(rt, args), layout=_layout(rt, args))
     samples = _count(rt, jobs)
 
     plain = _plain_caller(rt, jobs)
     ms_graph = _timed(lambda: plan.launch(jobs), args.steps, args.warmup)
     ms_plain = _timed(plain, args.steps, args.warmup)
     # the same batch with exact empty-space skipping (same images, fewer samples gathered)
-    plan_s = rt.BatchPlan(len(jobs), _storage(rt, args), skip_empty=True)
+    plan_s = rt.BatchPlan(len(jobs), _storage(rt, args), layout=_layout(rt, args), skip_empty=True)
     jobs_s = [rt.Job(vols[vi], tfs[vi], cam, side, side, 0.5, 0.99, skip_empty=True) for vi, cam, side in views]
     ms_skip = _timed(lambda: plan_s.launch(jobs_s), args.steps, args.warmup)
     torch.cuda.synchronize()
@@ -542,8 +548,9 @@ def bench_batch(args):
     g = samples / (ms_graph * 1e-3) / 1e9
     line = _contract("ray samples/sec (G/s): 128 views of 32 uneven u16 volumes, one persistent graph launch vs "
                      "128 plain launches", round(g, 3), "Gsamples/s", args, ms_graph, "f32",
-                     {"workload": "uneven-batch-32vol-128views-u16", "volumes": len(specs), "views": len(jobs),
-                      "storage": args.storage,
+                     {"workload": f"uneven-batch-32vol-128views-{args.storage}-{args.layout}", "volumes": len(specs),
+                      "views": len(jobs), "source_dtype": "u16 (12-bit range)", "storage": args.storage,
+                      "layout": args.layout,
                       "sizes": sorted({s.dims for s in specs}), "image_sides": [min(j.width for j in jobs),
                                                                               max(j.width for j in jobs)],
                       "step_vox": 0.5, "alpha_cutoff": 0.99, "tf_entries": 4096, "launch": "graph"},
@@ -744,8 +751,11 @@ def main():
     ap.add_argument("--ingest-traffic", default=None, metavar="DIR",
                     help="read rocprofv3 FETCH_SIZE/WRITE_SIZE CSVs from DIR/{fetch,write,copy_fetch,copy_write} "
                          "and record the orbit kernel's HBM bytes per launch in profiles/traffic.json")
-    ap.add_argument("--traffic-key", default="brain-orbit-36x512x512-u12:cells:graph",
-                    help="workload:layout:form the ingested counters belong to")
+    ap.add_argument("--traffic-key", default="brain-orbit-36x512x512-u12-quads:graph",
+                    help="workload:form the ingested counters belong to")
+    ap.add_argument("--valu-kernel", default="march_batch_kernel<6, 4>",
+                    help="kernel whose counters --ingest-valu reads (name and template arguments as the "
+                         "profiler prints them)")
     ap.add_argument("--ingest-valu", default=None, metavar="DIR",
                     help="read a rocprofv3 SQ/GRBM counter CSV from DIR/valu and record the orbit kernel's VALU "
                          "issue figures in profiles/valu_counters.json (key --traffic-key; needs --valu-samples)")
@@ -759,14 +769,17 @@ def main():
                          "iso-surface)")
     ap.add_argument("--tile-order", type=int, choices=[0, 1, 2], default=0,
                     help="serve: tile order of the executor's plans (0 = its default, spread; 1 compact; 2 spread)")
-    ap.add_argument("--layout", choices=["cells", "poly", "linear"], default="cells",
-                    help="device layout of the orbit volume")
+    ap.add_argument("--layout", choices=["cells", "poly", "linear", "quads"], default=None,
+                    help="device layout of the orbit volume (and of every volume of the batch workload); "
+                         "default: quad bricks for u12/u16 storage, cells for u15")
     ap.add_argument("--storage", choices=["u16", "u15", "u12"], default="u12",
                     help="device storage of the 12-bit uint16 phantoms, all exact for them (u15: x-pairs as "
                          "differences, images bit-identical to u16; u12: halves of value-2048, images equal to "
                          "u16 within binary32 rounding); the orbit compares its images with u16 storage in the "
                          "run; the precision workload always measures its own list")
     args = ap.parse_args()
+    if args.layout is None:
+        args.layout = "cells" if args.storage == "u15" else "quads"
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py renders on exactly one GPU: the raycaster has no multi-GPU path "
@@ -787,7 +800,7 @@ def main():
     if args.ingest_valu:
         if args.valu_samples <= 0:
             raise SystemExit("--ingest-valu needs --valu-samples")
-        return ingest_valu(args.ingest_valu, args.traffic_key, args.valu_samples)
+        return ingest_valu(args.ingest_valu, args.traffic_key, args.valu_samples, kernel=args.valu_kernel)
     if args.workload == "precision":
         return bench_precision(args)
     if args.workload == "batch":
@@ -806,10 +819,8 @@ def main():
 
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
-    layout = {"cells": rt.LAYOUT_CELLS, "poly": rt.LAYOUT_POLY, "linear": rt.LAYOUT_LINEAR}[args.layout]
+    layout = _layout(rt, args)
     storage = _storage(rt, args)
-    if storage != rt.U16 and layout != rt.LAYOUT_CELLS:
-        raise SystemExit(args.storage + " storage exists in the cell layout only")
     vol = rt.Volume(vol_np, vs.spacing, storage=storage, layout=layout)
     tf = rt.TransferFunction(tf_np, ts.vmin, ts.vmax)
     outs = [torch.empty((height, width, 4), dtype=torch.float32, device="cuda") for _ in range(n_views)]
@@ -927,8 +938,8 @@ def main():
     bytes_per_launch = algo_bytes / launches_per_step
     samples_per_launch = samples_per_step / launches_per_step
     ms_per_launch = ms_step / launches_per_step
-    workload = f"brain-orbit-36x512x512-{args.storage}"
-    key = workload + ":" + args.layout + ":" + best
+    workload = f"brain-orbit-36x512x512-{args.storage}-{args.layout}"
+    key = workload + ":" + best
     traffic = load_traffic(key)
     roof = None
     if best != "skip":  # skipped samples are never gathered: no per-sample roofline for that form
@@ -948,7 +959,7 @@ def main():
             "valu_per_sample_from": "VALU instructions per sample of the compositing loop in the built gfx950 "
                                     "code object (paper_1211_5595_amd/isa.py)",
             "samples_per_launch": int(samples_per_launch),
-            "limiter": _limiter(best, args.storage),
+            "limiter": _limiter(best, args.storage, args.layout),
             "logical_gather": {"bytes_per_launch": int(bytes_per_launch), "GB_per_s": gb(bytes_per_launch),
                                "frac_of_hbm_peak": round(bytes_per_launch / (ms_per_launch * 1e-3) / 1e9
                                                          / PEAK_HBM_GBS, 4),

@@ -93,9 +93,16 @@ typedef enum {
                            * cell use its owning brick's (lo, scale), kept once per 2x2x2 block */
     RT_LAYOUT_LINEAR = 1, /* RT_U8/RT_U16/RT_F16/RT_F32: the bordered grid in C order (1x the grid) */
     RT_LAYOUT_BRICKS = 2, /* RT_U8_BRICKSCALED: per brick the codes of local nodes -1..B+1 ((B+3)^3) */
-    RT_LAYOUT_POLY = 3    /* RT_U8/RT_U16: every cell stores the 8 coefficients of its trilinear polynomial
+    RT_LAYOUT_POLY = 3,   /* RT_U8/RT_U16: every cell stores the 8 coefficients of its trilinear polynomial
                            * as binary32 (exact for integer data), cells in 2x2x2 blocks (32 B per cell);
                            * a sample then costs 7 fused multiply-adds */
+    RT_LAYOUT_QUADS = 4   /* RT_U16/RT_U12: quad bricks.  A quad is the 2x2 nodes of a padded cell column at one
+                           * padded layer (8 bytes); a brick holds 2x2 columns by 4 layers (128 bytes, 3 cells
+                           * deep, consecutive bricks in z sharing a layer), so a sample's cell is the quads of
+                           * its two layers, one 16-byte load, in the cell layout's word order: images equal
+                           * those of RT_LAYOUT_CELLS of the same storage type bit for bit, in 2/3 of the
+                           * memory (5.3 bytes of storage per 16-bit value against 8).  At most 65533 slices,
+                           * 2^20 bricks per z-brick slice, 2 GiB in all. */
 } rt_layout;
 
 /* Ray functions (Section 4.1 list; Section 2.4 for maximum intensity and

@@ -33,7 +33,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "librtvol.so")
 
 U8, U16, F16, F32, U8_BRICKSCALED, U15, U12 = 0, 1, 2, 3, 4, 5, 6
-LAYOUT_CELLS, LAYOUT_LINEAR, LAYOUT_BRICKS, LAYOUT_POLY = 0, 1, 2, 3
+LAYOUT_CELLS, LAYOUT_LINEAR, LAYOUT_BRICKS, LAYOUT_POLY, LAYOUT_QUADS = 0, 1, 2, 3, 4
 COMPOSITE, MIP, XRAY, AVERAGE, ISO, THRESHOLD = range(6)
 _DTYPE_CODE = {np.dtype(np.uint8): U8, np.dtype(np.uint16): U16, np.dtype(np.float16): F16,
                np.dtype(np.float32): F32}
@@ -354,7 +354,8 @@ class Volume:
 
     ``values``: numpy array or CUDA tensor, C-order [z][y][x] of uint8,
     uint16, float16 or float32.  ``storage``: one of U8, U16, F16, F32
-    (``layout`` LAYOUT_CELLS or LAYOUT_LINEAR; LAYOUT_POLY for U8/U16) or
+    (``layout`` LAYOUT_CELLS or LAYOUT_LINEAR; LAYOUT_POLY for U8/U16;
+    LAYOUT_QUADS for U16 and U12, which also take LAYOUT_CELLS) or
     U8_BRICKSCALED (``brick`` 8/16/32, ``layout`` LAYOUT_CELLS or
     LAYOUT_BRICKS).  With ``stream`` given, the conversion runs there after
     the work already queued on the current stream (which produced the

@@ -2,7 +2,7 @@
 
 Tunables: the ray tile of one wavefront (8x8, 16x4, 4x16, 32x2 pixels), the
 wavefronts per workgroup (4, 8, 12 for fixed steps; 4, 8, 16 with skipping) and, per volume at creation, the storage
-layout (cell-packed, polynomial cells for integer data, or linear; for 8-bit
+layout (cell-packed, polynomial cells for integer data, x-pairs for 16- and 12-bit data, or linear; for 8-bit
 brick storage the brick edge 8, 16 or 32) or, for integer data, the storage
 type among the encodings that hold the grid exactly (tune_storage).  Tile shape and wavefronts never
 change a pixel; the cell-packed and linear layouts render the same image bit
@@ -154,18 +154,18 @@ def exact_storages(values) -> List[Tuple[int, int]]:
     half cells when it is at most 4096 (both in the cell layout).  Float data
     has no alternative to its own type here (empty list)."""
     import numpy as np
-    from . import LAYOUT_CELLS, LAYOUT_LINEAR, LAYOUT_POLY, U8, U12, U15, U16
+    from . import LAYOUT_CELLS, LAYOUT_LINEAR, LAYOUT_POLY, LAYOUT_QUADS, U8, U12, U15, U16
     dt = np.asarray(values).dtype
     if dt not in (np.uint8, np.uint16):
         return []
     vmax = int(np.asarray(values).max()) if np.asarray(values).size else 0
-    out = [(U16, LAYOUT_CELLS), (U16, LAYOUT_POLY), (U16, LAYOUT_LINEAR)]
+    out = [(U16, LAYOUT_CELLS), (U16, LAYOUT_POLY), (U16, LAYOUT_LINEAR), (U16, LAYOUT_QUADS)]
     if dt == np.uint8:
         out = [(U8, LAYOUT_CELLS), (U8, LAYOUT_POLY), (U8, LAYOUT_LINEAR)] + out
     if vmax <= 32767:
         out.append((U15, LAYOUT_CELLS))
     if vmax <= 4096:
-        out.append((U12, LAYOUT_CELLS))
+        out += [(U12, LAYOUT_CELLS), (U12, LAYOUT_QUADS)]
     return out
 
 
@@ -214,8 +214,8 @@ def tune_layout(values, spacing, storage: int, tf, cameras, width: int, height: 
     """Choose the storage layout (and brick edge for 8-bit brick storage) of a
     volume by timing batched renders of representative views.  Candidates are
     (layout, brick) pairs."""
-    from . import (Job, LAYOUT_BRICKS, LAYOUT_CELLS, LAYOUT_LINEAR, LAYOUT_POLY, U8, U16, U8_BRICKSCALED, Volume,
-                   render_batch)
+    from . import (Job, LAYOUT_BRICKS, LAYOUT_CELLS, LAYOUT_LINEAR, LAYOUT_POLY, LAYOUT_QUADS, U8, U12, U16,
+                   U8_BRICKSCALED, Volume, render_batch)
     import torch
     nz, ny, nx = values.shape
     key = f"{_gpu_arch()}|layout|s{storage}|v{size_class(nx * ny * nz)}|i{size_class(width * height)}"
@@ -226,8 +226,12 @@ def tune_layout(values, spacing, storage: int, tf, cameras, width: int, height: 
     if candidates is None:
         if storage == U8_BRICKSCALED:
             candidates = [(l, b) for l in (LAYOUT_CELLS, LAYOUT_BRICKS) for b in (8, 16, 32)]
-        elif storage in (U8, U16):
+        elif storage == U16:
+            candidates = [(LAYOUT_CELLS, 0), (LAYOUT_POLY, 0), (LAYOUT_LINEAR, 0), (LAYOUT_QUADS, 0)]
+        elif storage == U8:
             candidates = [(LAYOUT_CELLS, 0), (LAYOUT_POLY, 0), (LAYOUT_LINEAR, 0)]
+        elif storage == U12:
+            candidates = [(LAYOUT_CELLS, 0), (LAYOUT_QUADS, 0)]
         else:
             candidates = [(LAYOUT_CELLS, 0), (LAYOUT_LINEAR, 0)]
 

@@ -202,6 +202,11 @@ __device__ __forceinline__ uint32_t mad24_s(uint32_t a, uint32_t b, uint32_t c) 
     asm("v_mad_u32_u24 %0, %1, %2, %3" : "=v"(d) : "v"(a), "s"(b), "v"(c));
     return d;
 }
+__device__ __forceinline__ uint32_t mul24_s(uint32_t a, uint32_t b) {
+    uint32_t d;
+    asm("v_mul_u32_u24 %0, %1, %2" : "=v"(d) : "v"(a), "s"(b));
+    return d;
+}
 __device__ __forceinline__ uint32_t mad24_imm6(uint32_t a, uint32_t c) {
     uint32_t d;
     asm("v_mad_u32_u24 %0, %1, 6, %2" : "=v"(d) : "v"(a), "v"(c));
@@ -468,6 +473,55 @@ struct Sampler<ST_U12, LAYOUT_CELLS> {
     }
     static __device__ __forceinline__ float value(const Raw& w, float fx, float fy, float fz) {
         return stored(w, fx, fy, fz) + bias;
+    }
+};
+
+// Quad bricks: the quads of the sample's cell's two layers are 16
+// consecutive bytes, one load from a raw buffer (whose bounds check covers
+// the whole vector offset).  In 8-byte units the cell's offset is
+// 4x + 8y + z + 8 (x>>1) + sy (y>>1) + sz (z/3), with z/3 as
+// (z * 43691) >> 17 (exact for z < 2^17; the layout keeps z below 2^16).
+// The four words are those of a 16-byte cell, so the interpolation is the
+// cell samplers' own and images equal the cell layout's bit for bit.
+__device__ __forceinline__ uint32_t div3(uint32_t z) {
+    uint32_t d;
+    asm("v_mul_u32_u24 %0, 0xaaab, %1" : "=v"(d) : "v"(z));
+    return d >> 17;
+}
+__device__ __forceinline__ uint32_t mad24_imm8(uint32_t a, uint32_t c) {
+    uint32_t d;
+    asm("v_mad_u32_u24 %0, %1, 8, %2" : "=v"(d) : "v"(a), "v"(c));
+    return d;
+}
+struct QuadsLoad {
+    using Raw = u32x4;
+    template <class VOL>
+    static __device__ __forceinline__ Raw load(__amdgpu_buffer_rsrc_t r, const VOL& vol, const Corners&,
+                                               const long long Q[3]) {
+        const uint32_t ix = hiword(Q[0]), iy = hiword(Q[1]), iz = hiword(Q[2]);
+        uint32_t c = lshl_add(lshl_add(iy, 1, ix), 2, iz);
+        c = mad24_imm8(ix >> 1, c);
+        c = mad24_s(iy >> 1, vol.sy, c);
+        c = mad24_s(div3(iz), vol.sz, c);
+        return __builtin_amdgcn_raw_buffer_load_b128(r, c << 3, 0, 0);
+    }
+};
+template <>
+struct Sampler<ST_U12, LAYOUT_QUADS> : QuadsLoad {
+    static constexpr float bias = Sampler<ST_U12, LAYOUT_CELLS>::bias;
+    static __device__ __forceinline__ float stored(const Raw& w, float fx, float fy, float fz) {
+        return Sampler<ST_U12, LAYOUT_CELLS>::stored(w, fx, fy, fz);
+    }
+    static __device__ __forceinline__ float value(const Raw& w, float fx, float fy, float fz) {
+        return Sampler<ST_U12, LAYOUT_CELLS>::value(w, fx, fy, fz);
+    }
+};
+template <>
+struct Sampler<ST_U16, LAYOUT_QUADS> : QuadsLoad {
+    static __device__ __forceinline__ float value(const Raw& w, float fx, float fy, float fz) {
+        float c[8];
+        CellBits<ST_U16>::unpack(w, c);
+        return trilinear8(c, fx, fy, fz);
     }
 };
 
@@ -901,15 +955,26 @@ __device__ __forceinline__ void march_pixel(const VD& V, const float4* __restric
                 bool liveA = true;
                 if (go) {
                     for (;;) {
+                        // each position passes through an empty asm: the loop
+                        // then keeps one 64-bit induction variable per axis
+                        // (left alone, strength reduction split some layouts'
+                        // positions into a base and an offset, adding several
+                        // adds per sample)
                         long long P1[3];
 #pragma unroll
-                        for (int q = 0; q < 3; ++q) P1[q] = P[q] + R.dQ[q];
+                        for (int q = 0; q < 3; ++q) {
+                            P1[q] = P[q] + R.dQ[q];
+                            asm("" : "+v"(P1[q]));
+                        }
                         wb = S::load(rsp, vol, cn, P1);
                         __builtin_amdgcn_sched_barrier(0);
                         composite(wa, P);
                         liveA = T > thr;  // r >= 2 here: sample B exists
 #pragma unroll
-                        for (int q = 0; q < 3; ++q) P[q] = P1[q] + R.dQ[q];
+                        for (int q = 0; q < 3; ++q) {
+                            P[q] = P1[q] + R.dQ[q];
+                            asm("" : "+v"(P[q]));
+                        }
                         wa = S::load(rsp, vol, cn, P);
                         __builtin_amdgcn_sched_barrier(0);
                         if (liveA) composite(wb, P1);
@@ -1480,9 +1545,10 @@ hipError_t launch_march_plain(const ViewDesc& v, const LaunchShape& ls, unsigned
                    : L == LAYOUT_POLY ? plain_launch<ST_U8, LAYOUT_POLY>(v, ls, counter, s)
                                       : plain_launch<ST_U8, LAYOUT_LINEAR>(v, ls, counter, s);
         case ST_U16:
-            return L == LAYOUT_CELLS  ? plain_launch<ST_U16, LAYOUT_CELLS>(v, ls, counter, s)
-                   : L == LAYOUT_POLY ? plain_launch<ST_U16, LAYOUT_POLY>(v, ls, counter, s)
-                                      : plain_launch<ST_U16, LAYOUT_LINEAR>(v, ls, counter, s);
+            return L == LAYOUT_CELLS    ? plain_launch<ST_U16, LAYOUT_CELLS>(v, ls, counter, s)
+                   : L == LAYOUT_POLY   ? plain_launch<ST_U16, LAYOUT_POLY>(v, ls, counter, s)
+                   : L == LAYOUT_QUADS ? plain_launch<ST_U16, LAYOUT_QUADS>(v, ls, counter, s)
+                                        : plain_launch<ST_U16, LAYOUT_LINEAR>(v, ls, counter, s);
         case ST_F16:
             return L == LAYOUT_CELLS ? plain_launch<ST_F16, LAYOUT_CELLS>(v, ls, counter, s)
                                      : plain_launch<ST_F16, LAYOUT_LINEAR>(v, ls, counter, s);
@@ -1495,7 +1561,9 @@ hipError_t launch_march_plain(const ViewDesc& v, const LaunchShape& ls, unsigned
         case ST_U15:
             return L == LAYOUT_CELLS ? plain_launch<ST_U15, LAYOUT_CELLS>(v, ls, counter, s) : hipErrorInvalidValue;
         case ST_U12:
-            return L == LAYOUT_CELLS ? plain_launch<ST_U12, LAYOUT_CELLS>(v, ls, counter, s) : hipErrorInvalidValue;
+            return L == LAYOUT_CELLS    ? plain_launch<ST_U12, LAYOUT_CELLS>(v, ls, counter, s)
+                   : L == LAYOUT_QUADS ? plain_launch<ST_U12, LAYOUT_QUADS>(v, ls, counter, s)
+                                        : hipErrorInvalidValue;
         default: return hipErrorInvalidValue;
     }
 }
@@ -1508,9 +1576,10 @@ hipError_t launch_skip_ranges(const VolDev& v, hipStream_t s) {
                    : L == LAYOUT_POLY ? skip_range_launch<ST_U8, LAYOUT_POLY>(v, s)
                                       : skip_range_launch<ST_U8, LAYOUT_LINEAR>(v, s);
         case ST_U16:
-            return L == LAYOUT_CELLS  ? skip_range_launch<ST_U16, LAYOUT_CELLS>(v, s)
-                   : L == LAYOUT_POLY ? skip_range_launch<ST_U16, LAYOUT_POLY>(v, s)
-                                      : skip_range_launch<ST_U16, LAYOUT_LINEAR>(v, s);
+            return L == LAYOUT_CELLS    ? skip_range_launch<ST_U16, LAYOUT_CELLS>(v, s)
+                   : L == LAYOUT_POLY   ? skip_range_launch<ST_U16, LAYOUT_POLY>(v, s)
+                   : L == LAYOUT_QUADS ? skip_range_launch<ST_U16, LAYOUT_QUADS>(v, s)
+                                        : skip_range_launch<ST_U16, LAYOUT_LINEAR>(v, s);
         case ST_F16:
             return L == LAYOUT_CELLS ? skip_range_launch<ST_F16, LAYOUT_CELLS>(v, s)
                                      : skip_range_launch<ST_F16, LAYOUT_LINEAR>(v, s);
@@ -1523,14 +1592,16 @@ hipError_t launch_skip_ranges(const VolDev& v, hipStream_t s) {
         case ST_U15:
             return L == LAYOUT_CELLS ? skip_range_launch<ST_U15, LAYOUT_CELLS>(v, s) : hipErrorInvalidValue;
         case ST_U12:
-            return L == LAYOUT_CELLS ? skip_range_launch<ST_U12, LAYOUT_CELLS>(v, s) : hipErrorInvalidValue;
+            return L == LAYOUT_CELLS    ? skip_range_launch<ST_U12, LAYOUT_CELLS>(v, s)
+                   : L == LAYOUT_QUADS ? skip_range_launch<ST_U12, LAYOUT_QUADS>(v, s)
+                                        : hipErrorInvalidValue;
         default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_march_batch(int kind, int layout, void* workspace, int grid, const LaunchShape& ls, int max_k,
                               bool skip, hipStream_t s) {
-    const bool C = layout == LAYOUT_CELLS, P = layout == LAYOUT_POLY;
+    const bool C = layout == LAYOUT_CELLS, P = layout == LAYOUT_POLY, X = layout == LAYOUT_QUADS;
     switch (kind) {
         case ST_U8:
             return C   ? batch_launch<ST_U8, LAYOUT_CELLS>(workspace, grid, ls, max_k, skip, s)
@@ -1539,6 +1610,7 @@ hipError_t launch_march_batch(int kind, int layout, void* workspace, int grid, c
         case ST_U16:
             return C   ? batch_launch<ST_U16, LAYOUT_CELLS>(workspace, grid, ls, max_k, skip, s)
                    : P ? batch_launch<ST_U16, LAYOUT_POLY>(workspace, grid, ls, max_k, skip, s)
+                   : X ? batch_launch<ST_U16, LAYOUT_QUADS>(workspace, grid, ls, max_k, skip, s)
                        : batch_launch<ST_U16, LAYOUT_LINEAR>(workspace, grid, ls, max_k, skip, s);
         case ST_F16:
             return C ? batch_launch<ST_F16, LAYOUT_CELLS>(workspace, grid, ls, max_k, skip, s)
@@ -1552,7 +1624,9 @@ hipError_t launch_march_batch(int kind, int layout, void* workspace, int grid, c
         case ST_U15:
             return C ? batch_launch<ST_U15, LAYOUT_CELLS>(workspace, grid, ls, max_k, skip, s) : hipErrorInvalidValue;
         case ST_U12:
-            return C ? batch_launch<ST_U12, LAYOUT_CELLS>(workspace, grid, ls, max_k, skip, s) : hipErrorInvalidValue;
+            return C   ? batch_launch<ST_U12, LAYOUT_CELLS>(workspace, grid, ls, max_k, skip, s)
+                   : X ? batch_launch<ST_U12, LAYOUT_QUADS>(workspace, grid, ls, max_k, skip, s)
+                       : hipErrorInvalidValue;
         default: return hipErrorInvalidValue;
     }
 }

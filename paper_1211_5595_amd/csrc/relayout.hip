@@ -157,6 +157,43 @@ __global__ void __launch_bounds__(256) relayout_cells_h12_kernel(const typename 
     }
 }
 
+// Quad bricks: one thread per 8-byte quad slot.  Slot e: brick e / 16
+// (x-fastest over nbx, nby, nbz), column c = (e / 4) % 4 of the brick
+// (x = 2 bx + (c & 1), y = 2 by + (c >> 1)), layer l = e % 4 (z = 3 bz + l);
+// the quad holds volume nodes clamp(x-1..x, y-1..y) of slice clamp(z-1),
+// x fastest: 16-bit integers, or (H12) the binary16 halves of
+// (value - 2048) with the value clamped to 0..4096 as in the 12-bit cells.
+template <int SRC, bool H12>
+__global__ void __launch_bounds__(256) relayout_quads_kernel(const typename Src<SRC>::T* __restrict__ src,
+                                                              uint2* __restrict__ dst, int nx, int ny, int nz,
+                                                              int nbx, int nby, int nbz) {
+    const size_t total = (size_t)16 * nbx * nby * nbz;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+        const int l = (int)(e & 3), c = (int)((e >> 2) & 3);
+        const size_t blk = e >> 4;
+        const int bx = (int)(blk % nbx);
+        const size_t t = blk / nbx;
+        const int by = (int)(t % nby), bz = (int)(t / nby);
+        const int cx = 2 * bx + (c & 1), cy = 2 * by + (c >> 1), lz = 3 * bz + l;
+        const int i0 = min(max(cx - 1, 0), nx - 1), i1 = min(cx, nx - 1);
+        const int j0 = min(max(cy - 1, 0), ny - 1), j1 = min(cy, ny - 1);
+        const int k = min(max(lz - 1, 0), nz - 1);
+        const size_t r0 = ((size_t)k * ny + j0) * nx, r1 = ((size_t)k * ny + j1) * nx;
+        const int v[4] = {(int)src[r0 + i0], (int)src[r0 + i1], (int)src[r1 + i0], (int)src[r1 + i1]};
+        unsigned int w[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if constexpr (H12) {
+                const _Float16 h = (_Float16)(min(v[q], 4096) - 2048);
+                w[q] = __builtin_bit_cast(unsigned short, h);
+            } else {
+                w[q] = (unsigned int)(v[q] & 0xffff);
+            }
+        }
+        dst[e] = make_uint2(w[0] | (w[1] << 16), w[2] | (w[3] << 16));
+    }
+}
+
 // Polynomial cells: as relayout_cells_kernel, but the 8 stored values are the
 // coefficients of the cell's trilinear polynomial, formed in integer
 // arithmetic from integer corners and stored as exact binary32 values.
@@ -423,6 +460,39 @@ hipError_t launch_relayout_poly(const void* src, int src_kind, const int32_t n[3
             hipLaunchKernelGGL(relayout_poly_kernel<ST_U16>, dim3(grid_for(total, 256)), dim3(256), 0, s,
                                static_cast<const unsigned short*>(src), d, n[0], n[1], n[2], nb[0], nb[1], nb[2]);
             break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_relayout_quads(const void* src, int src_kind, int dst_kind, const int32_t n[3],
+                                 const int32_t nb[3], void* dst, hipStream_t s) {
+    const size_t total = (size_t)16 * nb[0] * nb[1] * nb[2];
+    uint2* d = static_cast<uint2*>(dst);
+    const int g = grid_for(total, 256);
+    if (dst_kind != ST_U16 && dst_kind != ST_U12) return hipErrorInvalidValue;
+    const bool h12 = dst_kind == ST_U12;
+    switch (src_kind) {
+        case ST_U8: {
+            const unsigned char* p = static_cast<const unsigned char*>(src);
+            if (h12)
+                hipLaunchKernelGGL((relayout_quads_kernel<ST_U8, true>), dim3(g), dim3(256), 0, s, p, d, n[0], n[1],
+                                   n[2], nb[0], nb[1], nb[2]);
+            else
+                hipLaunchKernelGGL((relayout_quads_kernel<ST_U8, false>), dim3(g), dim3(256), 0, s, p, d, n[0], n[1],
+                                   n[2], nb[0], nb[1], nb[2]);
+            break;
+        }
+        case ST_U16: {
+            const unsigned short* p = static_cast<const unsigned short*>(src);
+            if (h12)
+                hipLaunchKernelGGL((relayout_quads_kernel<ST_U16, true>), dim3(g), dim3(256), 0, s, p, d, n[0], n[1],
+                                   n[2], nb[0], nb[1], nb[2]);
+            else
+                hipLaunchKernelGGL((relayout_quads_kernel<ST_U16, false>), dim3(g), dim3(256), 0, s, p, d, n[0],
+                                   n[1], n[2], nb[0], nb[1], nb[2]);
+            break;
+        }
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

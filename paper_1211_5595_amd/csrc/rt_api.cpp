@@ -82,13 +82,15 @@ int elem_bytes(int kind) {
 // Which layouts a storage type can be held in.
 bool layout_allowed(int storage, int layout) {
     switch (storage) {
-        case RT_U8:
-        case RT_U16: return layout == RT_LAYOUT_CELLS || layout == RT_LAYOUT_LINEAR || layout == RT_LAYOUT_POLY;
+        case RT_U8: return layout == RT_LAYOUT_CELLS || layout == RT_LAYOUT_LINEAR || layout == RT_LAYOUT_POLY;
+        case RT_U16:
+            return layout == RT_LAYOUT_CELLS || layout == RT_LAYOUT_LINEAR || layout == RT_LAYOUT_POLY ||
+                   layout == RT_LAYOUT_QUADS;
         case RT_F16:
         case RT_F32: return layout == RT_LAYOUT_CELLS || layout == RT_LAYOUT_LINEAR;
         case RT_U8_BRICKSCALED: return layout == RT_LAYOUT_CELLS || layout == RT_LAYOUT_BRICKS;
-        case RT_U15:
-        case RT_U12: return layout == RT_LAYOUT_CELLS;
+        case RT_U15: return layout == RT_LAYOUT_CELLS;
+        case RT_U12: return layout == RT_LAYOUT_CELLS || layout == RT_LAYOUT_QUADS;
         default: return false;
     }
 }
@@ -217,6 +219,22 @@ rt_status compute_data_layout(const int64_t dims[3], int storage, int layout, in
             return fail(RT_ERR_UNSUPPORTED, "slice too large for the cell-packed layout (24-bit strides)");
         L.sy = (uint32_t)(8 * (size_t)L.nb[0] - 4);
         L.sz = (uint32_t)(8 * (size_t)L.nb[0] * L.nb[1] - 8);
+    } else if (layout == RT_LAYOUT_QUADS) {
+        // quad bricks: 2x2 padded cell columns (0..n in x and y) by 4 padded
+        // layers, 128 B each, 3 cells deep (consecutive z-bricks share a
+        // layer); 8-byte-unit strides below 2^24, byte offsets below 2^31
+        L.layout = LAYOUT_QUADS;
+        L.nb[0] = (int32_t)((dims[0] + 2) / 2);
+        L.nb[1] = (int32_t)((dims[1] + 2) / 2);
+        L.nb[2] = (int32_t)((dims[2] + 3) / 3);
+        if (dims[2] + 2 >= 65536) return fail(RT_ERR_UNSUPPORTED, "more than 65533 slices in the quad layout");
+        const size_t slice = (size_t)L.nb[0] * L.nb[1];
+        if (slice * 16 >= ((size_t)1 << 24))
+            return fail(RT_ERR_UNSUPPORTED, "slice too large for the quad layout (24-bit strides)");
+        L.sy = (uint32_t)(16 * (size_t)L.nb[0] - 16);  // y-brick stride less the in-brick y step, 8 B units
+        L.sz = (uint32_t)(16 * slice - 3);                // z-brick stride less 3 layers, 8 B units
+        L.data_bytes = slice * L.nb[2] * 128;
+        if (L.data_bytes >= ((size_t)1 << 31)) return fail(RT_ERR_UNSUPPORTED, "volume larger than 2 GiB of storage");
     } else {
         L.layout = LAYOUT_LINEAR;
         L.sy = (uint32_t)(px * e);
@@ -455,7 +473,7 @@ rt_status build_batch_into(const rt_render_job* jobs, int n, const LaunchShape& 
                                  J.alpha_cutoff, J.bg_rgba, J.out_dev, J.pixel_counts, ls, J.ray_function,
                                  J.iso_value, J.iso_high, J.skip_empty, J.opacity_unit_distance, descs[i]);
         if (st != RT_OK) return fail(st, "job " + std::to_string(i) + ": " + g_last_error);
-        const int k = J.volume->dev.kind * 4 + J.volume->dev.layout;  // storage type and layout
+        const int k = J.volume->dev.kind * 8 + J.volume->dev.layout;  // storage type and layout
         if (*kind < 0) *kind = k;
         if (k != *kind) return fail(RT_ERR_UNSUPPORTED, "all volumes of a batch must share one storage type and layout");
         *max_k = std::max(*max_k, J.tf->K);
@@ -504,6 +522,7 @@ int layout_code(int layout) {
     return layout == RT_LAYOUT_LINEAR   ? LAYOUT_LINEAR
            : layout == RT_LAYOUT_BRICKS ? LAYOUT_BRICKS
            : layout == RT_LAYOUT_POLY   ? LAYOUT_POLY
+           : layout == RT_LAYOUT_QUADS ? LAYOUT_QUADS
                                         : LAYOUT_CELLS;
 }
 
@@ -513,10 +532,10 @@ namespace rtv {
 
 int storage_layout_kind(int storage, int layout) {
     if (storage < RT_U8 || storage > RT_U12 || !layout_allowed(storage, layout)) return -1;
-    return (storage == RT_U8_BRICKSCALED ? ST_U8B : storage) * 4 + layout_code(layout);
+    return (storage == RT_U8_BRICKSCALED ? ST_U8B : storage) * 8 + layout_code(layout);
 }
 
-int volume_kind(const rt_volume* vol) { return vol ? vol->dev.kind * 4 + vol->dev.layout : -1; }
+int volume_kind(const rt_volume* vol) { return vol ? vol->dev.kind * 8 + vol->dev.layout : -1; }
 
 int set_last_error(int status, const char* msg) { return fail(static_cast<rt_status>(status), msg); }
 
@@ -607,6 +626,8 @@ rt_status rt_create_volume(const void* src_dev, int src_dtype, const int64_t dim
         e = launch_relayout_cells(src_dev, src_dtype, storage, n, L.nb, base, s);
     else if (L.layout == LAYOUT_POLY)
         e = launch_relayout_poly(src_dev, src_dtype, n, L.nb, base, s);
+    else if (L.layout == LAYOUT_QUADS)
+        e = launch_relayout_quads(src_dev, src_dtype, storage, n, L.nb, base, s);
     else
         e = launch_relayout_linear(src_dev, src_dtype, storage, n, base, s);
     if (e != hipSuccess) return hip_fail(e, "relayout launch");
@@ -781,7 +802,7 @@ rt_status rt_render_batch(const rt_render_job* jobs, int n, void* workspace, siz
     g_staging.pending = true;
     const bool skip = any_skip;  // the kernel the shape was checked for
     const int grid = std::min(batch_persistent_grid(ls, max_k, skip), std::max(prefix.back(), 1));
-    e = launch_march_batch(kind / 4, kind % 4, workspace, grid, ls, max_k, skip, s);
+    e = launch_march_batch(kind / 8, kind % 8, workspace, grid, ls, max_k, skip, s);
     if (e != hipSuccess) return hip_fail(e, "batch launch");
     return RT_OK;
 }
@@ -818,7 +839,7 @@ rt_status rt_batch_plan_create(int max_jobs, int storage, int layout, void* work
     // table, whose header starts the block queue at zero.
     e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess)
-        e = launch_march_batch(p->kind / 4, p->kind % 4, workspace, p->grid, ls, kMaxK, opts && opts->skip_empty, cs);
+        e = launch_march_batch(p->kind / 8, p->kind % 8, workspace, p->grid, ls, kMaxK, opts && opts->skip_empty, cs);
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(cs, &g);
     if (e == hipSuccess) e = e2;
@@ -985,7 +1006,7 @@ rt_status rt_render_batch_noalloc(const rt_render_job* jobs, int n, unsigned lon
     if (e == hipSuccess) e = fill_workspace(w, kNoAllocDescOffset, descs, (size_t)n * sizeof(ViewDesc), s);
     if (e != hipSuccess) return hip_fail(e, "workspace fill");
     const int grid = std::min(batch_persistent_grid(ls, max_k, any_skip), std::max(prefix[n], 1));
-    e = launch_march_batch(kind / 4, kind % 4, ws, grid, ls, max_k, any_skip, s);
+    e = launch_march_batch(kind / 8, kind % 8, ws, grid, ls, max_k, any_skip, s);
     if (e != hipSuccess) return hip_fail(e, "batch launch");
     return RT_OK;
 }

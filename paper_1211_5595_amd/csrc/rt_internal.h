@@ -20,7 +20,7 @@ enum StorageKind : int { ST_U8 = 0, ST_U16 = 1, ST_F16 = 2, ST_F32 = 3, ST_U8B =
 enum RayFn : int { RT_FN_COMPOSITE = 0, RT_FN_MIP = 1, RT_FN_XRAY = 2, RT_FN_AVERAGE = 3, RT_FN_ISO = 4,
                    RT_FN_THRESHOLD = 5 };
 
-enum LayoutKind : int { LAYOUT_CELLS = 0, LAYOUT_LINEAR = 1, LAYOUT_BRICKS = 2, LAYOUT_POLY = 3 };
+enum LayoutKind : int { LAYOUT_CELLS = 0, LAYOUT_LINEAR = 1, LAYOUT_BRICKS = 2, LAYOUT_POLY = 3, LAYOUT_QUADS = 4 };
 
 // Device view of a volume in storage layout.  All layouts work on the
 // padded grid: nodes P = 0..n+1 per axis, node P holding node clamp(P-1)
@@ -40,6 +40,18 @@ enum LayoutKind : int { LAYOUT_CELLS = 0, LAYOUT_LINEAR = 1, LAYOUT_BRICKS = 2, 
 //    polynomial v = p0 + px fx + py fy + pz fz + pxy fx fy + pxz fx fz
 //    + pyz fy fz + pxyz fx fy fz (sums of at most 8 integer corners: exact).
 //  LAYOUT_LINEAR (U8/U16/F16/F32): the padded grid in C order.
+//  LAYOUT_QUADS (U16/U12): the quad of a padded cell column (x, y) at a
+//    padded layer z is its 4 nodes (x..x+1, y..y+1) at that layer, four
+//    16-bit words, x fastest (for U12 the halves of value - 2048); a cell is
+//    the quads of its two layers.  Quad bricks of 2x2 columns by 4 layers
+//    hold 3 cells in z (z-brick b: layers 3b..3b+3, the last shared with
+//    brick b+1), one 128-byte line each, x-fastest brick order; within a
+//    brick column (y&1)*2 + (x&1) holds its 4 layers contiguously, so a
+//    cell's quads are 16 consecutive bytes in the cell layout's word order.
+//    nb: bricks per axis; sy = 16 nb[0] - 16 and sz = 16 nb[0] nb[1] - 3:
+//    the y and z brick strides in 8-byte units less what the in-brick terms
+//    already count (cell offset / 8 = 4x + 8y + z + 8 (x>>1) + sy (y>>1)
+//    + sz (z/3)).
 //    For U8B the cell blocks are shifted by one cell (block = (C+1)/2) so a
 //    block never straddles a brick (B even); each block keeps the (lo,
 //    scale) of the brick owning its cells in `brick_par` (8 B per block)
@@ -157,6 +169,8 @@ hipError_t launch_skip_ranges(const VolDev& vol, hipStream_t s);
 hipError_t launch_relayout_linear(const void* src, int src_kind, int dst_kind, const int32_t n[3], void* dst,
                                   hipStream_t s);
 hipError_t launch_relayout_cells(const void* src, int src_kind, int dst_kind, const int32_t n[3],
+                                 const int32_t nb[3], void* dst, hipStream_t s);
+hipError_t launch_relayout_quads(const void* src, int src_kind, int dst_kind, const int32_t n[3],
                                  const int32_t nb[3], void* dst, hipStream_t s);
 hipError_t launch_relayout_poly(const void* src, int src_kind, const int32_t n[3], const int32_t nb[3], void* dst,
                                 hipStream_t s);

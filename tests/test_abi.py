@@ -90,6 +90,14 @@ def test_volume_bytes(rt):
     # polynomial cells (integer data): as cells, 8 binary32 coefficients each
     assert vb((256, 256, 160), rt.U16, rt.LAYOUT_POLY) == r256(129 * 129 * 81 * 8 * 8 * 4)
     assert vb((64, 64, 32), rt.U8, rt.LAYOUT_POLY) == r256(33 * 33 * 17 * 8 * 8 * 4)
+    # quad bricks (16-bit and 12-bit storage): 2x2 padded cell columns (0..n) by 3 cells in z
+    # per 128-byte brick
+    X = rt.LAYOUT_QUADS
+    assert vb((256, 256, 160), rt.U16, X) == r256(129 * 129 * 54 * 128)
+    assert vb((256, 256, 160), rt.U12, X) == r256(129 * 129 * 54 * 128)
+    assert vb((512, 512, 256), rt.U12, X) == r256(257 * 257 * 86 * 128)
+    assert vb((2, 2, 2), rt.U16, X) == r256(2 * 2 * 1 * 128)
+    assert vb((3, 3, 4), rt.U16, X) == r256(2 * 2 * 2 * 128)
     # brick-scaled, halo bricks: ceil((n-1)/B) bricks per axis, (B+3)^3 codes and 8 bytes each
     nb = 16 * 16 * 10
     assert vb((256, 256, 160), rt.U8_BRICKSCALED, rt.LAYOUT_BRICKS, 16) == \
@@ -130,6 +138,15 @@ def test_cell_layout_size_limits(rt):
     ((4, 4, 4), 6, 1, 0, "InvalidArgument"),    # 12-bit half cells: cell layout only
     ((4, 4, 4), 6, 3, 0, "InvalidArgument"),
     ((4, 4, 4), 7, 0, 0, "InvalidArgument"),
+    ((4, 4, 4), 0, 4, 0, "InvalidArgument"),    # quads: 16-bit and 12-bit storage only
+    ((4, 4, 4), 2, 4, 0, "InvalidArgument"),
+    ((4, 4, 4), 3, 4, 0, "InvalidArgument"),
+    ((4, 4, 4), 4, 4, 8, "InvalidArgument"),
+    ((4, 4, 4), 5, 4, 0, "InvalidArgument"),
+    ((4, 4, 4), 1, 5, 0, "InvalidArgument"),    # no layout 5
+    ((2048, 2046, 2), 1, 4, 0, "Unsupported"),   # 2^20 quad bricks per z-brick slice or more
+    ((1024, 1024, 1024), 6, 4, 0, "Unsupported"),  # quads of 2 GiB or more
+    ((2, 2, 65534), 1, 4, 0, "Unsupported"),      # more than 65533 slices
 ])
 def test_volume_bytes_errors(rt, dims, storage, layout, brick, exc):
     with pytest.raises(getattr(rt, exc)):

@@ -46,7 +46,7 @@ def test_tuned_launch_is_bitwise_equal_and_not_slower(tmp_path):
     assert torch.equal(a, b)
     lay = at.tune_layout(W.phantom_brain(9, dims=(64, 64, 48), spacing=sp), sp, rt.U16, tf, cams[:2], 128, 128,
                          reps=1)
-    assert lay["layout"] in (rt.LAYOUT_CELLS, rt.LAYOUT_POLY, rt.LAYOUT_LINEAR)
+    assert lay["layout"] in (rt.LAYOUT_CELLS, rt.LAYOUT_POLY, rt.LAYOUT_LINEAR, rt.LAYOUT_QUADS)
 
 
 def test_exact_storage_candidates():

@@ -13,7 +13,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 sys.path.insert(0, ROOT)
 import bench  # noqa: E402
 
-MARCH = "void rtv::(anonymous namespace)::march_batch_kernel<6, 0>(char*, rtv::LaunchShape, int, int)"
+MARCH = "void rtv::(anonymous namespace)::march_batch_kernel<6, 4>(char*, rtv::LaunchShape, int, int)"
 COPY = "__amd_rocclr_copyBuffer"
 
 
@@ -81,8 +81,9 @@ def test_percentile_interpolates():
 def test_limiter_names_the_timed_kernel():
     assert bench._limiter("graph", "u12").startswith("VALU instruction issue")
     assert bench._limiter("plain", "u12").startswith("the longest ray")
-    for form, st in (("graph", "u12"), ("plain", "u16"), ("skip", "u15")):
-        note = bench._limiter(form, st)
+    for form, st, lay in (("graph", "u12", "quads"), ("plain", "u16", "quads"), ("skip", "u15", "cells"),
+                          ("graph", "u12", "cells")):
+        note = bench._limiter(form, st, lay)
         assert note.count("(") == note.count(")")
         if "see " in note:
             assert os.path.exists(os.path.join(ROOT, note.split("see ")[1].rstrip(")")))

@@ -23,7 +23,8 @@ def test_orbit_line_fields_and_consistency():
     for k, v in (("n_gpus", 1), ("steps", 3), ("warmup", 1), ("higher_is_better", True), ("scaling", "weak"),
                  ("vs_baseline", None), ("data", "synthetic"), ("unit", "Gsamples/s")):
         assert line[k] == v, k
-    assert line["config"]["workload"] == "brain-orbit-36x512x512-u12" and line["config"]["storage"] == "u12"
+    assert line["config"]["workload"] == "brain-orbit-36x512x512-u12-quads" and line["config"]["storage"] == "u12"
+    assert line["config"]["layout"] == "quads"
     assert line["config"]["tile"] == [4, 16] and line["config"]["waves_per_block"] == 12
     samples, ms = line["samples_per_step"], line["ms_per_step"]
     assert samples > 0 and ms > 0

@@ -714,17 +714,19 @@ def test_u12_brain_views_match_oracle(rt, torch_mod, orc, brain):
 
 def test_timed_orbit_launch_matches_oracle(rt, torch_mod, orc, brain):
     """The launch the throughput figure times: all 36 orbit views in one
-    graph-captured batch plan over 12-bit half cells, 4x16-pixel tiles and 12
-    wavefronts per workgroup, in its non-counting form.  Every pixel of every
-    view against the oracle (tie-aware, 1e-5) and every pixel's sample count
-    (from the counting form of the same plan) exactly off ties; the
-    launch-wide counter against the per-pixel counts; the non-counting form
-    bitwise equal to the counting one on two replays; and the other launch
-    shapes the autotuner may pick bitwise equal to this one."""
+    graph-captured batch plan over 12-bit halves in quad bricks, 4x16-pixel
+    tiles and 12 wavefronts per workgroup, in its non-counting form.  Every
+    pixel of every view against the oracle (tie-aware, 1e-5) and every
+    pixel's sample count (from the counting form of the same plan) exactly off
+    ties; the launch-wide counter against the per-pixel counts; the
+    non-counting form bitwise equal to the counting one on two replays; the
+    same plan over the cell layout, and the other launch shapes the autotuner
+    may pick, bitwise equal to this one."""
     torch = torch_mod
-    gv = rt.Volume(brain["np"], brain["sp"], storage=rt.U12)
+    Q = rt.LAYOUT_QUADS
+    gv = rt.Volume(brain["np"], brain["sp"], storage=rt.U12, layout=Q)
     cams = brain["cams"]
-    plan = rt.BatchPlan(len(cams), rt.U12, tile=(4, 16), waves_per_block=12)
+    plan = rt.BatchPlan(len(cams), rt.U12, layout=Q, tile=(4, 16), waves_per_block=12)
     with pytest.raises(rt.Unsupported):  # fixed-step batches take at most 12 waves per workgroup
         rt.BatchPlan(len(cams), rt.U12, tile=(4, 16), waves_per_block=16)
     rt.BatchPlan(len(cams), rt.U12, tile=(4, 16), waves_per_block=16, skip_empty=True).close()
@@ -753,17 +755,27 @@ def test_timed_orbit_launch_matches_oracle(rt, torch_mod, orc, brain):
         ties += int(((ref.tie & 1) != 0).sum())
     print(f"timed orbit launch: {total} samples, 36 whole views: max err {err:.3g}, worst band distance "
           f"{worst:.3g}, {ties} tie pixels")
+    gc = rt.Volume(brain["np"], brain["sp"], storage=rt.U12)
+    cells = [rt.Job(gc, brain["gtf"], c, 512, 512, 0.5, 0.99) for c in cams]
+    pc = rt.BatchPlan(len(cams), rt.U12, tile=(4, 16), waves_per_block=12)
+    pc.launch(cells)
+    torch.cuda.synchronize()
+    for a, b in zip(timed, cells):
+        assert torch.equal(a.out, b.out), "cell layout"
+    pc.close()
+    del cells, gc
     from paper_1211_5595_amd import autotune
     for (tw, th), waves in autotune.launch_candidates(skip_empty=False):
         if ((tw, th), waves) == ((4, 16), 12):
             continue
         other = [rt.Job(gv, brain["gtf"], c, 512, 512, 0.5, 0.99) for c in cams]
-        p2 = rt.BatchPlan(len(cams), rt.U12, tile=(tw, th), waves_per_block=waves)
+        p2 = rt.BatchPlan(len(cams), rt.U12, layout=Q, tile=(tw, th), waves_per_block=waves)
         p2.launch(other)
         torch.cuda.synchronize()
         for a, b in zip(timed, other):
             assert torch.equal(a.out, b.out), ((tw, th), waves)
         p2.close()
+
 
 @pytest.mark.parametrize("seed", range(6))
 def test_u12_random_small_cases(rt, torch_mod, orc, seed):
