@@ -566,6 +566,44 @@ def bench_batch(args):
     print(json.dumps(line), flush=True)
 
 
+def serve_breakdown(recs):
+    """Where the latency of served requests goes.  recs: one dict per request
+    with its arrival `target`, the server's stamps t_submit, t_launch (batch
+    launched), t_done (completion seen by the server thread), the size of its
+    batch and its image side, all on one monotonic clock.  Returns
+    percentiles of the submit delay, queue wait and batch service time, those
+    of the slowest 1 % beside those of all requests, the batch sizes, and the
+    server's occupancy: batches already in flight when each batch launched
+    and requests waiting when each request arrived."""
+    import numpy as np
+    if not recs:
+        return None
+    g = lambda k: np.array([r[k] for r in recs], dtype=np.float64)
+    target, ts, tl, td = g("target"), g("t_submit"), g("t_launch"), g("t_done")
+    bsz, side = g("batch"), g("side")
+    lat, sub, que, svc = td - target, ts - target, tl - ts, td - tl
+    ms = lambda a, q: round(float(np.percentile(a, q)) * 1e3, 4) if a.size else None
+    tail = lat >= np.percentile(lat, 99)
+    part = lambda m: {"n": int(m.sum()), "latency_ms": ms(lat[m], 50), "submit_ms": ms(sub[m], 50),
+                      "queue_ms": ms(que[m], 50), "service_ms": ms(svc[m], 50),
+                      "batch_size": round(float(bsz[m].mean()), 2), "image_side": round(float(side[m].mean()), 1)}
+    # one interval per batch (its requests share launch and completion stamps)
+    batches = sorted({(a, b) for a, b in zip(tl, td)})
+    starts = np.array([b[0] for b in batches])
+    ends = np.array([b[1] for b in batches])
+    in_flight = np.array([int(((starts < s0) & (ends > s0)).sum()) for s0 in starts])
+    waiting = np.array([int(((ts <= t) & (tl > t)).sum()) - 1 for t in ts])
+    hist = lambda a: {str(int(k)): int(v) for k, v in zip(*np.unique(a, return_counts=True))}
+    return {"p50": {"submit_ms": ms(sub, 50), "queue_ms": ms(que, 50), "service_ms": ms(svc, 50)},
+            "p99": {"submit_ms": ms(sub, 99), "queue_ms": ms(que, 99), "service_ms": ms(svc, 99)},
+            "all_median": part(np.ones_like(tail)), "slowest_1pct_median": part(tail),
+            "batches": len(batches), "batch_size_hist": hist(bsz[np.unique(tl, return_index=True)[1]]),
+            "batches_in_flight_at_launch_hist": hist(in_flight),
+            "requests_waiting_at_arrival_p50": float(np.percentile(waiting, 50)),
+            "requests_waiting_at_arrival_p99": float(np.percentile(waiting, 99)),
+            "requests_waiting_at_arrival_max": int(waiting.max())}
+
+
 def bench_serve(args):
     """Poisson stream (200 req/s, seed 300) over 16 resident u16 volumes (4 of
     each batch size, seeds 200+i); each request has its own camera, square
@@ -584,7 +622,7 @@ def bench_serve(args):
     sp = (0.9, 0.9, 1.2)
     dims = [d for d in W.BATCH_SIZES for _ in range(4)]
     ex = GpuExecutor(n_streams=3, max_batch=64, storage=_storage(rt, args),  # exact empty-space skipping on
-                     tile_order=args.tile_order or 2)
+                     tile_order=args.tile_order or 2, layout=_layout(rt, args), batch_form=args.batch_form)
     for i, d in enumerate(dims):
         ex.add_volume(i, W.phantom_brain(200 + i, dims=d, spacing=sp), sp)
         print(f"volume {i} {d} resident", file=sys.stderr, flush=True)
@@ -635,13 +673,15 @@ def bench_serve(args):
         the request loop.  Latency = completion time stamped by the server
         thread (CLOCK_MONOTONIC, the clock of perf_counter) - arrival time."""
         n = n or n_req
+        counter = torch.zeros(1, dtype=torch.int64, device="cuda")
         srv = NativeServer(pool_bytes, n_streams=3, max_batch=64, storage=_storage(rt, args),
-                           tile_order=args.tile_order or 2)
+                           tile_order=args.tile_order or 2, layout=_layout(rt, args), batch_form=args.batch_form,
+                           sample_counter=counter)
         srv.volumes = ex.volumes                  # the same resident volumes
         import queue as _q
         import threading as _th
         w = warm if speed == 1.0 else 0
-        lat, done, samples, failed = [], [], [0.0], []
+        lat, done, failed, recs = [], [], [], []
         tickets = _q.Queue()
 
         def consume():  # the client side: take each image as it completes and give its memory back
@@ -650,7 +690,7 @@ def bench_serve(args):
                 item = tickets.get()
                 if item is None:
                     return
-                target, t = item
+                target, t, side = item
                 info = srv.wait(t)
                 if info.state != rt.REQ_DONE:
                     failed.append((i, info.status))
@@ -658,7 +698,8 @@ def bench_serve(args):
                 if i >= w:
                     lat.append(info.t_done - target)
                     done.append(info.t_done)
-                    samples[0] += info.batch_samples / max(info.batch_size, 1)
+                    recs.append({"target": target, "t_submit": info.t_submit, "t_launch": info.t_launch,
+                                 "t_done": info.t_done, "batch": info.batch_size, "side": side})
                 i += 1
 
         th = _th.Thread(target=consume, daemon=True)
@@ -668,19 +709,22 @@ def bench_serve(args):
         for k in range(n):
             target = t0 + trace[k]["t"] / speed
             wait_until(target)
-            tickets.put((target, srv.submit(reqs[k])))
+            tickets.put((target, srv.submit(reqs[k]), reqs[k].width))
             if k == w:
                 first = target
         tickets.put(None)
         th.join()
         if failed:
             raise RuntimeError(f"requests failed: {failed[:5]}")
-        samples = samples[0]
         st = srv.stats()
         srv.close()
+        torch.cuda.synchronize()
+        # the device counter covers every request, warm-up included: scale to the measured ones
+        samples = int(counter.item()) * (n - w) / n
         out = summarize(lat, int(samples), first, max(done), n - w)
         out.update({"pool_bytes": int(st.pool_bytes), "pool_peak_bytes": int(st.pool_peak),
-                    "batches": int(st.batches), "mean_batch": round(n / max(int(st.batches), 1), 2)})
+                    "batches": int(st.batches), "mean_batch": round(n / max(int(st.batches), 1), 2),
+                    "breakdown": serve_breakdown(recs)})
         return out
 
     def serial(speed=1.0, n=None):
@@ -720,8 +764,9 @@ def bench_serve(args):
     line = _contract("p50/p99 render latency (ms), Poisson 200 req/s over 16 resident u16 volumes, continuous "
                      "batching (native server; value = p99)", nat_loose["p99_ms"], "ms", args, nat_loose["mean_ms"],
                      "f32",
-                     {"workload": "serve-poisson200-16vol-u16", "volumes": len(dims), "sizes": W.BATCH_SIZES,
-                      "storage": args.storage, "tile_order": args.tile_order or 2,
+                     {"workload": f"serve-poisson200-16vol-{args.storage}-{args.layout}", "volumes": len(dims),
+                      "sizes": W.BATCH_SIZES, "storage": args.storage, "layout": args.layout,
+                      "batch_form": args.batch_form, "tile_order": args.tile_order or 2,
                       "requests": n_req, "warmup_requests": warm, "image_sides": [256, 1024], "streams": 3,
                       "max_batch": 64, "step_vox": 0.5, "alpha_cutoff": 0.99, "tf_entries": 4096,
                       "skip_empty": True},
@@ -767,6 +812,9 @@ def main():
                          "volumes x 4 views in one launch vs 128 launches; serve: Poisson request stream; "
                          "projection: the orbit under every ray function (projections, thresholding, "
                          "iso-surface)")
+    ap.add_argument("--batch-form", type=int, choices=[0, 1, 2], default=0,
+                    help="serve: the servers' batch plans take the latency form by batch size (0), never (1) or "
+                         "always (2)")
     ap.add_argument("--tile-order", type=int, choices=[0, 1, 2], default=0,
                     help="serve: tile order of the executor's plans (0 = its default, spread; 1 compact; 2 spread)")
     ap.add_argument("--layout", choices=["cells", "poly", "linear", "quads"], default=None,

@@ -176,6 +176,13 @@ typedef struct {
                                          * table is staged (compositing and thresholding; the
                                          * paper's compositing, Section 4.2, uses the table opacity
                                          * per sample, which is the default 0) */
+    int batch_form;                     /* batch plans: 0 = by size: a batch of at most
+                                         * rt_batch_latency_pixels() pixels takes the latency form
+                                         * (one workgroup per block of tiles, workgroups sized to the
+                                         * batch as rt_render sizes them to a view, the single-view
+                                         * kernel's occupancy), a larger one the persistent form;
+                                         * 1 = always persistent; 2 = always the latency form.
+                                         * Images are identical in either form. */
 } rt_render_opts;
 
 /* Empty-space skipping (compositing only).  Each volume keeps, per skip brick
@@ -236,11 +243,14 @@ rt_status rt_tf_bytes(int K, size_t* bytes);
  * buffer owned by the handle and uploaded to dev_buf (>= rt_tf_bytes(K),
  * 16-byte aligned) on `stream`; the call does not wait for the upload, and
  * the caller's table may be reused as soon as it returns.  An update keeps
- * dev_buf and K (pass dev_buf NULL or the same buffer); it waits only for
- * this handle's previous upload, and renders that read the table must be
- * ordered after it (same stream, or an event).
+ * dev_buf (pass NULL or the same buffer) and may change K while
+ * rt_tf_bytes(K) still fits dev_buf and the handle's pinned buffer (sized by
+ * the K it was created with), so a handle created with 4096 entries takes any
+ * table without allocating; it waits only for this handle's previous upload,
+ * and renders that read the table must be ordered after it (same stream, or
+ * an event).
  * Errors: RT_ERR_INVALID_ARG (NULL, K outside [2,4096], vmax <= vmin,
- * non-finite or out-of-range entries, changed buffer or K),
+ * non-finite or out-of-range entries, changed buffer),
  * RT_ERR_OUT_OF_MEMORY (buffer too small), RT_ERR_DEVICE. */
 rt_status rt_set_transfer_function(rt_tf** tf, const float* rgba, int K, double vmin, double vmax, void* dev_buf,
                                    size_t dev_buf_bytes, void* stream);
@@ -299,13 +309,18 @@ rt_status rt_render_batch(const rt_render_job* jobs, int n, void* workspace, siz
  * fixed workspace, replayed for every batch of up to max_jobs views of one
  * storage type and layout.  rt_batch_plan_launch copies the job table into the
  * workspace (plain stream copy, outside the graph) and launches the graph on
- * `stream`.  The plan keeps a pinned host staging buffer and waits for the
+ * `stream` -- or, for a batch small enough for the latency form
+ * (opts->batch_form), launches that form's kernel directly, its grid the
+ * batch's block count.  The plan keeps a pinned host staging buffer and waits for the
  * previous launch's copy before reusing it.  Calls on one plan must not run
  * concurrently.  A plan created with opts->skip_empty set skips empty space
  * for the jobs whose skip_empty is set; a plan created without it never skips
  * (the images are the same either way). */
 rt_status rt_batch_plan_create(int max_jobs, int storage, int layout, void* workspace, size_t ws_bytes,
                                const rt_render_opts* opts, rt_batch_plan** out);
+/* Pixels (summed over a batch's views) up to which a plan with batch_form 0
+ * takes the latency form on the current device. */
+long long rt_batch_latency_pixels(void);
 rt_status rt_batch_plan_launch(rt_batch_plan* plan, const rt_render_job* jobs, int n,
                                unsigned long long* sample_counter, void* stream);
 rt_status rt_batch_plan_destroy(rt_batch_plan* plan);

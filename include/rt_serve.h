@@ -8,7 +8,11 @@
  * queue waits for memory rather than being overtaken) goes into one launch of
  * that stream's captured batch plan, so requests that arrive while others
  * render are started as soon as a stream and memory free up and their work
- * overlaps on the device.  A server thread inside the library uploads the
+ * overlaps on the device.  A batch also closes before its images would
+ * exceed 16 x rt_batch_latency_pixels() pixels in all (one request at least),
+ * so a burst of arrivals is split over the streams rather than finishing as
+ * one long launch; batches up to rt_batch_latency_pixels() take the plans'
+ * latency form.  A server thread inside the library uploads the
  * requests' transfer functions, launches, and retires finished batches;
  * callers only submit, wait and release.  Every image is bitwise the image
  * rt_render gives for the same request alone (the batched launch renders each
@@ -19,14 +23,17 @@
  * the same ray caster.
  *
  * Memory: the caller allocates one device arena (rt_server_arena_bytes) that
- * holds, per stream, the batch workspace, a sample counter and max_batch
- * transfer-function slots of 4096 entries, followed by the image pool.  The
+ * holds, per stream, the batch workspace and max_batch transfer-function
+ * slots of 4096 entries, followed by the image pool.  The
  * image pool is the admission budget: a request holds W*H*16 bytes of it
  * (rounded up to 256) from admission until the caller releases it.  Host
  * memory: small pinned staging buffers per stream and per table slot.
  *
  * Threads: every entry point may be called from any thread.  Volumes must stay
- * alive until the requests that use them are released.
+ * alive until the requests that use them are released.  A request submitted
+ * to an empty queue while a stream is free is launched by rt_server_submit in
+ * the caller's thread (saving the server thread's wake-up); every other
+ * request is launched by the server thread.
  */
 #pragma once
 
@@ -68,9 +75,9 @@ typedef struct {
     int state;                          /* RT_REQ_* */
     rt_status status;                   /* RT_OK, or the failure of the request's batch */
     float* image_dev;                   /* DONE: H x W x 4 float32 in the image pool, else NULL */
-    double t_submit, t_launch, t_done;  /* CLOCK_MONOTONIC seconds; 0 until reached */
+    double t_submit, t_launch, t_done;  /* CLOCK_MONOTONIC seconds, 0 until reached: queued, taken from
+                                         * the queue into a batch (in queue order), seen complete */
     int batch_size;                     /* requests in the launch that rendered it */
-    unsigned long long batch_samples;   /* samples composited by that launch */
 } rt_request_info;
 
 typedef struct {
@@ -84,9 +91,12 @@ typedef struct {
 rt_status rt_server_arena_bytes(int n_streams, int max_batch, size_t image_pool_bytes, size_t* bytes);
 
 /* Create a server for volumes of one storage type and layout on the current
- * device.  opts selects the launch shape, tile order and empty-space skipping
- * of the batch plans (its counters, pixel counts and ray-function fields are
- * not used; each request carries its own ray function).  arena_dev is
+ * device.  opts selects the launch shape, tile order, batch form and
+ * empty-space skipping of the batch plans; opts->sample_counter, when not
+ * NULL, is a device counter every batch atomically adds its composited samples
+ * to (no copy back: read it on the device or after the server is idle); the
+ * pixel-count and ray-function fields are not used (each request carries its
+ * own ray function).  arena_dev is
  * 256-byte aligned device memory of at least rt_server_arena_bytes(...) bytes,
  * owned by the caller and kept until rt_server_destroy returns.  Starts the
  * server thread.  Errors: RT_ERR_INVALID_ARG (sizes, storage/layout, opts,

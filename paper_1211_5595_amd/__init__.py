@@ -24,6 +24,7 @@ __all__ = [
     "lib", "rt_volume_bytes", "rt_create_volume", "rt_destroy_volume", "rt_tf_bytes",
     "rt_set_transfer_function", "rt_destroy_tf", "rt_render", "rt_batch_workspace_bytes",
     "rt_render_batch", "rt_render_batch_noalloc", "rt_batch_plan_create", "rt_batch_plan_launch", "rt_batch_plan_destroy",
+    "rt_batch_latency_pixels",
     "rt_server_arena_bytes", "rt_server_create", "rt_server_submit", "rt_server_wait", "rt_server_release",
     "rt_server_get_stats", "rt_server_destroy", "REQ_QUEUED", "REQ_RUNNING", "REQ_DONE", "REQ_FAILED",
     "Volume", "TransferFunction", "BatchPlan", "render", "render_batch", "Job",
@@ -71,7 +72,7 @@ class rt_render_opts(C.Structure):
     _fields_ = [("sample_counter", C.c_void_p), ("pixel_counts", C.c_void_p), ("ray_function", C.c_int),
                 ("iso_value", C.c_float), ("iso_high", C.c_float), ("tile_w", C.c_int), ("tile_h", C.c_int),
                 ("waves_per_block", C.c_int), ("skip_empty", C.c_int), ("tile_order", C.c_int),
-                ("opacity_unit_distance", C.c_double)]
+                ("opacity_unit_distance", C.c_double), ("batch_form", C.c_int)]
 
 
 class rt_render_job(C.Structure):
@@ -92,8 +93,7 @@ class rt_request(C.Structure):
 
 class rt_request_info(C.Structure):
     _fields_ = [("state", C.c_int), ("status", C.c_int), ("image_dev", C.c_void_p), ("t_submit", C.c_double),
-                ("t_launch", C.c_double), ("t_done", C.c_double), ("batch_size", C.c_int),
-                ("batch_samples", C.c_ulonglong)]
+                ("t_launch", C.c_double), ("t_done", C.c_double), ("batch_size", C.c_int)]
 
 
 class rt_server_stats(C.Structure):
@@ -156,6 +156,8 @@ def lib():
         L.rt_last_error.restype = C.c_char_p
         L.rt_last_error.argtypes = []
         L.rt_version.restype = C.c_char_p
+        L.rt_batch_latency_pixels.restype = C.c_longlong
+        L.rt_batch_latency_pixels.argtypes = []
         _lib = L
     return _lib
 
@@ -198,8 +200,9 @@ def make_camera(cam) -> rt_camera:
 
 def make_opts(sample_counter=None, pixel_counts=None, ray_function=COMPOSITE, iso_value=0.0, iso_high=0.0,
               tile=(0, 0), waves_per_block=0, skip_empty=False, tile_order=0,
-              opacity_unit_distance=0.0) -> rt_render_opts:
+              opacity_unit_distance=0.0, batch_form=0) -> rt_render_opts:
     o = rt_render_opts()
+    o.batch_form = int(batch_form)
     o.tile_order = int(tile_order)
     o.opacity_unit_distance = float(opacity_unit_distance)
     o.skip_empty = 1 if skip_empty else 0
@@ -299,6 +302,11 @@ def rt_batch_plan_launch(plan_h: int, jobs, counter_ptr: Optional[int] = None, s
     arr = (rt_render_job * len(jobs))(*jobs)
     _check(lib().rt_batch_plan_launch(C.c_void_p(plan_h), arr, len(jobs), C.c_void_p(counter_ptr),
                                       _stream_ptr(stream)), "rt_batch_plan_launch")
+
+
+def rt_batch_latency_pixels() -> int:
+    """Pixels up to which a plan (batch_form 0) takes the latency form."""
+    return int(lib().rt_batch_latency_pixels())
 
 
 def rt_batch_plan_destroy(plan_h: int):
@@ -431,6 +439,7 @@ class TransferFunction:
         self.vmax = self.vmax if vmax is None else float(vmax)
         self.handle = rt_set_transfer_function(self.handle, t, self.vmin, self.vmax, 0, 0, stream)
         self.table = t
+        self.K = int(t.shape[0])
 
     def close(self):
         if getattr(self, "handle", None):
@@ -525,14 +534,17 @@ def render_batch(jobs: Sequence[Job], sample_counter=None, workspace=None, tile=
 
 
 class BatchPlan:
-    """The persistent batched launch captured once in a HIP graph."""
+    """The persistent batched launch captured once in a HIP graph, and its
+    latency form for small batches (batch_form: 0 by size, 1 persistent
+    always, 2 latency form always)."""
 
     def __init__(self, max_jobs: int, storage: int, tile=(0, 0), waves_per_block=0, device="cuda",
-                 layout: int = LAYOUT_CELLS, skip_empty: bool = False, tile_order: int = 0):
+                 layout: int = LAYOUT_CELLS, skip_empty: bool = False, tile_order: int = 0, batch_form: int = 0):
         self.ws = _Workspace(max_jobs, device)
         self.handle = rt_batch_plan_create(max_jobs, storage, layout, self.ws.buf.data_ptr(), self.ws.nbytes,
                                            make_opts(tile=tile, waves_per_block=waves_per_block,
-                                                     skip_empty=skip_empty, tile_order=tile_order))
+                                                     skip_empty=skip_empty, tile_order=tile_order,
+                                                     batch_form=batch_form))
 
     def launch(self, jobs: Sequence[Job], sample_counter=None, stream=None):
         rt_batch_plan_launch(self.handle, [j.struct() for j in jobs],

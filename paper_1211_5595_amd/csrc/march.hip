@@ -202,11 +202,6 @@ __device__ __forceinline__ uint32_t mad24_s(uint32_t a, uint32_t b, uint32_t c) 
     asm("v_mad_u32_u24 %0, %1, %2, %3" : "=v"(d) : "v"(a), "s"(b), "v"(c));
     return d;
 }
-__device__ __forceinline__ uint32_t mul24_s(uint32_t a, uint32_t b) {
-    uint32_t d;
-    asm("v_mul_u32_u24 %0, %1, %2" : "=v"(d) : "v"(a), "s"(b));
-    return d;
-}
 __device__ __forceinline__ uint32_t mad24_imm6(uint32_t a, uint32_t c) {
     uint32_t d;
     asm("v_mad_u32_u24 %0, %1, 6, %2" : "=v"(d) : "v"(a), "v"(c));
@@ -339,7 +334,6 @@ template <int KIND>
 struct CellBits;
 template <>
 struct CellBits<ST_U8> {
-    static constexpr int shift = 3;
     using Raw = u32x2;
     static __device__ __forceinline__ Raw load(__amdgpu_buffer_rsrc_t r, uint32_t cell) {
         return struct_load_b64(r, cell, 0, 0, 0);
@@ -351,7 +345,6 @@ struct CellBits<ST_U8> {
 };
 template <>
 struct CellBits<ST_U16> {
-    static constexpr int shift = 4;
     using Raw = u32x4;
     static __device__ __forceinline__ Raw load(__amdgpu_buffer_rsrc_t r, uint32_t cell) {
         return struct_load_b128(r, cell, 0, 0, 0);
@@ -366,7 +359,6 @@ struct CellBits<ST_U16> {
 };
 template <>
 struct CellBits<ST_F16> {
-    static constexpr int shift = 4;
     using Raw = u32x4;
     static __device__ __forceinline__ Raw load(__amdgpu_buffer_rsrc_t r, uint32_t cell) {
         return struct_load_b128(r, cell, 0, 0, 0);
@@ -381,7 +373,6 @@ struct CellBits<ST_F16> {
 };
 template <>
 struct CellBits<ST_F32> {
-    static constexpr int shift = 5;
     struct Raw {
         u32x4 a;
         u32x4 b;
@@ -1405,6 +1396,58 @@ __global__ void RT_BATCH_SKIP_ATTRS march_batch_skip_kernel(char* __restrict__ w
     batch_body<KIND, LAYOUT, true>(ws, ls, tw_shift, tf_entries);
 }
 
+// Latency form of the batched launch: one workgroup per block of tiles, no
+// queue, with the single-view kernel's occupancy and cell ring.  A batch
+// smaller than the GPU then spreads over every compute unit in workgroups
+// sized to it, as a lone view does, instead of filling a few 16-wavefront
+// workgroups of the persistent kernel.  Each workgroup stages its own view's
+// table (and skip mask) and renders one block.
+template <int KIND, int LAYOUT, bool SKIP>
+__global__ void RT_PLAIN_ATTRS march_views_kernel(char* __restrict__ ws, const LaunchShape ls, int tw_shift) {
+    extern __shared__ float4 s_tf[];
+    const CBatchHeader* hdr = (const CBatchHeader*)(ws);
+    const CInt* prefix = (const CInt*)(ws + kBatchHeaderBytes);
+    const CViewDesc* jobs = (const CViewDesc*)(ws + kBatchHeaderBytes + kBatchPrefixBytes);
+    const int n_jobs = (int)hdr->n_jobs;
+    const int g = xcd_remap(blockIdx.x, gridDim.x);
+    int lo = 0, hi = n_jobs;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (prefix[mid] <= g) lo = mid;
+        else hi = mid;
+    }
+    const CViewDesc& V = jobs[lo];
+    uint32_t* s_mask = reinterpret_cast<uint32_t*>(s_tf + hdr->tf_lds_entries);
+    load_tf(s_tf, V.tf, V.K, V.alpha_exp);
+    if (SKIP && V.skip_empty) build_skip_mask(s_mask, V);
+    __syncthreads();
+    render_block<KIND, LAYOUT, SKIP, true, CViewDesc>(V, s_tf, s_mask, g - prefix[lo], ls, tw_shift, hdr->counter);
+}
+
+// The same for a batch carried in the kernel arguments.  The batch is the
+// first argument, at offset 0 of the kernel-argument segment, and is read
+// through that segment's constant address: scalar loads of the view at its
+// index, as from the workspace (indexing the by-value argument itself would
+// copy it to private memory).
+typedef __attribute__((address_space(4))) const SmallBatch CSmallBatch;
+template <int KIND, int LAYOUT, bool SKIP>
+__global__ void RT_PLAIN_ATTRS march_views_args_kernel(const SmallBatch B, const LaunchShape ls, int tw_shift) {
+    extern __shared__ float4 s_tf[];
+    (void)B;
+    const CSmallBatch* b = (const CSmallBatch*)__builtin_amdgcn_kernarg_segment_ptr();
+    const int g = xcd_remap(blockIdx.x, gridDim.x);
+    const int n = b->n;
+    int lo = 0;
+#pragma unroll
+    for (int i = 1; i < kSmallBatchJobs; ++i) lo += (i < n && b->prefix[i] <= g) ? 1 : 0;
+    const CViewDesc& V = b->v[lo];
+    uint32_t* s_mask = reinterpret_cast<uint32_t*>(s_tf + b->tf_lds_entries);
+    load_tf(s_tf, V.tf, V.K, V.alpha_exp);
+    if (SKIP && V.skip_empty) build_skip_mask(s_mask, V);
+    __syncthreads();
+    render_block<KIND, LAYOUT, SKIP, true, CViewDesc>(V, s_tf, s_mask, g - b->prefix[lo], ls, tw_shift, b->counter);
+}
+
 // Value range of every skip brick, one workgroup per brick: each of its
 // padded cells is sampled by the marcher's own sampler at the cell's 8
 // corners, so the range bounds what a sample in the brick can read (up to
@@ -1534,6 +1577,46 @@ hipError_t batch_launch(void* ws, int grid, const LaunchShape& ls, int max_k, bo
                 : batch_launch_k<KIND, LAYOUT, false>(ws, grid, ls, max_k, s);
 }
 
+template <int KIND, int LAYOUT, bool SKIP>
+hipError_t views_launch_k(void* ws, int blocks, const LaunchShape& ls, int max_k, hipStream_t s) {
+    const size_t lds = (size_t)(max_k + 1) * sizeof(float4) + (SKIP ? (size_t)kSkipMaskBytes : 0);
+    static const hipError_t attr =
+        hipFuncSetAttribute((const void*)march_views_kernel<KIND, LAYOUT, SKIP>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)((kMaxK + 1) * sizeof(float4) + kSkipMaskBytes));
+    (void)attr;
+    if (blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL((march_views_kernel<KIND, LAYOUT, SKIP>), dim3(blocks), dim3(64 * ls.waves), lds, s,
+                       static_cast<char*>(ws), ls, log2i(ls.tile_w));
+    return hipGetLastError();
+}
+
+template <int KIND, int LAYOUT>
+hipError_t views_launch(void* ws, int blocks, const LaunchShape& ls, int max_k, bool skip, hipStream_t s) {
+    return skip ? views_launch_k<KIND, LAYOUT, true>(ws, blocks, ls, max_k, s)
+                : views_launch_k<KIND, LAYOUT, false>(ws, blocks, ls, max_k, s);
+}
+
+template <int KIND, int LAYOUT, bool SKIP>
+hipError_t views_args_launch_k(const SmallBatch& b, const LaunchShape& ls, hipStream_t s) {
+    const size_t lds = (size_t)b.tf_lds_entries * sizeof(float4) + (SKIP ? (size_t)kSkipMaskBytes : 0);
+    static const hipError_t attr =
+        hipFuncSetAttribute((const void*)march_views_args_kernel<KIND, LAYOUT, SKIP>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)((kMaxK + 1) * sizeof(float4) + kSkipMaskBytes));
+    (void)attr;
+    const int blocks = b.prefix[b.n];
+    if (blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL((march_views_args_kernel<KIND, LAYOUT, SKIP>), dim3(blocks), dim3(64 * ls.waves), lds, s, b,
+                       ls, log2i(ls.tile_w));
+    return hipGetLastError();
+}
+
+template <int KIND, int LAYOUT>
+hipError_t views_args_launch(const SmallBatch& b, const LaunchShape& ls, bool skip, hipStream_t s) {
+    return skip ? views_args_launch_k<KIND, LAYOUT, true>(b, ls, s) : views_args_launch_k<KIND, LAYOUT, false>(b, ls, s);
+}
+
 }  // namespace
 
 hipError_t launch_march_plain(const ViewDesc& v, const LaunchShape& ls, unsigned long long* counter,
@@ -1626,6 +1709,70 @@ hipError_t launch_march_batch(int kind, int layout, void* workspace, int grid, c
         case ST_U12:
             return C   ? batch_launch<ST_U12, LAYOUT_CELLS>(workspace, grid, ls, max_k, skip, s)
                    : X ? batch_launch<ST_U12, LAYOUT_QUADS>(workspace, grid, ls, max_k, skip, s)
+                       : hipErrorInvalidValue;
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_march_views(int kind, int layout, void* workspace, int blocks, const LaunchShape& ls, int max_k,
+                              bool skip, hipStream_t s) {
+    const bool C = layout == LAYOUT_CELLS, P = layout == LAYOUT_POLY, X = layout == LAYOUT_QUADS;
+    switch (kind) {
+        case ST_U8:
+            return C   ? views_launch<ST_U8, LAYOUT_CELLS>(workspace, blocks, ls, max_k, skip, s)
+                   : P ? views_launch<ST_U8, LAYOUT_POLY>(workspace, blocks, ls, max_k, skip, s)
+                       : views_launch<ST_U8, LAYOUT_LINEAR>(workspace, blocks, ls, max_k, skip, s);
+        case ST_U16:
+            return C   ? views_launch<ST_U16, LAYOUT_CELLS>(workspace, blocks, ls, max_k, skip, s)
+                   : P ? views_launch<ST_U16, LAYOUT_POLY>(workspace, blocks, ls, max_k, skip, s)
+                   : X ? views_launch<ST_U16, LAYOUT_QUADS>(workspace, blocks, ls, max_k, skip, s)
+                       : views_launch<ST_U16, LAYOUT_LINEAR>(workspace, blocks, ls, max_k, skip, s);
+        case ST_F16:
+            return C ? views_launch<ST_F16, LAYOUT_CELLS>(workspace, blocks, ls, max_k, skip, s)
+                     : views_launch<ST_F16, LAYOUT_LINEAR>(workspace, blocks, ls, max_k, skip, s);
+        case ST_F32:
+            return C ? views_launch<ST_F32, LAYOUT_CELLS>(workspace, blocks, ls, max_k, skip, s)
+                     : views_launch<ST_F32, LAYOUT_LINEAR>(workspace, blocks, ls, max_k, skip, s);
+        case ST_U8B:
+            return C ? views_launch<ST_U8B, LAYOUT_CELLS>(workspace, blocks, ls, max_k, skip, s)
+                     : views_launch<ST_U8B, LAYOUT_BRICKS>(workspace, blocks, ls, max_k, skip, s);
+        case ST_U15:
+            return C ? views_launch<ST_U15, LAYOUT_CELLS>(workspace, blocks, ls, max_k, skip, s) : hipErrorInvalidValue;
+        case ST_U12:
+            return C   ? views_launch<ST_U12, LAYOUT_CELLS>(workspace, blocks, ls, max_k, skip, s)
+                   : X ? views_launch<ST_U12, LAYOUT_QUADS>(workspace, blocks, ls, max_k, skip, s)
+                       : hipErrorInvalidValue;
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_march_views_args(int kind, int layout, const SmallBatch& b, const LaunchShape& ls, bool skip,
+                                   hipStream_t s) {
+    const bool C = layout == LAYOUT_CELLS, P = layout == LAYOUT_POLY, X = layout == LAYOUT_QUADS;
+    switch (kind) {
+        case ST_U8:
+            return C   ? views_args_launch<ST_U8, LAYOUT_CELLS>(b, ls, skip, s)
+                   : P ? views_args_launch<ST_U8, LAYOUT_POLY>(b, ls, skip, s)
+                       : views_args_launch<ST_U8, LAYOUT_LINEAR>(b, ls, skip, s);
+        case ST_U16:
+            return C   ? views_args_launch<ST_U16, LAYOUT_CELLS>(b, ls, skip, s)
+                   : P ? views_args_launch<ST_U16, LAYOUT_POLY>(b, ls, skip, s)
+                   : X ? views_args_launch<ST_U16, LAYOUT_QUADS>(b, ls, skip, s)
+                       : views_args_launch<ST_U16, LAYOUT_LINEAR>(b, ls, skip, s);
+        case ST_F16:
+            return C ? views_args_launch<ST_F16, LAYOUT_CELLS>(b, ls, skip, s)
+                     : views_args_launch<ST_F16, LAYOUT_LINEAR>(b, ls, skip, s);
+        case ST_F32:
+            return C ? views_args_launch<ST_F32, LAYOUT_CELLS>(b, ls, skip, s)
+                     : views_args_launch<ST_F32, LAYOUT_LINEAR>(b, ls, skip, s);
+        case ST_U8B:
+            return C ? views_args_launch<ST_U8B, LAYOUT_CELLS>(b, ls, skip, s)
+                     : views_args_launch<ST_U8B, LAYOUT_BRICKS>(b, ls, skip, s);
+        case ST_U15:
+            return C ? views_args_launch<ST_U15, LAYOUT_CELLS>(b, ls, skip, s) : hipErrorInvalidValue;
+        case ST_U12:
+            return C   ? views_args_launch<ST_U12, LAYOUT_CELLS>(b, ls, skip, s)
+                   : X ? views_args_launch<ST_U12, LAYOUT_QUADS>(b, ls, skip, s)
                        : hipErrorInvalidValue;
         default: return hipErrorInvalidValue;
     }

@@ -33,6 +33,7 @@ struct rt_tf {
     double vmin, vmax;
     size_t bytes;
     void* staging;      // pinned host copy of the table for the asynchronous upload
+    size_t staging_bytes;
     hipEvent_t copied;  // recorded after the upload on the caller's stream
     bool pending;
 };
@@ -40,7 +41,10 @@ struct rt_tf {
 struct rt_batch_plan {
     int max_jobs;
     int kind;
+    int form;       // rt_render_opts.batch_form
+    bool skip;      // opts->skip_empty at creation
     LaunchShape ls;
+    LaunchShape ls_lat;  // the latency form's tile and order (waves set per batch)
     int grid;
     void* ws;
     size_t ws_bytes;
@@ -315,13 +319,27 @@ int cu_count() {
 // Default wavefronts per workgroup of a single view: as many as keep every
 // compute unit busy -- a 16-wavefront workgroup fills a CU's four SIMDs, so a
 // view of fewer tiles than 16 per CU would leave CUs idle.
-int default_waves(int W, int H, const LaunchShape& ls) {
-    const long long tiles = (long long)((W + ls.tile_w - 1) / ls.tile_w) * ((H + ls.tile_h - 1) / ls.tile_h);
+int default_waves_for_tiles(long long tiles) {
     const long long per_cu = tiles / std::max(cu_count(), 1);
     int waves = 1;
     while (waves < 16 && 2LL * waves <= per_cu) waves *= 2;
     return waves;
 }
+int default_waves(int W, int H, const LaunchShape& ls) {
+    return default_waves_for_tiles((long long)((W + ls.tile_w - 1) / ls.tile_w) * ((H + ls.tile_h - 1) / ls.tile_h));
+}
+// Ray tiles of a batch's views (sizes not yet checked: non-positive counts 0).
+long long batch_tiles(const rt_render_job* jobs, int n, const LaunchShape& ls) {
+    long long t = 0;
+    for (int i = 0; i < n; ++i)
+        if (jobs[i].width > 0 && jobs[i].height > 0)
+            t += (long long)((jobs[i].width + ls.tile_w - 1) / ls.tile_w) * ((jobs[i].height + ls.tile_h - 1) / ls.tile_h);
+    return t;
+}
+// Batches up to this many pixels take a plan's latency form by default: the
+// rays the single-view kernel's occupancy (4 wavefronts per SIMD) holds at
+// once on every compute unit.
+long long latency_pixels() { return (long long)cu_count() * 4 * 4 * 64; }
 
 rt_status make_view(const rt_volume* vol, const int64_t dims[3], const double spacing[3], const rt_tf* tf,
                     const rt_camera* cam, int W, int H, double step_vox, double cutoff, const float* bg,
@@ -530,6 +548,15 @@ int layout_code(int layout) {
 
 namespace rtv {
 
+// Every value in [0, 1] (NaN fails): a branch-free pass the compiler
+// vectorizes, as tables of 16384 values are checked on every request.
+bool unit_range(const float* v, size_t n) {
+    int bad = 0;
+    for (size_t i = 0; i < n; ++i) bad |= !(v[i] >= 0.0f) | !(v[i] <= 1.0f);
+    return bad == 0;
+}
+
+
 int storage_layout_kind(int storage, int layout) {
     if (storage < RT_U8 || storage > RT_U12 || !layout_allowed(storage, layout)) return -1;
     return (storage == RT_U8_BRICKSCALED ? ST_U8B : storage) * 8 + layout_code(layout);
@@ -686,13 +713,13 @@ rt_status rt_set_transfer_function(rt_tf** tf, const float* rgba, int K, double 
     if (!tf || !rgba) return fail(RT_ERR_INVALID_ARG, "NULL handle pointer or table");
     if (K < 2 || K > kMaxK) return fail(RT_ERR_INVALID_ARG, "K must be in [2, 4096]");
     if (!std::isfinite(vmin) || !std::isfinite(vmax) || !(vmax > vmin)) return fail(RT_ERR_INVALID_ARG, "need vmin < vmax");
-    for (int i = 0; i < 4 * K; ++i)
-        if (!(rgba[i] >= 0.0f && rgba[i] <= 1.0f)) return fail(RT_ERR_INVALID_ARG, "table entries must be in [0, 1]");
+    if (!unit_range(rgba, 4 * (size_t)K)) return fail(RT_ERR_INVALID_ARG, "table entries must be in [0, 1]");
     const size_t need = tf_layout_bytes(K);
     rt_tf* t = *tf;
     if (t) {
-        if (t->K != K || (dev_buf && dev_buf != (const void*)t->dev))
-            return fail(RT_ERR_INVALID_ARG, "an update must keep the buffer and K");
+        if (dev_buf && dev_buf != (const void*)t->dev) return fail(RT_ERR_INVALID_ARG, "an update must keep the buffer");
+        if (need > t->bytes || need > t->staging_bytes)
+            return fail(RT_ERR_OUT_OF_MEMORY, "table larger than the handle's device or staging buffer");
     } else {
         if (!dev_buf) return fail(RT_ERR_INVALID_ARG, "NULL device buffer");
         if (dev_buf_bytes < need) return fail(RT_ERR_OUT_OF_MEMORY, "transfer-function buffer smaller than rt_tf_bytes");
@@ -703,6 +730,7 @@ rt_status rt_set_transfer_function(rt_tf** tf, const float* rgba, int K, double 
         t->dev = static_cast<const float4*>(dev_buf);
         t->K = K;
         t->bytes = dev_buf_bytes;
+        t->staging_bytes = need;
         hipError_t e = hipHostMalloc(&t->staging, need, hipHostMallocDefault);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&t->copied, hipEventDisableTiming);
         if (e != hipSuccess) {
@@ -732,6 +760,7 @@ rt_status rt_set_transfer_function(rt_tf** tf, const float* rgba, int K, double 
         return hip_fail(e, "transfer-function copy");
     }
     t->pending = true;
+    t->K = K;
     t->vmin = vmin;
     t->vmax = vmax;
     *tf = t;
@@ -817,6 +846,8 @@ rt_status rt_batch_plan_create(int max_jobs, int storage, int layout, void* work
     if (ws_bytes < batch_ws_bytes(max_jobs)) return fail(RT_ERR_OUT_OF_MEMORY, "workspace smaller than rt_batch_workspace_bytes");
     if (storage < RT_U8 || storage > RT_U12) return fail(RT_ERR_INVALID_ARG, "unknown storage type");
     if (!layout_allowed(storage, layout)) return fail(RT_ERR_INVALID_ARG, "layout not available for this storage type");
+    if (opts && (opts->batch_form < 0 || opts->batch_form > 2))
+        return fail(RT_ERR_INVALID_ARG, "batch_form must be 0, 1 or 2");
     LaunchShape ls;
     rt_status st = make_shape(opts, opts && opts->skip_empty ? LAUNCH_BATCH_SKIP : LAUNCH_BATCH, ls);
     if (st != RT_OK) return st;
@@ -825,7 +856,16 @@ rt_status rt_batch_plan_create(int max_jobs, int storage, int layout, void* work
     std::memset(p, 0, sizeof(*p));
     p->max_jobs = max_jobs;
     p->kind = storage_layout_kind(storage, layout);
+    p->form = opts ? opts->batch_form : 0;
+    p->skip = opts && opts->skip_empty;
     p->ls = ls;
+    // the latency form: rt_render's tile (8x8 unless given) in spread order
+    st = make_shape(opts, LAUNCH_SINGLE, p->ls_lat);
+    if (st != RT_OK) {
+        delete p;
+        return st;
+    }
+    p->ls_lat.order = 1;
     p->grid = batch_persistent_grid(ls, kMaxK, opts && opts->skip_empty);
     p->ws = workspace;
     p->ws_bytes = ws_bytes;
@@ -864,16 +904,45 @@ rt_status rt_batch_plan_create(int max_jobs, int storage, int layout, void* work
     return RT_OK;
 }
 
+long long rt_batch_latency_pixels(void) { return latency_pixels(); }
+
 rt_status rt_batch_plan_launch(rt_batch_plan* p, const rt_render_job* jobs, int n, unsigned long long* sample_counter,
                                void* stream) {
     if (!p) return fail(RT_ERR_INVALID_ARG, "plan is NULL");
     if (n > p->max_jobs) return fail(RT_ERR_INVALID_ARG, "more jobs than the plan holds");
+    if (!jobs || n < 1) return fail(RT_ERR_INVALID_ARG, "empty batch");
+    long long pixels = 0;
+    for (int i = 0; i < n; ++i) pixels += (long long)std::max(jobs[i].width, 0) * std::max(jobs[i].height, 0);
+    const bool lat = p->form == 2 || (p->form == 0 && pixels <= latency_pixels());
+    LaunchShape ls = p->ls;
+    if (lat) {  // workgroups sized to the batch, as rt_render sizes them to a view
+        ls = p->ls_lat;
+        set_waves(ls, default_waves_for_tiles(batch_tiles(jobs, n, ls)));
+    }
     std::vector<ViewDesc> descs;
     std::vector<int> prefix;
     int kind, max_k;
-    rt_status st = build_batch(jobs, n, p->ls, &kind, &max_k, descs, prefix);
+    rt_status st = build_batch(jobs, n, ls, &kind, &max_k, descs, prefix);
     if (st != RT_OK) return st;
     if (kind != p->kind) return fail(RT_ERR_INVALID_ARG, "jobs' storage type or layout differs from the plan's");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (lat && n == 1) {  // one view: the single-view kernel, as rt_render launches it
+        hipError_t e = launch_march_plain(descs[0], ls, sample_counter, s);
+        if (e != hipSuccess) return hip_fail(e, "latency-form launch");
+        return RT_OK;
+    }
+    if (lat && n <= kSmallBatchJobs) {  // the job table travels in the kernel arguments
+        SmallBatch b;
+        std::memset(&b, 0, sizeof(b));
+        for (int i = 0; i < n; ++i) b.v[i] = descs[i];
+        for (int i = 0; i <= n; ++i) b.prefix[i] = prefix[i];
+        b.n = n;
+        b.tf_lds_entries = max_k + 1;
+        b.counter = sample_counter;
+        hipError_t e = launch_march_views_args(p->kind / 8, p->kind % 8, b, ls, p->skip, s);
+        if (e != hipSuccess) return hip_fail(e, "latency-form launch");
+        return RT_OK;
+    }
     if (p->copy_pending) {
         hipError_t e = hipEventSynchronize(p->copy_done);
         if (e != hipSuccess) return hip_fail(e, "waiting for the previous job-table copy");
@@ -881,12 +950,16 @@ rt_status rt_batch_plan_launch(rt_batch_plan* p, const rt_render_job* jobs, int 
     }
     const size_t bytes = batch_copy_bytes(n);
     write_batch_host(p->staging, descs, prefix, max_k, sample_counter);
-    hipStream_t s = static_cast<hipStream_t>(stream);
     hipError_t e = hipMemcpyAsync(p->ws, p->staging, bytes, hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return hip_fail(e, "job-table copy");
     e = hipEventRecord(p->copy_done, s);
     if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
     p->copy_pending = true;
+    if (lat) {
+        e = launch_march_views(p->kind / 8, p->kind % 8, p->ws, prefix.back(), ls, max_k, p->skip, s);
+        if (e != hipSuccess) return hip_fail(e, "latency-form launch");
+        return RT_OK;
+    }
     e = hipGraphLaunch(p->exec, s);
     if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
     return RT_OK;

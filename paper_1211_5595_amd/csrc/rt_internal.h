@@ -162,6 +162,22 @@ hipError_t launch_march_plain(const ViewDesc& v, const LaunchShape& ls, unsigned
 hipError_t launch_march_batch(int kind, int layout, void* workspace, int grid, const LaunchShape& ls, int max_k,
                               bool skip, hipStream_t s);
 int batch_persistent_grid(const LaunchShape& ls, int max_k, bool skip);
+// The latency form of a batch: one workgroup per block (blocks = the
+// prefix's total), the job table read from the workspace as above.
+hipError_t launch_march_views(int kind, int layout, void* workspace, int blocks, const LaunchShape& ls, int max_k,
+                              bool skip, hipStream_t s);
+// A latency-form batch of at most kSmallBatchJobs views carried whole in the
+// kernel arguments (under 4 KiB): no job-table copy precedes the launch.
+static constexpr int kSmallBatchJobs = 6;
+struct SmallBatch {
+    ViewDesc v[kSmallBatchJobs];
+    int32_t prefix[kSmallBatchJobs + 1];  // prefix[i] = first block of view i, prefix[n] = blocks
+    int32_t n;
+    int32_t tf_lds_entries;               // max K over the views, +1
+    unsigned long long* counter;          // nullable sample counter
+};
+hipError_t launch_march_views_args(int kind, int layout, const SmallBatch& b, const LaunchShape& ls, bool skip,
+                                   hipStream_t s);
 
 // Per skip brick value range of a volume in its storage layout (march.hip).
 hipError_t launch_skip_ranges(const VolDev& vol, hipStream_t s);
@@ -188,6 +204,7 @@ hipError_t launch_relayout_u8b_cells(const void* src, int src_kind, const int32_
 // the batch calls apply to one view, run without any device work (the table is
 // given by its size and value window only); *kind receives the volume's code.
 int storage_layout_kind(int storage, int layout);
+bool unit_range(const float* v, size_t n);
 int volume_kind(const rt_volume* vol);
 // Record msg as the calling thread's rt_last_error(); returns status.
 int set_last_error(int status, const char* msg);

@@ -49,8 +49,8 @@ size_t workspace_bytes(int max_batch) {
     rt_batch_workspace_bytes(max_batch, &b);
     return r256(b);
 }
-// Per stream: workspace, 256 B for the sample counter, max_batch table slots.
-size_t lane_bytes(int max_batch) { return workspace_bytes(max_batch) + 256 + (size_t)max_batch * slot_bytes(); }
+// Per stream: workspace, max_batch table slots.
+size_t lane_bytes(int max_batch) { return workspace_bytes(max_batch) + (size_t)max_batch * slot_bytes(); }
 
 // First-fit allocator over [0, size) with coalescing; offsets 256-aligned.
 struct Pool {
@@ -95,6 +95,7 @@ struct Pool {
 struct Req {
     rt_request r;
     std::vector<float> table;
+    const float* ext_table = nullptr;  // the caller's table, while rt_server_submit launches the request itself
     rt_request_info info;
     size_t img_off = 0, img_bytes = 0;
     bool has_img = false;
@@ -103,7 +104,6 @@ struct Req {
 struct Slot {
     void* dev = nullptr;
     rt_tf* tf = nullptr;
-    int K = 0;
 };
 
 struct Lane {
@@ -112,11 +112,10 @@ struct Lane {
     rt_batch_plan* plan = nullptr;
     void* ws = nullptr;
     size_t ws_bytes = 0;
-    unsigned long long* counter = nullptr;  // device, cumulative
-    unsigned long long last = 0;            // counter value at the previous retirement
     std::vector<Slot> slots;
     std::vector<uint64_t> tickets;
     bool busy = false;
+    bool launching = false;  // busy, and its launch still being enqueued (the event is not yet this batch's)
 };
 
 }  // namespace
@@ -124,12 +123,13 @@ struct Lane {
 struct rt_server {
     int device = 0;
     int max_batch = 0;
+    long long batch_pixels = 0;  // a batch closes before it would exceed this many pixels
     int kind = -1;
     int skip = 0;
+    unsigned long long* counter = nullptr;  // caller's device sample counter, nullable
     char* pool_base = nullptr;
     Pool pool;
     std::vector<Lane> lanes;
-    unsigned long long* host_counts = nullptr;  // pinned, one per lane
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
     std::deque<uint64_t> queue;
@@ -149,18 +149,14 @@ bool rt_server::retire_locked() {
     bool any = false;
     for (size_t k = 0; k < lanes.size(); ++k) {
         Lane& L = lanes[k];
-        if (!L.busy) continue;
+        if (!L.busy || L.launching) continue;
         const hipError_t e = hipEventQuery(L.done);
         if (e == hipErrorNotReady) continue;
         const double t = now_s();
-        const unsigned long long total = host_counts[k];
-        const unsigned long long n = total - L.last;
-        L.last = total;
         for (uint64_t id : L.tickets) {
             Req& q = reqs.at(id);
             q.info.t_done = t;
             q.info.batch_size = (int)L.tickets.size();
-            q.info.batch_samples = n;
             if (e == hipSuccess) {
                 q.info.state = RT_REQ_DONE;
                 q.info.image_dev = reinterpret_cast<float*>(pool_base + q.img_off);
@@ -195,8 +191,11 @@ bool rt_server::launch(std::unique_lock<std::mutex>& lk) {
     if (k < 0) return false;
     Lane& L = lanes[k];
     std::vector<uint64_t> batch;
+    long long pixels = 0;
     while (!queue.empty() && (int)batch.size() < max_batch) {
         Req& q = reqs.at(queue.front());
+        const long long px = (long long)q.r.width * q.r.height;
+        if (!batch.empty() && pixels + px > batch_pixels) break;  // the rest goes to the next free stream
         size_t off;
         if (!pool.alloc(q.img_bytes, &off)) break;  // the head waits for memory
         q.img_off = off;
@@ -204,29 +203,32 @@ bool rt_server::launch(std::unique_lock<std::mutex>& lk) {
         q.info.state = RT_REQ_RUNNING;
         batch.push_back(queue.front());
         queue.pop_front();
+        pixels += px;
     }
     if (batch.empty()) return false;
     L.busy = true;  // reserved while unlocked
+    L.launching = true;
     L.tickets = batch;
     stats.queued -= (int)batch.size();
     stats.running += (int)batch.size();
+    // stamped as the batch leaves the queue (under the lock, so in queue order
+    // whichever thread launches it)
+    const double t_launch = now_s();
     std::vector<Req*> rq;
-    for (uint64_t id : batch) rq.push_back(&reqs.at(id));  // stable: queued/running requests are never erased
+    for (uint64_t id : batch) {
+        rq.push_back(&reqs.at(id));  // stable: queued/running requests are never erased
+        rq.back()->info.t_launch = t_launch;
+    }
     lk.unlock();
 
     rt_status st = RT_OK;
     std::vector<rt_render_job> jobs(batch.size());
     for (size_t j = 0; j < batch.size() && st == RT_OK; ++j) {
         Req& q = *rq[j];
-        Slot& sl = L.slots[j];
-        if (sl.tf && sl.K != q.r.tf_entries) {
-            rt_destroy_tf(sl.tf);
-            sl.tf = nullptr;
-        }
-        st = rt_set_transfer_function(&sl.tf, q.table.data(), q.r.tf_entries, q.r.tf_vmin, q.r.tf_vmax, sl.dev,
-                                      slot_bytes(), L.stream);
+        Slot& sl = L.slots[j];  // created with 4096 entries: any table fits, nothing is allocated here
+        st = rt_set_transfer_function(&sl.tf, q.ext_table ? q.ext_table : q.table.data(), q.r.tf_entries,
+                                      q.r.tf_vmin, q.r.tf_vmax, sl.dev, slot_bytes(), L.stream);
         if (st != RT_OK) break;
-        sl.K = q.r.tf_entries;
         rt_render_job& J = jobs[j];
         std::memset(&J, 0, sizeof(J));
         J.volume = q.r.volume;
@@ -245,18 +247,12 @@ bool rt_server::launch(std::unique_lock<std::mutex>& lk) {
         J.opacity_unit_distance = q.r.opacity_unit_distance;
         J.skip_empty = skip;
     }
-    const double t_launch = now_s();
-    if (st == RT_OK) st = rt_batch_plan_launch(L.plan, jobs.data(), (int)jobs.size(), L.counter, L.stream);
-    if (st == RT_OK) {
-        hipError_t e = hipMemcpyAsync(host_counts + k, L.counter, sizeof(unsigned long long), hipMemcpyDeviceToHost,
-                                      L.stream);
-        if (e == hipSuccess) e = hipEventRecord(L.done, L.stream);
-        if (e != hipSuccess) st = RT_ERR_DEVICE;
-    }
+    if (st == RT_OK) st = rt_batch_plan_launch(L.plan, jobs.data(), (int)jobs.size(), counter, L.stream);
+    if (st == RT_OK && hipEventRecord(L.done, L.stream) != hipSuccess) st = RT_ERR_DEVICE;
 
     lk.lock();
+    L.launching = false;
     ++stats.batches;
-    for (Req* q : rq) q->info.t_launch = t_launch;
     if (st != RT_OK) {  // the batch never reached the device: fail its requests
         for (Req* q : rq) {
             q->info.state = RT_REQ_FAILED;
@@ -320,7 +316,6 @@ void destroy_resources(rt_server* s) {
         if (L.done) (void)hipEventDestroy(L.done);
         if (L.stream) (void)hipStreamDestroy(L.stream);
     }
-    if (s->host_counts) (void)hipHostFree(s->host_counts);
     delete s;
 }
 
@@ -355,8 +350,13 @@ rt_status rt_server_create(int n_streams, int max_batch, int storage, int layout
     if (!s) return err(RT_ERR_OUT_OF_MEMORY, "host allocation failed");
     (void)hipGetDevice(&s->device);
     s->max_batch = max_batch;
+    // about 16 views' worth of the rays the GPU holds at once: near the
+    // persistent launch's full throughput, and ~1 ms of work, so a burst is
+    // split over the streams instead of completing as one long batch
+    s->batch_pixels = 16 * rt_batch_latency_pixels();
     s->kind = kind;
     s->skip = opts && opts->skip_empty ? 1 : 0;
+    s->counter = opts ? opts->sample_counter : nullptr;
     rt_render_opts po;
     std::memset(&po, 0, sizeof(po));
     if (opts) {
@@ -365,13 +365,9 @@ rt_status rt_server_create(int n_streams, int max_batch, int storage, int layout
         po.waves_per_block = opts->waves_per_block;
         po.skip_empty = opts->skip_empty;
         po.tile_order = opts->tile_order;
+        po.batch_form = opts->batch_form;
     }
-    hipError_t e = hipHostMalloc((void**)&s->host_counts, kMaxStreams * sizeof(unsigned long long), hipHostMallocDefault);
-    if (e != hipSuccess) {
-        delete s;
-        return err(RT_ERR_DEVICE, std::string("hipHostMalloc: ") + hipGetErrorString(e));
-    }
-    std::memset(s->host_counts, 0, kMaxStreams * sizeof(unsigned long long));
+    hipError_t e = hipSuccess;
     char* base = static_cast<char*>(arena_dev);
     s->lanes.resize(n_streams);
     for (int k = 0; k < n_streams; ++k) {
@@ -379,12 +375,10 @@ rt_status rt_server_create(int n_streams, int max_batch, int storage, int layout
         char* lb = base + (size_t)k * lane_bytes(max_batch);
         L.ws = lb;
         L.ws_bytes = workspace_bytes(max_batch);
-        L.counter = reinterpret_cast<unsigned long long*>(lb + L.ws_bytes);
         L.slots.resize(max_batch);
-        for (int j = 0; j < max_batch; ++j) L.slots[j].dev = lb + L.ws_bytes + 256 + (size_t)j * slot_bytes();
+        for (int j = 0; j < max_batch; ++j) L.slots[j].dev = lb + L.ws_bytes + (size_t)j * slot_bytes();
         e = hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&L.done, hipEventDisableTiming);
-        if (e == hipSuccess) e = hipMemsetAsync(L.counter, 0, sizeof(unsigned long long), L.stream);
         if (e != hipSuccess) {
             destroy_resources(s);
             return err(RT_ERR_DEVICE, std::string("stream set-up: ") + hipGetErrorString(e));
@@ -394,6 +388,18 @@ rt_status rt_server_create(int n_streams, int max_batch, int storage, int layout
             const std::string m = rt_last_error();
             destroy_resources(s);
             return err(st, "batch plan: " + m);
+        }
+        // every table slot's handle (and its pinned staging buffer) made now,
+        // at the largest size, so the request path never allocates or frees
+        // pinned memory (calls that can wait for the whole device)
+        const std::vector<float> blank(4 * (size_t)kMaxK, 0.0f);
+        for (int j = 0; j < max_batch && st == RT_OK; ++j)
+            st = rt_set_transfer_function(&L.slots[j].tf, blank.data(), kMaxK, 0.0, 1.0, L.slots[j].dev, slot_bytes(),
+                                          L.stream);
+        if (st != RT_OK) {
+            const std::string m = rt_last_error();
+            destroy_resources(s);
+            return err(st, "table slots: " + m);
         }
         e = hipStreamSynchronize(L.stream);
         if (e != hipSuccess) {
@@ -426,17 +432,14 @@ rt_status rt_server_submit(rt_server* s, const rt_request* req, uint64_t* ticket
                                                         req->opacity_unit_distance, &kind));
     if (st != RT_OK) return st;
     if (kind != s->kind) return err(RT_ERR_INVALID_ARG, "volume of another storage type or layout than the server's");
-    for (int i = 0; i < 4 * K; ++i)
-        if (!(req->tf_rgba[i] >= 0.0f && req->tf_rgba[i] <= 1.0f))
-            return err(RT_ERR_INVALID_ARG, "table entries must be in [0, 1]");
+    if (!unit_range(req->tf_rgba, 4 * (size_t)K)) return err(RT_ERR_INVALID_ARG, "table entries must be in [0, 1]");
     const size_t img = r256((size_t)req->width * (size_t)req->height * 16);
     if (img > s->pool.size) return err(RT_ERR_OUT_OF_MEMORY, "image larger than the server's image pool");
-    std::lock_guard<std::mutex> g(s->mu);
+    std::unique_lock<std::mutex> lk(s->mu);
     if (s->stop) return err(RT_ERR_INVALID_ARG, "server is shutting down");
     const uint64_t id = ++s->next_ticket;
     Req& q = s->reqs[id];
     q.r = *req;
-    q.table.assign(req->tf_rgba, req->tf_rgba + 4 * (size_t)K);
     q.r.tf_rgba = nullptr;
     std::memset(&q.info, 0, sizeof(q.info));
     q.info.state = RT_REQ_QUEUED;
@@ -446,8 +449,26 @@ rt_status rt_server_submit(rt_server* s, const rt_request* req, uint64_t* ticket
     s->queue.push_back(id);
     ++s->stats.submitted;
     ++s->stats.queued;
-    s->cv_work.notify_one();
     *ticket = id;
+    // A request that finds the queue otherwise empty and a stream free is
+    // launched from the caller's thread: the server thread would first have
+    // to wake up.  Its table is uploaded from the caller's memory (the lock is
+    // held from the push until launch() takes the queue's head, so no other
+    // thread can take it).  The server thread retires it as any other batch.
+    bool free_lane = false;
+    if (s->queue.size() == 1)
+        for (const Lane& L : s->lanes) free_lane = free_lane || !L.busy;
+    if (free_lane) {
+        q.ext_table = req->tf_rgba;
+        int prev = -1;
+        const bool other = hipGetDevice(&prev) == hipSuccess && prev != s->device;
+        if (other) (void)hipSetDevice(s->device);
+        s->launch(lk);
+        if (other) (void)hipSetDevice(prev);
+        q.ext_table = nullptr;  // uploaded, or still queued (then it gets its own copy below)
+    }
+    if (q.info.state == RT_REQ_QUEUED) q.table.assign(req->tf_rgba, req->tf_rgba + 4 * (size_t)K);
+    s->cv_work.notify_one();
     return RT_OK;
 }
 

@@ -219,9 +219,9 @@ def test_server_arena_and_argument_checks(rt):
     """The serving runtime's sizes, and its argument checks, which run before
     any device work."""
     r = lambda x: (x + 255) // 256 * 256
-    lane = r(rt.rt_batch_workspace_bytes(64)) + 256 + 64 * r(rt.rt_tf_bytes(4096))
+    lane = r(rt.rt_batch_workspace_bytes(64)) + 64 * r(rt.rt_tf_bytes(4096))
     assert rt.rt_server_arena_bytes(3, 64, 1 << 20) == 3 * lane + (1 << 20)
-    assert rt.rt_server_arena_bytes(1, 1, 1000) == r(rt.rt_batch_workspace_bytes(1)) + 256 + r(rt.rt_tf_bytes(4096)) \
+    assert rt.rt_server_arena_bytes(1, 1, 1000) == r(rt.rt_batch_workspace_bytes(1)) + r(rt.rt_tf_bytes(4096)) \
         + 1024
     for args in ((0, 4, 4096), (9, 4, 4096), (1, 0, 4096), (1, 257, 4096), (1, 4, 255)):
         with pytest.raises(rt.InvalidArgument):

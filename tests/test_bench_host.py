@@ -142,3 +142,22 @@ def test_isa_loop_counts_from_the_built_library():
         assert 30.0 <= lp["valu_per_sample"] <= 90.0
     assert isa.loop_profile(rt.LIB_PATH, rt.U12, rt.LAYOUT_CELLS)["valu_per_sample"] < \
         isa.loop_profile(rt.LIB_PATH, rt.U16, rt.LAYOUT_CELLS)["valu_per_sample"]
+
+
+def test_serve_breakdown_splits_latency():
+    """Per-request stamps -> submit, queue and service parts; batches in flight
+    at each launch and requests waiting at each arrival."""
+    recs = []
+    # three batches: A (2 requests) 0..1 ms, B (1) 0.5..2 ms overlapping A, C (1) 5..6 ms
+    for k, (tgt, ts, tl, td, b) in enumerate([(0.0, 0.0, 0.0001, 0.001, 2), (0.0, 0.00005, 0.0001, 0.001, 2),
+                                             (0.0002, 0.0002, 0.0005, 0.002, 1), (0.005, 0.005, 0.005, 0.006, 1)]):
+        recs.append({"target": tgt, "t_submit": ts, "t_launch": tl, "t_done": td, "batch": b, "side": 256 + 64 * k})
+    bd = bench.serve_breakdown(recs)
+    assert bd["batches"] == 3
+    assert bd["batch_size_hist"] == {"1": 2, "2": 1}
+    assert bd["batches_in_flight_at_launch_hist"] == {"0": 2, "1": 1}
+    assert bd["requests_waiting_at_arrival_max"] == 1
+    # the slowest request (1.8 ms, arrived at 0.2 ms) waited 0.3 ms and rendered 1.5 ms
+    s = bd["slowest_1pct_median"]
+    assert s["n"] == 1 and abs(s["queue_ms"] - 0.3) < 1e-9 and abs(s["service_ms"] - 1.5) < 1e-9
+    assert bench.serve_breakdown([]) is None

@@ -140,7 +140,8 @@ def test_small_pool_first_come_first_served(rt, torch_mod, vols):
 
 def test_rejections_and_ticket_rules(rt, torch_mod, vols):
     from paper_1211_5595_amd.serve import NativeServer, RenderRequest
-    srv = NativeServer(1 << 20, n_streams=1, max_batch=4, storage=rt.U12)
+    counter = torch_mod.zeros(1, dtype=torch_mod.int64, device="cuda")
+    srv = NativeServer(1 << 20, n_streams=1, max_batch=4, storage=rt.U12, sample_counter=counter)
     srv.add_volume(0, *vols[0])
     cam = W.orbit_cameras(vols[0][0].shape[::-1], vols[0][1], 4)[1]
     tf = W.random_tf(128, 3)
@@ -158,7 +159,13 @@ def test_rejections_and_ticket_rules(rt, torch_mod, vols):
         srv.submit(RenderRequest("u16", cam, 32, 32, tf))
     t = srv.submit(RenderRequest(0, cam, 32, 32, tf))
     info = srv.wait(t)
-    assert info.state == rt.REQ_DONE and info.batch_size == 1 and info.batch_samples > 0
+    assert info.state == rt.REQ_DONE and info.batch_size == 1
+    # the server's batches counted into the caller's device counter: as rt_render counts the same view
+    torch_mod.cuda.synchronize()
+    ref = torch_mod.zeros(1, dtype=torch_mod.int64, device="cuda")
+    rt.render(srv.volumes[0], rt.TransferFunction(tf, 0.0, 4095.0), cam, 32, 32, sample_counter=ref, skip_empty=True)
+    torch_mod.cuda.synchronize()
+    assert int(counter.item()) == int(ref.item()) > 0
     srv.release(t)
     with pytest.raises(rt.InvalidArgument):      # released: unknown
         srv.release(t)
