@@ -314,15 +314,18 @@ def _timed(fn, steps, warmup):
 
 def _limiter(form, storage, layout="quads"):
     """What bounds the timed kernel, with the profile summary that shows it."""
-    if form in ("batch", "graph", "skip"):
-        # the caches serve two thirds of the logical gathers, so the fraction
-        # can exceed 1; what binds is vector-instruction issue
+    if form in ("batch", "graph"):
+        # the caches serve three quarters of the logical gathers, so their rate
+        # can exceed the HBM peak; what binds is vector-instruction issue
         text, prof = "VALU instruction issue (raw SQ_INSTS_VALU over busy cycles", \
             f"profiles/march_batch_{storage}_{layout}_brain_orbit.md"
+    elif form == "skip":
+        text, prof = "VALU instruction issue of the samples taken (skipped ones cost a leap per brick", \
+            "profiles/march_batch_other_forms_brain_orbit.md"
     else:
         # one launch per view: the longest ray's own instruction stream
         text, prof = "the longest ray of each lone view (one launch per view", \
-            f"profiles/march_plain_{storage}_{layout}_brain_orbit_views.md"
+            "profiles/march_batch_other_forms_brain_orbit.md"
     here = os.path.dirname(os.path.abspath(__file__))
     return text + (f", see {prof})" if os.path.exists(os.path.join(here, prof)) else ")")
 

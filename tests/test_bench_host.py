@@ -80,6 +80,7 @@ def test_percentile_interpolates():
 
 def test_limiter_names_the_timed_kernel():
     assert bench._limiter("graph", "u12").startswith("VALU instruction issue")
+    assert "see profiles/march_batch_u12_quads_brain_orbit.md" in bench._limiter("graph", "u12", "quads")
     assert bench._limiter("plain", "u12").startswith("the longest ray")
     for form, st, lay in (("graph", "u12", "quads"), ("plain", "u16", "quads"), ("skip", "u15", "cells"),
                           ("graph", "u12", "cells")):
