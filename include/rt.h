@@ -332,7 +332,7 @@ rt_status rt_batch_plan_destroy(rt_batch_plan* plan);
  * before any device work); otherwise arguments, errors and results are those
  * of rt_render_batch, images bitwise identical.  The header, block prefix and
  * job table are delivered to the array by small kernels whose arguments carry
- * them (about 43 KB of device memory per GPU, held until the process ends),
+ * them (about 52 KB of device memory per GPU, held until the process ends),
  * so the call makes no device or pinned-host allocation and no copy from
  * pageable memory.  The array of the current device is used; `stream` must
  * belong to it.  Every call on one GPU shares that array: calls that may
