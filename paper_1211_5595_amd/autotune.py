@@ -2,11 +2,11 @@
 
 Tunables: the ray tile of one wavefront (8x8, 16x4, 4x16, 32x2 pixels), the
 wavefronts per workgroup (4, 8, 12 for fixed steps; 4, 8, 16 with skipping) and, per volume at creation, the storage
-layout (cell-packed, polynomial cells for integer data, x-pairs for 16- and 12-bit data, or linear; for 8-bit
+layout (cell-packed, quad bricks for 16- and 12-bit data, polynomial cells for integer data, or linear; for 8-bit
 brick storage the brick edge 8, 16 or 32) or, for integer data, the storage
 type among the encodings that hold the grid exactly (tune_storage).  Tile shape and wavefronts never
-change a pixel; the cell-packed and linear layouts render the same image bit
-for bit, and the polynomial layout evaluates the same interpolant in another
+change a pixel; the cell-packed, quad-brick and linear layouts render the same
+image bit for bit, and the polynomial layout evaluates the same interpolant in another
 rounding order (within the same tolerance of the exact result), so the choice
 is speed.  Each candidate is timed on
 representative views with device events; results are cached in a JSON file
@@ -150,8 +150,8 @@ def tune_launch(volume, tf, cameras, width: int, height: int, step_vox: float = 
 def exact_storages(values) -> List[Tuple[int, int]]:
     """(storage, layout) pairs that hold an integer grid without loss: 8-bit
     data as u8 (any integer layout) or u16; 16-bit data as u16, and also as
-    15-bit difference cells when its maximum is at most 32767 and as 12-bit
-    half cells when it is at most 4096 (both in the cell layout).  Float data
+    15-bit difference cells when its maximum is at most 32767 (cell layout)
+    and as 12-bit halves when it is at most 4096 (cells or quad bricks).  Float data
     has no alternative to its own type here (empty list)."""
     import numpy as np
     from . import LAYOUT_CELLS, LAYOUT_LINEAR, LAYOUT_POLY, LAYOUT_QUADS, U8, U12, U15, U16

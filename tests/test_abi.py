@@ -135,7 +135,7 @@ def test_cell_layout_size_limits(rt):
     ((4, 4, 4), 4, 3, 8, "InvalidArgument"),
     ((4, 4, 4), 5, 1, 0, "InvalidArgument"),    # 15-bit difference cells: cell layout only
     ((4, 4, 4), 5, 3, 0, "InvalidArgument"),
-    ((4, 4, 4), 6, 1, 0, "InvalidArgument"),    # 12-bit half cells: cell layout only
+    ((4, 4, 4), 6, 1, 0, "InvalidArgument"),    # 12-bit halves: cells or quad bricks only
     ((4, 4, 4), 6, 3, 0, "InvalidArgument"),
     ((4, 4, 4), 7, 0, 0, "InvalidArgument"),
     ((4, 4, 4), 0, 4, 0, "InvalidArgument"),    # quads: 16-bit and 12-bit storage only
