@@ -98,6 +98,10 @@ def test_volume_bytes(rt):
     assert vb((512, 512, 256), rt.U12, X) == r256(257 * 257 * 86 * 128)
     assert vb((2, 2, 2), rt.U16, X) == r256(2 * 2 * 1 * 128)
     assert vb((3, 3, 4), rt.U16, X) == r256(2 * 2 * 2 * 128)
+    # the largest quad volume of 1022 x 1022 cross-section: 63 z-bricks, one short of 2^31 bytes
+    assert vb((1022, 1022, 188), rt.U12, X) == 512 * 512 * 63 * 128
+    with pytest.raises(rt.Unsupported):
+        vb((1022, 1022, 189), rt.U12, X)
     # brick-scaled, halo bricks: ceil((n-1)/B) bricks per axis, (B+3)^3 codes and 8 bytes each
     nb = 16 * 16 * 10
     assert vb((256, 256, 160), rt.U8_BRICKSCALED, rt.LAYOUT_BRICKS, 16) == \

@@ -142,3 +142,55 @@ def test_quads_random_grids_large_steps(rt, torch_mod, orc, seed):
         out = rt.render_batch([rt.Job(gv, gtf, cam, Wd, Hd, step, cutoff)])[0]
         torch_mod.cuda.synchronize()
         assert np.array_equal(out.cpu().numpy().astype(np.float64), got)
+
+
+@pytest.fixture(scope="module")
+def largest_quads(rt, orc):
+    """The largest grid of the quad-brick layout in one axis pair: 1022 x 1022
+    x 188 nodes, 512 x 512 x 63 bricks of 128 bytes, one z-brick short of
+    2^31 bytes (byte offsets up to 2^31 - 2^25): a separable smooth field
+    plus separable integer noise on a 12-bit range, and the oracle's view."""
+    dims, sp = (1022, 1022, 188), (1.0, 1.0, 1.0)
+    ax = [np.arange(n, dtype=np.float32) for n in dims]
+    smooth = (np.sin(ax[2] / 13.0 + 0.5)[:, None, None] * np.cos(ax[1] / 41.0)[None, :, None]
+              * (1500.0 * np.sin(ax[0] / 37.0)).astype(np.float32)[None, None, :])
+    hrng = np.random.default_rng(82)
+    hz, hy, hx = (hrng.integers(0, 81, size=n).astype(np.int16) for n in dims[::-1])
+    noise = (hz[:, None, None] + hy[None, :, None]) + hx[None, None, :]
+    v = (np.rint(smooth).astype(np.int16) + (noise % 81 - 40) + 2048).astype(np.uint16)
+    del smooth, noise
+    return dims, sp, v, orc.Volume(v, sp)
+
+
+@pytest.mark.parametrize("storage", ["U12", "U16"])
+def test_quads_largest_volume(rt, torch_mod, orc, largest_quads, storage):
+    """Rays through the far corner of the largest quad-brick grid (where the
+    byte offsets approach 2^31) and through the whole volume, from one launch
+    and from a batch, against the oracle on sampled pixels."""
+    torch = torch_mod
+    dims, sp, v, ov = largest_quads
+    st = getattr(rt, storage)
+    nbytes = rt.rt_volume_bytes(dims, st, rt.LAYOUT_QUADS)
+    assert (1 << 31) - (1 << 26) <= nbytes < (1 << 31)
+    gv = rt.Volume(v, sp, storage=st, layout=rt.LAYOUT_QUADS)
+    t = W.random_tf(4096, 34, alpha_max=0.05)
+    gtf, otf = rt.TransferFunction(t, 0, 4095), orc.TF(t, 0, 4095)
+    hi = np.array([(n - 1) * s for n, s in zip(dims, sp)])
+    corner = W.Camera(tuple(hi + np.array([90.0, 70.0, 40.0])), tuple(hi - np.array([60.0, 60.0, 30.0])), (0, 0, 1),
+                      True, 40.0)
+    # and the whole volume from above (an orbit about z would see this flat box edge-on)
+    c = hi / 2
+    above = W.Camera(tuple(c + np.array([300.0, -400.0, 1200.0])), tuple(c), (0, 1, 0), True, 50.0)
+    cams = [corner, above]
+    rng = np.random.default_rng(83)
+    for ci, cam in enumerate(cams):
+        got, c = gpu_render(rt, torch, gv, gtf, cam, 192, 160, 0.5, 0.99)
+        out = rt.render_batch([rt.Job(gv, gtf, cam, 192, 160, 0.5, 0.99)])[0]
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy().astype(np.float64), got)
+        assert (c > 0).mean() > 0.3
+        px = rng.choice(192 * 160, size=400, replace=False)
+        ref = orc.render(ov, otf, cam, 192, 160, 0.5, 0.99, pixels=px, tie_delta=DELTA, want_band=True)
+        check(got.reshape(-1, 4)[px], ref, c.reshape(-1)[px], f"{storage} largest quad volume, camera {ci}")
+    del gv
+    torch.cuda.empty_cache()
