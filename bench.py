@@ -534,15 +534,23 @@ def bench_batch(args):
         print(f"volume {i} {sp.dims} ready", file=sys.stderr, flush=True)
     gen_s = time.perf_counter() - t0
     jobs = [rt.Job(vols[vi], tfs[vi], cam, side, side, 0.5, 0.99) for vi, cam, side in views]
-    plan = rt.BatchPlan(len(jobs), _storage(rt, args), layout=_layout(rt, args))
+    jobs_s = [rt.Job(vols[vi], tfs[vi], cam, side, side, 0.5, 0.99, skip_empty=True) for vi, cam, side in views]
+    tuned = tuned_s = None
+    shape, shape_s = {}, {}
+    if not args.no_autotune:  # ray-tile shape and workgroup size of each launch form, timed on this batch
+        from paper_1211_5595_amd import autotune
+        tuned = autotune.tune_batch(jobs, _storage(rt, args), _layout(rt, args))
+        tuned_s = autotune.tune_batch(jobs_s, _storage(rt, args), _layout(rt, args), skip_empty=True)
+        shape = dict(tile=tuple(tuned["tile"]), waves_per_block=tuned["waves_per_block"])
+        shape_s = dict(tile=tuple(tuned_s["tile"]), waves_per_block=tuned_s["waves_per_block"])
+    plan = rt.BatchPlan(len(jobs), _storage(rt, args), layout=_layout(rt, args), **shape)
     samples = _count(rt, jobs)
 
     plain = _plain_caller(rt, jobs)
     ms_graph = _timed(lambda: plan.launch(jobs), args.steps, args.warmup)
     ms_plain = _timed(plain, args.steps, args.warmup)
     # the same batch with exact empty-space skipping (same images, fewer samples gathered)
-    plan_s = rt.BatchPlan(len(jobs), _storage(rt, args), layout=_layout(rt, args), skip_empty=True)
-    jobs_s = [rt.Job(vols[vi], tfs[vi], cam, side, side, 0.5, 0.99, skip_empty=True) for vi, cam, side in views]
+    plan_s = rt.BatchPlan(len(jobs), _storage(rt, args), layout=_layout(rt, args), skip_empty=True, **shape_s)
     ms_skip = _timed(lambda: plan_s.launch(jobs_s), args.steps, args.warmup)
     torch.cuda.synchronize()
     same = all(torch.equal(a.out, b.out) for a, b in zip(jobs, jobs_s))
@@ -556,7 +564,9 @@ def bench_batch(args):
                       "layout": args.layout,
                       "sizes": sorted({s.dims for s in specs}), "image_sides": [min(j.width for j in jobs),
                                                                               max(j.width for j in jobs)],
-                      "step_vox": 0.5, "alpha_cutoff": 0.99, "tf_entries": 4096, "launch": "graph"},
+                      "step_vox": 0.5, "alpha_cutoff": 0.99, "tf_entries": 4096, "launch": "graph",
+                      "tile": list(shape.get("tile", (8, 8))), "waves_per_block": shape.get("waves_per_block", 12)},
+                     autotune={"graph": tuned, "graph_skip_empty": tuned_s},
                      samples_per_step=samples, pixels_per_step=pixels,
                      ms_per_step_by_form={"graph": round(ms_graph, 4), "plain_128_launches": round(ms_plain, 4),
                                           "graph_skip_empty": round(ms_skip, 4)},
@@ -788,7 +798,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--probe-copy", action="store_true")
-    ap.add_argument("--no-autotune", action="store_true", help="orbit: keep the default 8x8 tiles, 12 waves")
+    ap.add_argument("--no-autotune", action="store_true", help="orbit and batch: keep the plans' default launch "
+                    "shape (8x8 tiles, 12 waves; 16 with skipping)")
     ap.add_argument("--only", choices=["batch", "plain", "graph", "skip"], default=None,
                     help="time one launch form only (for profiling); skip = the graph form with empty-space "
                          "skipping")

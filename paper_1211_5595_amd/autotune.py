@@ -147,6 +147,40 @@ def tune_launch(volume, tf, cameras, width: int, height: int, step_vox: float = 
     return result
 
 
+def tune_batch(jobs, storage: int, layout: int, reps: int = 2, tiles: Sequence[Tuple[int, int]] = TILES,
+               waves: Optional[Sequence[int]] = None, cache: Optional[Cache] = None, force: bool = False,
+               skip_empty: bool = False) -> dict:
+    """Choose tile shape and wavefronts per workgroup for one batch of jobs
+    (views of several volumes and sizes) as it runs: a persistent batch plan
+    per candidate shape, replayed on the whole batch.  The cache key is the
+    storage type, layout, job count and total pixels (in powers of two)."""
+    from . import BatchPlan
+    import torch
+    pixels = sum(j.width * j.height for j in jobs)
+    key = (f"{_gpu_arch()}|batch|s{storage}|l{layout}|n{size_class(len(jobs))}|p{size_class(pixels)}"
+           + ("|skip" if skip_empty else ""))
+    if cache is not None and not force:
+        hit = cache.get(key)
+        if hit is not None:
+            return hit
+
+    def measure(c):
+        plan = BatchPlan(len(jobs), storage, tile=c[0], waves_per_block=c[1], layout=layout, skip_empty=skip_empty,
+                         batch_form=1)
+        try:
+            return _time_ms(lambda: plan.launch(jobs), reps)
+        finally:
+            torch.cuda.synchronize()
+            plan.close()
+
+    best, table = pick_best(launch_candidates(skip_empty, tiles, waves), measure)
+    result = {"tile": list(best[0]), "waves_per_block": best[1], "ms": table[str(best)], "timings_ms": table,
+              "key": key, "timed": "batch plan (graph replay) of the whole batch"}
+    if cache is not None:
+        cache.put(key, result)
+    return result
+
+
 def exact_storages(values) -> List[Tuple[int, int]]:
     """(storage, layout) pairs that hold an integer grid without loss: 8-bit
     data as u8 (any integer layout) or u16; 16-bit data as u16, and also as

@@ -95,3 +95,35 @@ def test_tuned_storage_renders_the_same_grid(tmp_path, orc):
         assert dist.max() <= 1e-5, (storage, layout, float(dist.max()))
         assert np.abs(got - ref.image)[~((ref.tie & 1) != 0)].max() <= 1e-5, (storage, layout)
         assert (counts.cpu().numpy() == ref.counts)[~ties].all(), (storage, layout)
+
+
+@pytest.mark.gpu
+def test_tune_batch_picks_a_candidate_and_renders_the_same(tmp_path):
+    """The whole-batch tuner times every (tile, waves) candidate on the batch
+    itself and picks the fastest; the tuned plan's images equal the default
+    plan's bit for bit (the shape never changes a pixel)."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1211_5595_amd as rt
+    import workloads as W
+    sp = (0.9, 0.9, 1.2)
+    vols = [rt.Volume(W.phantom_brain(40 + i, dims=d, spacing=sp), sp, storage=rt.U12, layout=rt.LAYOUT_QUADS)
+            for i, d in enumerate([(96, 96, 48), (128, 128, 64)])]
+    tf = rt.TransferFunction(W.random_tf(4096, 41, alpha_max=0.05), 0, 4095)
+    rng = np.random.default_rng(42)
+    views = [(i % 2, W.random_camera(rng, vols[i % 2].dims, sp), 64 * (2 + i % 3)) for i in range(6)]
+    jobs = [rt.Job(vols[v], tf, c, s, s, 0.5, 0.99) for v, c, s in views]
+    cache = at.Cache(str(tmp_path / "b.json"))
+    res = at.tune_batch(jobs, rt.U12, rt.LAYOUT_QUADS, reps=1, cache=cache)
+    assert len(res["timings_ms"]) == len(at.launch_candidates(False))
+    assert res["ms"] == min(res["timings_ms"].values())
+    assert at.tune_batch(jobs, rt.U12, rt.LAYOUT_QUADS, cache=cache) == res      # served from the cache
+    tuned = rt.BatchPlan(6, rt.U12, layout=rt.LAYOUT_QUADS, tile=tuple(res["tile"]),
+                         waves_per_block=res["waves_per_block"], batch_form=1)
+    ref = [rt.Job(vols[v], tf, c, s, s, 0.5, 0.99) for v, c, s in views]
+    tuned.launch(jobs)
+    rt.BatchPlan(6, rt.U12, layout=rt.LAYOUT_QUADS, batch_form=1).launch(ref)
+    torch.cuda.synchronize()
+    for a, b in zip(jobs, ref):
+        assert torch.equal(a.out, b.out)
