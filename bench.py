@@ -160,10 +160,10 @@ def ingest_valu(d, key, samples, cus=256, kernel="march_batch_kernel<6, 4>"):
 
 
 def valu_roofline(samples, ms_per_launch, valu_per_sample, cus):
-    """Vector-ALU roofline of one launch: the VALU lane-operations the
-    composited samples require (samples x VALU instructions per sample of the
-    compositing loop, read from the built code object) per second, against
-    the fp32 vector peak in lane-operations."""
+    """Vector-ALU roofline of one launch: the VALU lane-slots the launch
+    issues (samples x VALU wave instructions per sample x 64 lanes / 64
+    samples per wave, i.e. samples x `valu_per_sample`) per second, against
+    the fp32 vector issue peak in lane-operations."""
     peak = valu_peak_tops(cus)
     achieved = samples * valu_per_sample / (ms_per_launch * 1e-3) / 1e12
     return {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3), "unit": "T VALU lane-ops/s",
@@ -989,12 +989,17 @@ def main():
         lat = single_view_latency(rt.make_opts(), outs)  # rt_render's own default launch shape
 
     # roofline of the dominant kernel.  The binding resource is vector-ALU
-    # instruction issue: the VALU work the composited samples require
-    # (samples x VALU instructions per sample of the compositing loop, counted
-    # in the built code object) per second against the non-packed issue
-    # peak.  Beside it, the logical gather bytes (8 trilinear corners x 2 B
-    # per sample + 16 B per output pixel; the caches serve most of them, so
-    # they are not a ceiling) and the fabric bytes the counters measured.
+    # instruction issue: the VALU lane-slots the launch issues per second
+    # against the non-packed issue peak.  The issued count is SQ_INSTS_VALU x
+    # 64 per launch, counted by rocprofv3 on the same kernel sources (a fixed
+    # property of kernel and workload: the same samples take the same
+    # branches), divided by the composited samples to give the figure per
+    # sample.  Without such counters the compositing loop of the built code
+    # object stands in, every sample taking the colour block (an upper bound
+    # of the loop's part that leaves out per-ray set-up).  Beside it, the
+    # logical gather bytes (8 trilinear corners x 2 B per sample + 16 B per
+    # output pixel; the caches serve most of them, so they are not a
+    # ceiling) and the fabric bytes the counters measured.
     algo_bytes = samples_per_step * 16 + n_views * width * height * 16
     launches_per_step = 1 if best in ("batch", "graph", "skip") else n_views
     bytes_per_launch = algo_bytes / launches_per_step
@@ -1009,17 +1014,30 @@ def main():
         batch_form = best in ("batch", "graph")
         kname = "march_batch_kernel" if batch_form else "march_plain_kernel"
         lp = isa.loop_profile(rt.LIB_PATH, storage, layout, kname)
-        if lp is None:
-            raise SystemExit(f"no compositing loop found for {kname}<{storage}, {layout}> in {rt.LIB_PATH}")
+        cnt = load_valu(key)
+        if cnt is not None:
+            vps = cnt["sq_insts_valu"] * 64.0 / samples_per_launch
+            vps_from = ("VALU lane-slots issued per composited sample: rocprofv3 SQ_INSTS_VALU x 64 per launch "
+                        "(profiles/valu_counters.json, same kernel sources) / samples per launch")
+        elif lp is not None:
+            vps = lp["valu_per_sample"]
+            vps_from = ("VALU instructions per compositing sample of the loop in the built gfx950 code object "
+                        "(paper_1211_5595_amd/isa.py); no counters for these kernel sources")
+        else:
+            raise SystemExit(f"no VALU counters and no compositing loop found for {kname}<{storage}, {layout}>")
         cus = torch.cuda.get_device_properties(0).multi_processor_count
-        roof = valu_roofline(samples_per_launch, ms_per_launch, lp["valu_per_sample"], cus)
+        roof = valu_roofline(samples_per_launch, ms_per_launch, vps, cus)
         gb = lambda b: round(b / (ms_per_launch * 1e-3) / 1e9, 1)
         roof.update({
             "traffic": traffic,
             "kernel": kname + "<" + args.storage + ">",
-            "valu_per_sample": lp["valu_per_sample"],
-            "valu_per_sample_from": "VALU instructions per sample of the compositing loop in the built gfx950 "
-                                    "code object (paper_1211_5595_amd/isa.py)",
+            "valu_per_sample": round(vps, 3),
+            "valu_per_sample_from": vps_from,
+            "loop": None if lp is None else {
+                "valu_per_compositing_sample": lp["valu_per_sample"],
+                "valu_per_transparent_sample": lp["valu_per_transparent_sample"],
+                "note": "the compositing loop of the built code object; a wave whose opacities are all zero "
+                        "skips the colour block"},
             "samples_per_launch": int(samples_per_launch),
             "limiter": _limiter(best, args.storage, args.layout),
             "logical_gather": {"bytes_per_launch": int(bytes_per_launch), "GB_per_s": gb(bytes_per_launch),
@@ -1033,7 +1051,6 @@ def main():
                 "note": "FETCH_SIZE x 2 + WRITE_SIZE x 1 per launch (scales from a plain copy); reads served "
                         "by the Infinity Cache count as fetched"},
         })
-        cnt = load_valu(key)
         if cnt is not None:
             roof["counters"] = {k: cnt.get(k) for k in ("sq_insts_valu", "valu_wave_insts_per_sample",
                                                        "lane_utilisation", "issue_frac_of_busy_cycles",

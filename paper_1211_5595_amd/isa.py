@@ -10,10 +10,18 @@ The code object is taken from the ``.hip_fatbin`` section of ``librtvol.so``
 (offload bundles, one per source file), unbundled for gfx950 and
 disassembled with the ROCm LLVM tools; only the named kernel is
 disassembled.  The loop is found structurally: a backward-branch range with
-no workgroup barrier whose body holds the transfer-function reads (two
-16-byte LDS reads per sample) and, among such loops of the kernel, the one
-with the fewest VALU instructions per sample (the plain compositing loop;
-thresholding adds its window test).
+no workgroup barrier whose body holds, per sample, one volume load and the
+transfer-function reads of one compositing step (the two opacities as one
+paired 4-byte LDS read, the two colours as two 12-byte reads), and, among
+such loops of the kernel, the one with the fewest VALU instructions per
+sample (the plain compositing loop; thresholding adds its window test).
+
+A sample whose interpolated opacity is zero in every lane of the wavefront
+skips its colour block: a branch on the wave's vote.  The instructions such
+branches jump over are counted apart, so the profile gives the cost of a
+sample that composites and of one that the whole wave finds transparent; the
+cost of a launch lies between the two and is measured by the hardware
+counters, not here.
 """
 from __future__ import annotations
 
@@ -104,7 +112,9 @@ def _loops(ins: List[Tuple[int, str, str]]) -> List[Tuple[int, int]]:
 def loop_profile(lib_path: str, kind: int, layout: int, kernel: str = "march_batch_kernel",
                  tail: Optional[str] = None) -> Optional[Dict]:
     """VALU (and other) instructions per sample of the compositing loop of
-    kernel<kind, layout, ...> in the built library, or None when not found.
+    kernel<kind, layout, ...> in the built library, or None when not found:
+    `valu_per_sample` for a sample that composites, and
+    `valu_per_transparent_sample` for one whose wave skips the colour block.
     `tail` is the mangled rest of the template arguments (the batched kernel
     has none; the single-view kernel's fixed-step compositing instantiation,
     <kind, layout, false, true>, is the default for it)."""
@@ -118,17 +128,40 @@ def loop_profile(lib_path: str, kind: int, layout: int, kernel: str = "march_bat
                 continue
             ins = _disassemble(co, syms[0])
             best = None
+            addr_idx = {a: k for k, (a, _, _) in enumerate(ins)}
+            base = ins[0][0] if ins else 0
             for lo, hi in _loops(ins):
                 body = [op for _, op, _ in ins[lo:hi + 1]]
-                lds = sum(op.startswith("ds_read_b128") for op in body)
-                if lds < 2 or lds % 2:
+                samples = body.count("ds_read2_b32")
+                loads = sum(op.startswith(("buffer_load", "global_load")) for op in body)
+                if samples < 1 or loads != samples or body.count("ds_read_b96") != 2 * samples:
                     continue
-                samples = lds // 2
                 valu = sum(op.startswith("v_") for op in body)
+                skipped = set()
+                after_alpha = False   # the wave's vote follows the sample's opacity read
+                for k in range(lo, hi + 1):
+                    a, op, ln = ins[k]
+                    if op == "ds_read2_b32":
+                        after_alpha = True
+                    elif op.startswith(("buffer_load", "global_load")):
+                        after_alpha = False
+                    m = _TGT.search(ln)
+                    if not op.startswith("s_cbranch_vcc") or not m or not after_alpha:
+                        continue
+                    after_alpha = False
+                    t = addr_idx.get(base + int(m.group(2), 16))
+                    if t is None:
+                        continue
+                    # a forward branch inside the body skips up to its target; one
+                    # back to the loop head skips the rest of the body
+                    end = t if k < t <= hi + 1 else (hi + 1 if t == lo else k + 1)
+                    skipped.update(j for j in range(k + 1, end) if ins[j][1].startswith("v_"))
+                skip = len(skipped)
                 rec = {"kernel": syms[0], "samples_per_iteration": samples, "valu_per_iteration": valu,
                        "valu_per_sample": valu / samples,
+                       "valu_per_transparent_sample": (valu - skip) / samples,
                        "salu_per_sample": sum(op.startswith("s_") for op in body) / samples,
-                       "vmem_per_sample": sum(op.startswith(("buffer_", "global_")) for op in body) / samples,
+                       "vmem_per_sample": loads / samples,
                        "lds_per_sample": sum(op.startswith("ds_") for op in body) / samples,
                        "instructions_per_iteration": len(body)}
                 if best is None or rec["valu_per_sample"] < best["valu_per_sample"]:

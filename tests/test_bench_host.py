@@ -131,18 +131,24 @@ def test_valu_roofline_is_a_ceiling():
 
 def test_isa_loop_counts_from_the_built_library():
     """The compositing loop of the batched kernel is found in the built code
-    object: two 16-byte table reads per sample, one cell load per sample for
-    the cell layout."""
+    object: per sample one cell load, one paired opacity read and two colour
+    reads from LDS; the colour block the wave's vote skips is counted apart."""
     import paper_1211_5595_amd as rt
     from paper_1211_5595_amd import isa
     if not os.path.exists(rt.LIB_PATH):
         pytest.skip("library not built")
     for kind in (rt.U12, rt.U16):
-        lp = isa.loop_profile(rt.LIB_PATH, kind, rt.LAYOUT_CELLS)
-        assert lp is not None and lp["lds_per_sample"] == 2.0 and lp["vmem_per_sample"] == 1.0
-        assert 30.0 <= lp["valu_per_sample"] <= 90.0
+        for layout in (rt.LAYOUT_CELLS, rt.LAYOUT_QUADS):
+            lp = isa.loop_profile(rt.LIB_PATH, kind, layout)
+            assert lp is not None and lp["lds_per_sample"] == 3.0 and lp["vmem_per_sample"] == 1.0
+            assert 30.0 <= lp["valu_per_sample"] <= 90.0
+            # three colour lerps, the product T a, three colour FMAs and the transmittance FMA
+            assert 8.0 <= lp["valu_per_sample"] - lp["valu_per_transparent_sample"] <= 16.0
     assert isa.loop_profile(rt.LIB_PATH, rt.U12, rt.LAYOUT_CELLS)["valu_per_sample"] < \
         isa.loop_profile(rt.LIB_PATH, rt.U16, rt.LAYOUT_CELLS)["valu_per_sample"]
+    plain = isa.loop_profile(rt.LIB_PATH, rt.U12, rt.LAYOUT_QUADS, "march_plain_kernel")
+    assert plain is not None and plain["vmem_per_sample"] == 1.0
+    assert 0.0 < plain["valu_per_transparent_sample"] < plain["valu_per_sample"]
 
 
 def test_serve_breakdown_splits_latency():

@@ -37,6 +37,11 @@ def test_orbit_line_fields_and_consistency():
     assert abs(rf["peak"] - cus * 4 * 32 * 2.4 / 1e3) <= 1e-3
     assert rf["samples_per_launch"] == samples
     assert 40.0 <= rf["valu_per_sample"] <= 90.0
+    if rf.get("counters"):
+        # the issued count: SQ_INSTS_VALU x 64 lanes per composited sample
+        assert abs(rf["valu_per_sample"] - rf["counters"]["sq_insts_valu"] * 64.0 / samples) <= 1e-3
+    lp = rf["loop"]
+    assert lp is not None and 0.0 < lp["valu_per_transparent_sample"] < lp["valu_per_compositing_sample"]
     assert abs(rf["achieved"] - samples * rf["valu_per_sample"] / (ms * 1e-3) / 1e12) <= 1e-3 * rf["achieved"] + 1e-3
     assert abs(rf["frac"] - rf["achieved"] / rf["peak"]) <= 1e-3
     assert 0.0 < rf["frac"] <= 1.0
