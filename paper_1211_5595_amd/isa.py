@@ -11,8 +11,10 @@ The code object is taken from the ``.hip_fatbin`` section of ``librtvol.so``
 disassembled with the ROCm LLVM tools; only the named kernel is
 disassembled.  The loop is found structurally: a backward-branch range with
 no workgroup barrier whose body holds, per sample, one volume load and the
-transfer-function reads of one compositing step (the two opacities as one
-paired 4-byte LDS read, the two colours as two 12-byte reads), and, among
+transfer-function reads of one compositing step (either the two table
+entries as two 16-byte LDS reads, or, where colour is composited under the
+wave's vote, the two opacities as one paired 4-byte read and the two colours
+as two 12-byte reads), and, among
 such loops of the kernel, the one with the fewest VALU instructions per
 sample (the plain compositing loop; thresholding adds its window test).
 
@@ -132,9 +134,14 @@ def loop_profile(lib_path: str, kind: int, layout: int, kernel: str = "march_bat
             base = ins[0][0] if ins else 0
             for lo, hi in _loops(ins):
                 body = [op for _, op, _ in ins[lo:hi + 1]]
-                samples = body.count("ds_read2_b32")
                 loads = sum(op.startswith(("buffer_load", "global_load")) for op in body)
-                if samples < 1 or loads != samples or body.count("ds_read_b96") != 2 * samples:
+                voted = body.count("ds_read2_b32")
+                if voted >= 1 and body.count("ds_read_b96") == 2 * voted:
+                    samples = voted   # opacities apart, colours under the wave's vote
+                else:
+                    wide = body.count("ds_read_b128")
+                    samples = wide // 2 if wide % 2 == 0 else 0   # both table entries whole
+                if samples < 1 or loads != samples:
                     continue
                 valu = sum(op.startswith("v_") for op in body)
                 skipped = set()

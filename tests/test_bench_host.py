@@ -132,7 +132,8 @@ def test_valu_roofline_is_a_ceiling():
 def test_isa_loop_counts_from_the_built_library():
     """The compositing loop of the batched kernel is found in the built code
     object: per sample one cell load, one paired opacity read and two colour
-    reads from LDS; the colour block the wave's vote skips is counted apart."""
+    reads from LDS; the colour block the wave's vote skips is counted apart.
+    The single-view kernel's ring loop is found too."""
     import paper_1211_5595_amd as rt
     from paper_1211_5595_amd import isa
     if not os.path.exists(rt.LIB_PATH):
@@ -146,9 +147,10 @@ def test_isa_loop_counts_from_the_built_library():
             assert 8.0 <= lp["valu_per_sample"] - lp["valu_per_transparent_sample"] <= 16.0
     assert isa.loop_profile(rt.LIB_PATH, rt.U12, rt.LAYOUT_CELLS)["valu_per_sample"] < \
         isa.loop_profile(rt.LIB_PATH, rt.U16, rt.LAYOUT_CELLS)["valu_per_sample"]
+    # the single-view ring composites without the vote: both entries read whole
     plain = isa.loop_profile(rt.LIB_PATH, rt.U12, rt.LAYOUT_QUADS, "march_plain_kernel")
-    assert plain is not None and plain["vmem_per_sample"] == 1.0
-    assert 0.0 < plain["valu_per_transparent_sample"] < plain["valu_per_sample"]
+    assert plain is not None and plain["vmem_per_sample"] == 1.0 and plain["lds_per_sample"] == 2.0
+    assert plain["valu_per_transparent_sample"] == plain["valu_per_sample"]
 
 
 def test_serve_breakdown_splits_latency():
