@@ -557,8 +557,8 @@ def bench_batch(args):
     pixels = sum(j.width * j.height for j in jobs)
     algo = samples * 16 + pixels * 16
     g = samples / (ms_graph * 1e-3) / 1e9
-    line = _contract("ray samples/sec (G/s): 128 views of 32 uneven u16 volumes, one persistent graph launch vs "
-                     "128 plain launches", round(g, 3), "Gsamples/s", args, ms_graph, "f32",
+    line = _contract(f"ray samples/sec (G/s): 128 views of 32 uneven 12-bit volumes stored as {args.storage}, one "
+                     "persistent graph launch vs 128 plain launches", round(g, 3), "Gsamples/s", args, ms_graph, "f32",
                      {"workload": f"uneven-batch-32vol-128views-{args.storage}-{args.layout}", "volumes": len(specs),
                       "views": len(jobs), "source_dtype": "u16 (12-bit range)", "storage": args.storage,
                       "layout": args.layout,
@@ -618,7 +618,7 @@ def serve_breakdown(recs):
 
 
 def bench_serve(args):
-    """Poisson stream (200 req/s, seed 300) over 16 resident u16 volumes (4 of
+    """Poisson stream (200 req/s, seed 300) over 16 resident 12-bit volumes (4 of
     each batch size, seeds 200+i); each request has its own camera, square
     size in 256..1024 and transfer function.  Served with continuous batching
     under a loose and a tight HBM budget, and serially (one plain render at a
@@ -774,8 +774,8 @@ def bench_serve(args):
     fast_n = min(1000, n_req)
     sat = {"speedup_of_arrivals": 20, "served": served(resident + (4 << 30), 20.0, fast_n),
            "native": served_native(4 << 30, 20.0, fast_n), "serial": serial(20.0, fast_n)}
-    line = _contract("p50/p99 render latency (ms), Poisson 200 req/s over 16 resident u16 volumes, continuous "
-                     "batching (native server; value = p99)", nat_loose["p99_ms"], "ms", args, nat_loose["mean_ms"],
+    line = _contract(f"p50/p99 render latency (ms), Poisson 200 req/s over 16 resident 12-bit volumes stored as "
+                     f"{args.storage}, continuous batching (native server; value = p99)", nat_loose["p99_ms"], "ms", args, nat_loose["mean_ms"],
                      "f32",
                      {"workload": f"serve-poisson200-16vol-{args.storage}-{args.layout}", "volumes": len(dims),
                       "sizes": W.BATCH_SIZES, "storage": args.storage, "layout": args.layout,
