@@ -557,6 +557,27 @@ def bench_batch(args):
     pixels = sum(j.width * j.height for j in jobs)
     algo = samples * 16 + pixels * 16
     g = samples / (ms_graph * 1e-3) / 1e9
+    # measured counters of this launch (rocprofv3, same kernel sources and launch shape), if taken:
+    # fabric bytes and VALU issue against their peaks -- neither is saturated, the launch waits on
+    # lines from beyond the caches (the volumes are far larger than the Infinity Cache)
+    tile = tuple(shape.get("tile", (8, 8)))
+    waves = shape.get("waves_per_block", 12)
+    key = f"uneven-batch-32vol-128views-{args.storage}-{args.layout}:graph:{tile[0]}x{tile[1]}x{waves}"
+    traffic, cnt = load_traffic(key), load_valu(key)
+    sec = ms_graph * 1e-3
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    counters = {
+        "key": key,
+        "fabric": None if traffic is None else {
+            "bytes_per_launch": traffic, "GB_per_s": round(traffic / sec / 1e9, 1),
+            "frac_of_hbm_peak": round(traffic / sec / 1e9 / PEAK_HBM_GBS, 4),
+            "note": "FETCH_SIZE x 2 + WRITE_SIZE x 1 per launch (scales from a plain copy)"},
+        "valu_issue": None if cnt is None else {
+            "lane_slots_T_per_s": round(cnt["sq_insts_valu"] * 64.0 / sec / 1e12, 3),
+            "frac_of_peak": round(cnt["sq_insts_valu"] * 64.0 / sec / 1e12 / valu_peak_tops(cus), 4),
+            "lane_utilisation": cnt.get("lane_utilisation"),
+            "issue_frac_of_busy_cycles": cnt.get("issue_frac_of_busy_cycles")},
+    }
     line = _contract(f"ray samples/sec (G/s): 128 views of 32 uneven 12-bit volumes stored as {args.storage}, one "
                      "persistent graph launch vs 128 plain launches", round(g, 3), "Gsamples/s", args, ms_graph, "f32",
                      {"workload": f"uneven-batch-32vol-128views-{args.storage}-{args.layout}", "volumes": len(specs),
@@ -570,7 +591,7 @@ def bench_batch(args):
                      samples_per_step=samples, pixels_per_step=pixels,
                      ms_per_step_by_form={"graph": round(ms_graph, 4), "plain_128_launches": round(ms_plain, 4),
                                           "graph_skip_empty": round(ms_skip, 4)},
-                     skip_empty_images_bitwise_equal=bool(same),
+                     skip_empty_images_bitwise_equal=bool(same), counters=counters,
                      gsamples_per_s_by_form={"graph": round(g, 3),
                                              "plain_128_launches": round(samples / (ms_plain * 1e-3) / 1e9, 3)},
                      speedup_vs_plain=round(ms_plain / ms_graph, 3),
