@@ -239,9 +239,10 @@ rt_status rt_destroy_volume(rt_volume* vol);
 rt_status rt_tf_bytes(int K, size_t* bytes);
 
 /* Create (*tf == NULL) or update in place (*tf != NULL) a transfer function:
- * the host table rgba[K][4] (each value in [0,1]) is copied into a pinned
- * buffer owned by the handle and uploaded to dev_buf (>= rt_tf_bytes(K),
- * 16-byte aligned) on `stream`; the call does not wait for the upload, and
+ * the host table rgba[K][4] (each value in [0,1]) is copied into a pinned,
+ * coherent buffer owned by the handle, which a small kernel on `stream` reads
+ * into dev_buf (>= rt_tf_bytes(K), 16-byte aligned; no runtime memory copy is
+ * made); the call does not wait for the upload, and
  * the caller's table may be reused as soon as it returns.  An update keeps
  * dev_buf (pass NULL or the same buffer) and may change K while
  * rt_tf_bytes(K) still fits dev_buf and the handle's pinned buffer (sized by
@@ -296,8 +297,9 @@ rt_status rt_batch_workspace_bytes(int max_jobs, size_t* bytes);
  * functions and sizes; all volumes of one storage type and layout; each job
  * selects its own ray function, the ray-function fields of opts are not used)
  * in one persistent launch that pulls
- * ray tiles from a device work queue.  Copies the job table into `workspace`
- * (>= rt_batch_workspace_bytes(n)) on `stream`; the job array may be reused
+ * ray tiles from a device work queue.  Writes the job table into `workspace`
+ * (>= rt_batch_workspace_bytes(n)) on `stream` through the arguments of small
+ * fill kernels (no runtime memory copy); the job array may be reused
  * once the call returns.  A workspace holds one batch at a time: batches that
  * may run at once (on different streams) need workspaces of their own.  Results are bitwise identical to rt_render of each
  * view.  Errors: as rt_render, plus RT_ERR_OUT_OF_MEMORY (workspace too
@@ -307,12 +309,12 @@ rt_status rt_render_batch(const rt_render_job* jobs, int n, void* workspace, siz
 
 /* A batch plan: the persistent launch captured once into a HIP graph over a
  * fixed workspace, replayed for every batch of up to max_jobs views of one
- * storage type and layout.  rt_batch_plan_launch copies the job table into the
- * workspace (plain stream copy, outside the graph) and launches the graph on
- * `stream` -- or, for a batch small enough for the latency form
- * (opts->batch_form), launches that form's kernel directly, its grid the
- * batch's block count.  The plan keeps a pinned host staging buffer and waits for the
- * previous launch's copy before reusing it.  Calls on one plan must not run
+ * storage type and layout.  rt_batch_plan_launch writes the job table into the
+ * workspace through the arguments of small fill kernels on `stream` (outside the
+ * graph; no runtime memory copy) and launches the graph on `stream` -- or, for
+ * a batch small enough for the latency form (opts->batch_form), launches that
+ * form's kernel directly, its grid the batch's block count (up to 6 views with
+ * the job table in its own arguments).  Calls on one plan must not run
  * concurrently.  A plan created with opts->skip_empty set skips empty space
  * for the jobs whose skip_empty is set; a plan created without it never skips
  * (the images are the same either way). */

@@ -27,7 +27,9 @@
  * slots of 4096 entries, followed by the image pool.  The
  * image pool is the admission budget: a request holds W*H*16 bytes of it
  * (rounded up to 256) from admission until the caller releases it.  Host
- * memory: small pinned staging buffers per stream and per table slot.
+ * memory: a pinned, coherent staging buffer per table slot, and a host copy of
+ * each stream's job table.  The request path makes no runtime memory copy:
+ * tables and job tables reach the device through small kernels.
  *
  * Threads: every entry point may be called from any thread.  Volumes must stay
  * alive until the requests that use them are released.  A request submitted

@@ -8,6 +8,7 @@
 #include <atomic>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -32,7 +33,8 @@ struct rt_tf {
     int K;
     double vmin, vmax;
     size_t bytes;
-    void* staging;      // pinned host copy of the table for the asynchronous upload
+    void* staging;      // pinned, coherent host copy of the table for the asynchronous upload
+    const void* staging_dev;  // its device-side address
     size_t staging_bytes;
     hipEvent_t copied;  // recorded after the upload on the caller's stream
     bool pending;
@@ -50,10 +52,8 @@ struct rt_batch_plan {
     size_t ws_bytes;
     hipGraph_t graph;
     hipGraphExec_t exec;
-    void* staging;  // pinned host copy of header + prefix + job table
+    void* staging;  // host copy of header + prefix + job table, in the workspace's layout
     size_t staging_bytes;
-    hipEvent_t copy_done;
-    bool copy_pending;
 };
 
 namespace {
@@ -440,36 +440,9 @@ rt_status make_view(const rt_volume* vol, const int64_t dims[3], const double sp
     return RT_OK;
 }
 
-// Pinned staging buffer reused across calls once its last copy has finished.
-struct Staging {
-    void* p = nullptr;
-    size_t bytes = 0;
-    hipEvent_t ev = nullptr;
-    bool pending = false;
-};
-thread_local Staging g_staging;
-
-rt_status staging_acquire(Staging& st, size_t bytes, void** out) {
-    if (st.pending) {
-        hipError_t e = hipEventSynchronize(st.ev);
-        if (e != hipSuccess) return hip_fail(e, "waiting for the previous job-table copy");
-        st.pending = false;
-    }
-    if (!st.ev) {
-        hipError_t e = hipEventCreateWithFlags(&st.ev, hipEventDisableTiming);
-        if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
-    }
-    if (st.bytes < bytes) {
-        if (st.p) (void)hipHostFree(st.p);
-        st.p = nullptr;
-        st.bytes = 0;
-        hipError_t e = hipHostMalloc(&st.p, bytes, hipHostMallocDefault);
-        if (e != hipSuccess) return hip_fail(e, "hipHostMalloc(staging)");
-        st.bytes = bytes;
-    }
-    *out = st.p;
-    return RT_OK;
-}
+// Host buffer for a one-off batch's header, prefix and job table (the fill
+// launches take the bytes with their arguments, so it is free again at once).
+thread_local std::vector<unsigned char> g_staging;
 
 size_t prefix_bytes() { return kBatchPrefixBytes; }
 
@@ -535,6 +508,65 @@ void write_batch_host(void* h, const std::vector<ViewDesc>& descs, const std::ve
 }
 
 size_t batch_copy_bytes(int n) { return kBatchHeaderBytes + prefix_bytes() + (size_t)n * sizeof(ViewDesc); }
+
+// A batch's header, block prefix and job table reach the device workspace
+// through the arguments of small fill kernels (the runtime copies kernel
+// arguments when the launch call is made, so the host buffer is free at once):
+// no runtime memory copy on the launch path, where a small host-to-device
+// copy has been seen to block its caller for milliseconds.
+constexpr int kFillPayload = 3584;  // table bytes per fill launch (kernel arguments stay under 4 KiB)
+
+struct FillChunk {
+    uint32_t dst_offset;   // first segment: byte offset in the workspace, 16-byte aligned
+    uint32_t bytes;        // multiple of 16
+    uint32_t dst_offset2;  // second segment, from data + bytes
+    uint32_t bytes2;       // multiple of 16; bytes + bytes2 <= kFillPayload
+    uint4 data[kFillPayload / 16];
+};
+
+__global__ void __launch_bounds__(256) fill_workspace_kernel(unsigned char* __restrict__ ws, const FillChunk c) {
+    for (uint32_t i = threadIdx.x; i * 16u < c.bytes + c.bytes2; i += blockDim.x) {
+        const uint32_t o = i * 16u;
+        const uint32_t d = o < c.bytes ? c.dst_offset + o : c.dst_offset2 + (o - c.bytes);
+        *reinterpret_cast<uint4*>(ws + d) = c.data[i];
+    }
+}
+
+// A table's upload: the device reads the pinned, coherent staging copy
+// directly (n16 16-byte units), so no runtime copy runs on the request path.
+__global__ void __launch_bounds__(256) upload_table_kernel(uint4* __restrict__ dst, const uint4* __restrict__ src,
+                                                           uint32_t n16) {
+    const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+    if (i < n16) dst[i] = src[i];
+}
+
+// Copy bytes_a from host a to ws + 0 and bytes_b from host b to ws + off_b
+// (each rounded up to 16; the sources must be readable that far, off_b
+// 16-byte aligned) in fill launches on stream s, as few as the payload allows.
+hipError_t fill_workspace(unsigned char* ws, const void* a, size_t bytes_a, size_t off_b, const void* b,
+                          size_t bytes_b, hipStream_t s) {
+    const unsigned char* pa = static_cast<const unsigned char*>(a);
+    const unsigned char* pb = static_cast<const unsigned char*>(b);
+    size_t ra = (bytes_a + 15) & ~(size_t)15, rb = (bytes_b + 15) & ~(size_t)15;
+    size_t da = 0, db = 0;  // bytes of each sent so far
+    while (da < ra || db < rb) {
+        FillChunk c;
+        const size_t na = std::min(ra - da, (size_t)kFillPayload);
+        const size_t nb = std::min(rb - db, (size_t)kFillPayload - na);
+        c.dst_offset = (uint32_t)da;
+        c.bytes = (uint32_t)na;
+        c.dst_offset2 = (uint32_t)(off_b + db);
+        c.bytes2 = (uint32_t)nb;
+        if (na) std::memcpy(c.data, pa + da, na);
+        if (nb) std::memcpy(reinterpret_cast<unsigned char*>(c.data) + na, pb + db, nb);
+        hipLaunchKernelGGL(fill_workspace_kernel, dim3(1), dim3(256), 0, s, ws, c);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        da += na;
+        db += nb;
+    }
+    return hipSuccess;
+}
 
 int layout_code(int layout) {
     return layout == RT_LAYOUT_LINEAR   ? LAYOUT_LINEAR
@@ -731,7 +763,10 @@ rt_status rt_set_transfer_function(rt_tf** tf, const float* rgba, int K, double 
         t->K = K;
         t->bytes = dev_buf_bytes;
         t->staging_bytes = need;
-        hipError_t e = hipHostMalloc(&t->staging, need, hipHostMallocDefault);
+        hipError_t e = hipHostMalloc(&t->staging, need, hipHostMallocCoherent);
+        void* sd = nullptr;
+        if (e == hipSuccess) e = hipHostGetDevicePointer(&sd, t->staging, 0);
+        t->staging_dev = sd;
         if (e == hipSuccess) e = hipEventCreateWithFlags(&t->copied, hipEventDisableTiming);
         if (e != hipSuccess) {
             if (t->staging) (void)hipHostFree(t->staging);
@@ -749,7 +784,11 @@ rt_status rt_set_transfer_function(rt_tf** tf, const float* rgba, int K, double 
     nz[0] = 0;
     for (int j = 0; j <= K; ++j) nz[j + 1] = nz[j] + (rgba[4 * std::min(j, K - 1) + 3] > 0.0f ? 1 : 0);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    hipError_t e = hipMemcpyAsync(const_cast<float4*>(t->dev), t->staging, need, hipMemcpyHostToDevice, s);
+    const uint32_t n16 = (uint32_t)(need / 16);  // need is a multiple of 256
+    hipLaunchKernelGGL(upload_table_kernel, dim3((n16 + 255) / 256), dim3(256), 0, s,
+                       reinterpret_cast<uint4*>(const_cast<float4*>(t->dev)),
+                       static_cast<const uint4*>(t->staging_dev), n16);
+    hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipEventRecord(t->copied, s);
     if (e != hipSuccess) {
         if (!*tf) {
@@ -819,16 +858,17 @@ rt_status rt_render_batch(const rt_render_job* jobs, int n, void* workspace, siz
     if (st != RT_OK) return st;
     if (ws_bytes < batch_ws_bytes(n)) return fail(RT_ERR_OUT_OF_MEMORY, "workspace smaller than rt_batch_workspace_bytes");
     const size_t bytes = batch_copy_bytes(n);
-    void* h = nullptr;
-    st = staging_acquire(g_staging, bytes, &h);
-    if (st != RT_OK) return st;
+    if (g_staging.size() < bytes) g_staging.resize(bytes);
+    void* h = g_staging.data();
     write_batch_host(h, descs, prefix, max_k, sample_counter);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    hipError_t e = hipMemcpyAsync(workspace, h, bytes, hipMemcpyHostToDevice, s);
-    if (e != hipSuccess) return hip_fail(e, "job-table copy");
-    e = hipEventRecord(g_staging.ev, s);
-    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
-    g_staging.pending = true;
+    // header and the n + 1 prefix entries, then the n job descriptions; the fill
+    // launches take the bytes with their arguments, so the staging buffer is free
+    unsigned char* hb = static_cast<unsigned char*>(h);
+    hipError_t e = fill_workspace(static_cast<unsigned char*>(workspace), hb,
+                                  kBatchHeaderBytes + (size_t)(n + 1) * sizeof(int), kBatchHeaderBytes + prefix_bytes(),
+                                  hb + kBatchHeaderBytes + prefix_bytes(), (size_t)n * sizeof(ViewDesc), s);
+    if (e != hipSuccess) return hip_fail(e, "job-table fill");
     const bool skip = any_skip;  // the kernel the shape was checked for
     const int grid = std::min(batch_persistent_grid(ls, max_k, skip), std::max(prefix.back(), 1));
     e = launch_march_batch(kind / 8, kind % 8, workspace, grid, ls, max_k, skip, s);
@@ -891,14 +931,11 @@ rt_status rt_batch_plan_create(int max_jobs, int storage, int layout, void* work
         return hip_fail(e, "batch graph capture");
     }
     p->graph = g;
-    e = hipEventCreateWithFlags(&p->copy_done, hipEventDisableTiming);
-    if (e == hipSuccess) {
-        p->staging_bytes = batch_copy_bytes(max_jobs);
-        e = hipHostMalloc(&p->staging, p->staging_bytes, hipHostMallocDefault);
-    }
-    if (e != hipSuccess) {
+    p->staging_bytes = batch_copy_bytes(max_jobs);
+    p->staging = std::aligned_alloc(64, (p->staging_bytes + 63) & ~(size_t)63);
+    if (!p->staging) {
         rt_batch_plan_destroy(p);
-        return hip_fail(e, "batch plan staging");
+        return fail(RT_ERR_OUT_OF_MEMORY, "batch plan staging");
     }
     *out = p;
     return RT_OK;
@@ -943,18 +980,13 @@ rt_status rt_batch_plan_launch(rt_batch_plan* p, const rt_render_job* jobs, int 
         if (e != hipSuccess) return hip_fail(e, "latency-form launch");
         return RT_OK;
     }
-    if (p->copy_pending) {
-        hipError_t e = hipEventSynchronize(p->copy_done);
-        if (e != hipSuccess) return hip_fail(e, "waiting for the previous job-table copy");
-        p->copy_pending = false;
-    }
-    const size_t bytes = batch_copy_bytes(n);
+    // header and the n + 1 prefix entries, then the n job descriptions
     write_batch_host(p->staging, descs, prefix, max_k, sample_counter);
-    hipError_t e = hipMemcpyAsync(p->ws, p->staging, bytes, hipMemcpyHostToDevice, s);
-    if (e != hipSuccess) return hip_fail(e, "job-table copy");
-    e = hipEventRecord(p->copy_done, s);
-    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
-    p->copy_pending = true;
+    unsigned char* st_b = static_cast<unsigned char*>(p->staging);
+    hipError_t e = fill_workspace(static_cast<unsigned char*>(p->ws), st_b,
+                                  kBatchHeaderBytes + (size_t)(n + 1) * sizeof(int), kBatchHeaderBytes + prefix_bytes(),
+                                  st_b + kBatchHeaderBytes + prefix_bytes(), (size_t)n * sizeof(ViewDesc), s);
+    if (e != hipSuccess) return hip_fail(e, "job-table fill");
     if (lat) {
         e = launch_march_views(p->kind / 8, p->kind % 8, p->ws, prefix.back(), ls, max_k, p->skip, s);
         if (e != hipSuccess) return hip_fail(e, "latency-form launch");
@@ -967,11 +999,9 @@ rt_status rt_batch_plan_launch(rt_batch_plan* p, const rt_render_job* jobs, int 
 
 rt_status rt_batch_plan_destroy(rt_batch_plan* p) {
     if (!p) return RT_OK;
-    if (p->copy_pending && p->copy_done) (void)hipEventSynchronize(p->copy_done);
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
-    if (p->copy_done) (void)hipEventDestroy(p->copy_done);
-    if (p->staging) (void)hipHostFree(p->staging);
+    std::free(p->staging);
     delete p;
     return RT_OK;
 }
@@ -992,22 +1022,9 @@ namespace {
 constexpr int kNoAllocMaxJobs = 64;
 constexpr size_t kNoAllocDescOffset = kBatchHeaderBytes + kBatchPrefixBytes;
 constexpr size_t kNoAllocBytes = kNoAllocDescOffset + (size_t)kNoAllocMaxJobs * sizeof(ViewDesc) + 16;
-constexpr int kFillPayload = 3584;  // table bytes per fill launch (kernel arguments stay under 4 KiB)
 constexpr int kMaxDevices = 64;
 
 static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
-
-struct FillChunk {
-    uint32_t dst_offset;  // byte offset in the workspace, 16-byte aligned
-    uint32_t bytes;       // multiple of 16, at most kFillPayload
-    uint32_t pad[2];
-    uint4 data[kFillPayload / 16];
-};
-
-__global__ void __launch_bounds__(256) fill_workspace_kernel(unsigned char* __restrict__ ws, const FillChunk c) {
-    for (uint32_t i = threadIdx.x; i * 16u < c.bytes; i += blockDim.x)
-        *reinterpret_cast<uint4*>(ws + c.dst_offset + i * 16u) = c.data[i];
-}
 
 std::mutex g_scratch_mu;
 void* g_scratch_dev[kMaxDevices];  // device address of `scratch` per device, set on first use
@@ -1029,24 +1046,6 @@ rt_status scratch_address(void** out) {
     }
     *out = g_scratch_dev[dev];
     return RT_OK;
-}
-
-// Copy `bytes` (rounded up to 16; the source must be readable that far) from
-// host memory to ws + dst_offset in fill launches on stream s.
-hipError_t fill_workspace(unsigned char* ws, size_t dst_offset, const void* src, size_t bytes, hipStream_t s) {
-    const unsigned char* p = static_cast<const unsigned char*>(src);
-    const size_t total = (bytes + 15) & ~(size_t)15;
-    for (size_t done = 0; done < total; done += kFillPayload) {
-        FillChunk c;
-        c.dst_offset = (uint32_t)(dst_offset + done);
-        c.bytes = (uint32_t)std::min(total - done, (size_t)kFillPayload);
-        c.pad[0] = c.pad[1] = 0;
-        std::memcpy(c.data, p + done, c.bytes);
-        hipLaunchKernelGGL(fill_workspace_kernel, dim3(1), dim3(256), 0, s, ws, c);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
 }
 
 }  // namespace
@@ -1075,8 +1074,8 @@ rt_status rt_render_batch_noalloc(const rt_render_job* jobs, int n, unsigned lon
     if (st != RT_OK) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
     unsigned char* w = static_cast<unsigned char*>(ws);
-    hipError_t e = fill_workspace(w, 0, head, kBatchHeaderBytes + (size_t)(n + 1) * sizeof(int), s);
-    if (e == hipSuccess) e = fill_workspace(w, kNoAllocDescOffset, descs, (size_t)n * sizeof(ViewDesc), s);
+    hipError_t e = fill_workspace(w, head, kBatchHeaderBytes + (size_t)(n + 1) * sizeof(int), kNoAllocDescOffset,
+                                  descs, (size_t)n * sizeof(ViewDesc), s);
     if (e != hipSuccess) return hip_fail(e, "workspace fill");
     const int grid = std::min(batch_persistent_grid(ls, max_k, any_skip), std::max(prefix[n], 1));
     e = launch_march_batch(kind / 8, kind % 8, ws, grid, ls, max_k, any_skip, s);
