@@ -18,6 +18,7 @@ import argparse
 import hashlib
 import json
 import os
+import subprocess
 import sys
 import time
 
@@ -1034,7 +1035,11 @@ def main():
         from paper_1211_5595_amd import isa
         batch_form = best in ("batch", "graph")
         kname = "march_batch_kernel" if batch_form else "march_plain_kernel"
-        lp = isa.loop_profile(rt.LIB_PATH, storage, layout, kname)
+        try:  # the loop's counts come from the ROCm LLVM tools; the line does not depend on them
+            lp = isa.loop_profile(rt.LIB_PATH, storage, layout, kname)
+        except (OSError, subprocess.SubprocessError, ValueError) as exc:
+            print(f"loop profile unavailable: {exc}", file=sys.stderr)
+            lp = None
         cnt = load_valu(key)
         if cnt is not None:
             vps = cnt["sq_insts_valu"] * 64.0 / samples_per_launch
