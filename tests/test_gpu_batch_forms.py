@@ -133,3 +133,26 @@ def test_table_update_changes_size_in_place(rt, scene):
     small = rt.TransferFunction(W.random_tf(64, 66), 0.0, 4095.0)
     with pytest.raises(rt.OutOfMemory):
         small.update(big)
+
+
+def test_table_updates_back_to_back_keep_each_render(rt, scene):
+    """A table handle updated again and again with a render after each
+    update, with no synchronisation in between: every render sees the table
+    given just before it (the upload kernel reads the handle's staging buffer
+    on the stream, and an update waits for the previous upload before
+    rewriting that buffer)."""
+    import torch
+    vol = rt.Volume(scene["grids"][0], scene["sp"], storage=rt.U12, layout=rt.LAYOUT_QUADS)
+    vi, cam = scene["cams"][0]
+    tables = [W.random_tf(K, 80 + i, alpha_max=0.3) for i, K in enumerate((4096, 300, 4096, 17, 2048, 4096, 5, 1000))]
+    tf = rt.TransferFunction(tables[0], 0.0, 4095.0)
+    got = []
+    for t in tables:
+        tf.update(t)
+        got.append(rt.render(vol, tf, cam, 72, 64, skip_empty=True))
+    torch.cuda.synchronize()
+    for k, t in enumerate(tables):
+        fresh = rt.TransferFunction(t, 0.0, 4095.0)
+        ref = rt.render(vol, fresh, cam, 72, 64, skip_empty=True)
+        torch.cuda.synchronize()
+        assert torch.equal(got[k], ref), k
